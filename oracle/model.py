@@ -1,0 +1,307 @@
+"""CPU oracle of the certificate-maintenance state machine: TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package's smoke check and the benchmark's CPU-baseline leg
+may import this module.  It shares no code with the GPU path; the one thing the
+two sides have in common is the seeded input generator (``synth``).
+
+The method (Section 2, Definition 1, Lemma 1, Definition 2, Algorithm 1 and the
+appendix's cumulative clock), written out in plain NumPy plus one brute-force C
+routine for the certificates themselves:
+
+* certificate of point i: (nn_i, d1_i, d2_i), by brute force over all points
+  (``nncert_oracle.c`` states the exact binary32 arithmetic);
+* clearance c_i = d2_i - d1_i (binary32 subtraction), validity radius c_i / 4;
+* per step, eps_t = the largest displacement of any point (Algorithm 1, its
+  first statement), measured as sqrtf of the largest binary32 squared
+  displacement;
+* clock S_t = S_{t-1} + eps_t in binary64 (appendix, per-step cost section:
+  the sum of per-step maxima);
+* a certificate last recomputed at clock S_i stays valid while
+  S_t - S_i < c_i / 4 (the appendix applies Theorem 2 to the accumulated
+  displacement); the point is a repair candidate once S_t reaches its expiry
+  key e_i = S_i + c_i / 4.  A guard gamma widens the candidate set to absorb
+  binary32 rounding:  e_i = S_i + (c_i - gamma * d2_i) * K,  K = 1 / (4 + 4 gamma),
+  all in binary64;  gamma = 0 is the paper's key exactly;
+* candidates are re-certified (repair) or every point is (rebuild); a
+  certificate fails when its nearest neighbour changes (Definition 2);
+* every point's grid cell is brought up to date every step (Algorithm 1);
+  cell of x: per axis g = clamp(floor(fl32(x * G)), 0, G-1), id = gx + G*(gy + G*gz);
+* normalised repair-frontier entropy (Definition 2) over the current cells:
+  H = (ln|F| - sum_k n_k ln n_k / |F|) / ln C, with C the number of occupied
+  cells; H = 0 when F is empty or C <= 1.
+
+The literal reading of Algorithm 1 across many steps (a point is a candidate
+when its possibly stale clearance is at most 4 * eps_t of this step alone) is
+kept as ``rule="literal"`` so that a test can show it misses failures.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nncert_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GUARD_DEFAULT = 2.0 ** -18
+
+FAILED = 0
+CANDIDATES = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle with gcc (no fused multiply-add)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-fopenmp", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        f32p = ctypes.POINTER(ctypes.c_float)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        _lib.orc_top2_f32.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, ctypes.c_int64,
+                                      i32p, f32p, f32p]
+        _lib.orc_nn_f64.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, ctypes.c_int64,
+                                    i32p, f64p]
+        _lib.orc_pair_sqdist64.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, i64p,
+                                           ctypes.c_int64, f64p]
+        _lib.orc_pair_sqdist32.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, i64p,
+                                           ctypes.c_int64, f32p]
+    return _lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _soa(pos: np.ndarray) -> np.ndarray:
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    if pos.ndim != 2 or pos.shape[0] not in (2, 3):
+        raise ValueError("positions must be float32 [d][n] with d in {2, 3}")
+    return pos
+
+
+# --- certificates by brute force (Definition 1) -------------------------------------
+
+def top2(pos: np.ndarray, queries=None):
+    """(nn int32, d1 float32, d2 float32) of the queried points (default: all)."""
+    pos = _soa(pos)
+    d, n = pos.shape
+    q = np.arange(n, dtype=np.int64) if queries is None else np.ascontiguousarray(queries, np.int64)
+    nn = np.empty(q.size, np.int32)
+    d1 = np.empty(q.size, np.float32)
+    d2 = np.empty(q.size, np.float32)
+    if q.size:
+        lib().orc_top2_f32(_ptr(pos, ctypes.c_float), n, d, _ptr(q, ctypes.c_int64), q.size,
+                           _ptr(nn, ctypes.c_int32), _ptr(d1, ctypes.c_float), _ptr(d2, ctypes.c_float))
+    return nn, d1, d2
+
+
+def nn_f64(pos: np.ndarray, queries=None):
+    """Nearest neighbour under binary64 distances of the binary32 coordinates."""
+    pos = _soa(pos)
+    d, n = pos.shape
+    q = np.arange(n, dtype=np.int64) if queries is None else np.ascontiguousarray(queries, np.int64)
+    nn = np.empty(q.size, np.int32)
+    s = np.empty(q.size, np.float64)
+    if q.size:
+        lib().orc_nn_f64(_ptr(pos, ctypes.c_float), n, d, _ptr(q, ctypes.c_int64), q.size,
+                         _ptr(nn, ctypes.c_int32), _ptr(s, ctypes.c_double))
+    return nn, s
+
+
+def pair_sqdist64(pos, a, b):
+    pos = _soa(pos)
+    d, n = pos.shape
+    a = np.ascontiguousarray(a, np.int64)
+    b = np.ascontiguousarray(b, np.int64)
+    out = np.empty(a.size, np.float64)
+    if a.size:
+        lib().orc_pair_sqdist64(_ptr(pos, ctypes.c_float), n, d, _ptr(a, ctypes.c_int64),
+                                _ptr(b, ctypes.c_int64), a.size, _ptr(out, ctypes.c_double))
+    return out
+
+
+def pair_sqdist32(pos, a, b):
+    pos = _soa(pos)
+    d, n = pos.shape
+    a = np.ascontiguousarray(a, np.int64)
+    b = np.ascontiguousarray(b, np.int64)
+    out = np.empty(a.size, np.float32)
+    if a.size:
+        lib().orc_pair_sqdist32(_ptr(pos, ctypes.c_float), n, d, _ptr(a, ctypes.c_int64),
+                                _ptr(b, ctypes.c_int64), a.size, _ptr(out, ctypes.c_float))
+    return out
+
+
+# --- the pieces of Algorithm 1 ------------------------------------------------------
+
+def cells(pos: np.ndarray, G: int) -> np.ndarray:
+    """Linear cell id of every point: x fastest, then y, then z (Algorithm 1's index order)."""
+    pos = _soa(pos)
+    if not np.all(np.isfinite(pos)):
+        raise FloatingPointError("non-finite coordinate")
+    q = pos * np.float32(G)                       # binary32 product
+    g = np.clip(np.floor(q), 0, G - 1).astype(np.int64)
+    cid = g[-1].copy()
+    for k in range(pos.shape[0] - 2, -1, -1):     # id = g0 + G*(g1 + G*g2)
+        cid = g[k] + G * cid
+    return cid.astype(np.int32)
+
+
+def max_step(p_old: np.ndarray, p_new: np.ndarray) -> np.float32:
+    """eps_t: sqrtf of the largest binary32 squared displacement (0 for no points)."""
+    p_old = _soa(p_old)
+    p_new = _soa(p_new)
+    if p_old.shape[1] == 0:
+        return np.float32(0.0)
+    dx = p_new[0] - p_old[0]
+    s = dx * dx
+    for k in range(1, p_old.shape[0]):
+        dk = p_new[k] - p_old[k]
+        s = s + dk * dk
+    return np.sqrt(np.max(s))
+
+
+def clearance(d1: np.ndarray, d2: np.ndarray) -> np.ndarray:
+    """c = d2 - d1 in binary32 (Definition 1); +inf when d2 is +inf."""
+    with np.errstate(invalid="ignore"):
+        c = (d2 - d1).astype(np.float32)
+    return np.where(np.isinf(d2), np.float32(np.inf), c)
+
+
+def expiry_key(S_i: float, d1: np.ndarray, d2: np.ndarray, guard: float) -> np.ndarray:
+    """Clock value at which a certificate computed at clock S_i must be revisited."""
+    K = 1.0 / (4.0 + 4.0 * guard)
+    c = clearance(d1, d2).astype(np.float64)
+    with np.errstate(invalid="ignore"):
+        num = c - guard * d2.astype(np.float64)
+        e = np.float64(S_i) + num * K
+    return np.where(np.isinf(d2), np.inf, e)
+
+
+def entropy(members: np.ndarray, cell: np.ndarray):
+    """(H, m, C, |F|) of the set ``members`` (bool mask over points) by current cell."""
+    occupied = np.unique(cell)
+    C = int(occupied.size)
+    fc = cell[members]
+    F = int(fc.size)
+    if F == 0:
+        return 0.0, 0, C, 0
+    _, counts = np.unique(fc, return_counts=True)
+    m = int(counts.size)
+    if C <= 1:
+        return 0.0, m, C, F
+    nk = counts.astype(np.float64)
+    H = (math.log(F) - float(np.sum(nk * np.log(nk))) / F) / math.log(C)
+    return H, m, C, F
+
+
+@dataclass
+class StepResult:
+    eps: np.float32
+    S: float
+    candidates: np.ndarray  # int64, ascending
+
+
+@dataclass
+class OracleScene:
+    """One moving point set and its certificates (the state of Algorithm 1)."""
+    d: int
+    n: int
+    G: int
+    guard: float = GUARD_DEFAULT
+    rule: str = "clock"             # "clock" (appendix) or "literal" (Algorithm 1 alone)
+    pos: np.ndarray = None
+    nn: np.ndarray = None
+    d1: np.ndarray = None
+    d2: np.ndarray = None
+    e: np.ndarray = None
+    cell: np.ndarray = None
+    fail: np.ndarray = None
+    S: float = 0.0
+    pending: StepResult = None
+    last_eps: np.float32 = field(default_factory=lambda: np.float32(0))
+
+    def _recompute(self, idx: np.ndarray):
+        nn, d1, d2 = top2(self.pos, idx)
+        old = self.nn[idx].copy()
+        self.nn[idx] = nn
+        self.d1[idx] = d1
+        self.d2[idx] = d2
+        self.e[idx] = expiry_key(self.S, d1, d2, self.guard)
+        self.fail[:] = False
+        self.fail[idx] = nn != old
+
+    def init_certificates(self, pos: np.ndarray):
+        self.pos = _soa(pos).copy()
+        n = self.n
+        self.nn = np.full(n, -1, np.int32)
+        self.d1 = np.full(n, np.inf, np.float32)
+        self.d2 = np.full(n, np.inf, np.float32)
+        self.e = np.full(n, np.inf, np.float64)
+        self.fail = np.zeros(n, bool)
+        self.S = 0.0
+        self.cell = cells(self.pos, self.G)
+        self._recompute(np.arange(n, dtype=np.int64))
+        self.fail[:] = False
+        self.pending = None
+
+    def step(self, pos_new: np.ndarray) -> StepResult:
+        pos_new = _soa(pos_new)
+        eps = max_step(self.pos, pos_new)
+        self.cell = cells(pos_new, self.G)        # every cell current (Algorithm 1)
+        self.pos = pos_new.copy()
+        self.S = float(np.float64(self.S) + np.float64(eps))
+        self.last_eps = eps
+        if self.rule == "clock":
+            cand = np.flatnonzero(self.S >= self.e)
+        elif self.rule == "literal":
+            c = clearance(self.d1, self.d2).astype(np.float64)
+            cand = np.flatnonzero(c <= 4.0 * np.float64(eps))
+        else:
+            raise ValueError(self.rule)
+        self.pending = StepResult(eps, self.S, cand.astype(np.int64))
+        return self.pending
+
+    def repair(self, frontier=None):
+        if self.pending is None:
+            raise RuntimeError("repair without a pending step")
+        idx = self.pending.candidates if frontier is None else np.ascontiguousarray(frontier, np.int64)
+        self._recompute(idx)
+        self.pending = None
+
+    def rebuild(self):
+        if self.pending is None:
+            raise RuntimeError("rebuild without a pending step")
+        self._recompute(np.arange(self.n, dtype=np.int64))
+        self.pending = None
+
+    def frontier_entropy(self, which: int = FAILED, candidates=None):
+        if which == FAILED:
+            mask = self.fail
+        else:
+            mask = np.zeros(self.n, bool)
+            mask[candidates] = True
+        return entropy(mask, self.cell)
+
+    def audit(self):
+        """Points whose kept nearest neighbour differs from brute force now (misses)."""
+        nn_bf, _, _ = top2(self.pos)
+        return np.flatnonzero(nn_bf != self.nn)

@@ -1,0 +1,196 @@
+"""Seeded synthetic workloads: moving point sets in [0,1]^d, d in {2, 3}.
+
+This module is shared by the CPU oracle and the GPU path as their common input.
+It holds no part of the certificate method (no distances, no clearances, no
+cells): it only draws positions.  Every trajectory is produced in float64 with a
+counter-based Philox generator and rounded once per frame to float32; both sides
+consume the same float32 arrays, so there is no cross-device RNG parity to keep.
+
+Layout: a trajectory is a float32 array of shape [T+1, d, N] (structure of
+arrays per frame: all x, then all y, then all z), frame 0 being the start.
+
+The paper names its motion families without defining them (Section 3, the list
+of ten families, and Table 1 for the names).  The five used here follow
+these definitions:
+
+* ``uniform_brownian``: start uniform in [0,1]^d; each step adds a Gaussian
+  displacement of per-axis scale eps/sqrt(d), its Euclidean length clipped to eps.
+* ``ring_rotation``: a ring of radius 0.4 about the box centre (in the z = 0.5
+  plane for d = 3) with static Gaussian thickness 1e-3; each step rotates the set
+  rigidly about the centre at rim speed eps/2 and adds Brownian jitter clipped
+  to eps/2.
+* ``adversarial_crossing``: two Gaussian blobs (sigma 0.05) centred at x = 0.45
+  and x = 0.55 translate toward each other by eps per step along x (they cross
+  after 0.05/eps steps).
+* ``clustered_drift``: 64 Gaussian clusters (sigma 0.01) with centres uniform in
+  [0.2, 0.8]^d, each translating rigidly by eps along its own fixed random unit
+  direction.
+* ``shear_band``: start uniform; each step moves a point by ((y - 0.5) * eps) along x.
+
+Point indices are a random permutation of the generation order, so an index
+carries no spatial information in any family.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+FAMILIES = (
+    "uniform_brownian",
+    "ring_rotation",
+    "adversarial_crossing",
+    "clustered_drift",
+    "shear_band",
+)
+
+
+def rng(*key: int) -> np.random.Generator:
+    """Philox stream keyed by a tuple of non-negative integers."""
+    return np.random.Generator(np.random.Philox(np.random.SeedSequence(list(key))))
+
+
+def _clip_norm(delta: np.ndarray, bound: float) -> np.ndarray:
+    """Scale columns of delta [d, n] whose Euclidean length exceeds ``bound``."""
+    norm = np.sqrt(np.sum(delta * delta, axis=0))
+    scale = np.where(norm > bound, bound / np.maximum(norm, 1e-300), 1.0)
+    return delta * scale
+
+
+def _brownian(g: np.random.Generator, d: int, n: int, bound: float) -> np.ndarray:
+    return _clip_norm(g.standard_normal((d, n)) * (bound / math.sqrt(d)), bound)
+
+
+def _f32(x: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+@dataclass
+class Trajectory:
+    family: str
+    d: int
+    n: int
+    eps: float
+    frames: np.ndarray  # float32 [T+1, d, n]
+
+    @property
+    def steps(self) -> int:
+        return self.frames.shape[0] - 1
+
+
+def initial_positions(family: str, n: int, d: int, g: np.random.Generator):
+    """Frame-0 positions (float64 [d, n]) and per-family motion parameters."""
+    if d not in (2, 3):
+        raise ValueError("d must be 2 or 3")
+    params: dict = {}
+    if family in ("uniform_brownian", "shear_band"):
+        p = g.random((d, n))
+    elif family == "ring_rotation":
+        theta = g.random(n) * (2.0 * math.pi)
+        radius = 0.4 + 1e-3 * g.standard_normal(n)
+        p = np.empty((d, n))
+        p[0] = 0.5 + radius * np.cos(theta)
+        p[1] = 0.5 + radius * np.sin(theta)
+        if d == 3:
+            p[2] = 0.5 + 1e-3 * g.standard_normal(n)
+    elif family == "adversarial_crossing":
+        na = n // 2
+        side = np.zeros(n)
+        side[:na] = 1.0
+        side[na:] = -1.0
+        mu = np.full((d, n), 0.5)
+        mu[0] = np.where(side > 0, 0.45, 0.55)
+        p = mu + 0.05 * g.standard_normal((d, n))
+        params["side"] = side  # +1 moves toward +x, -1 toward -x
+    elif family == "clustered_drift":
+        k = 64
+        centres = 0.2 + 0.6 * g.random((d, k))
+        label = np.arange(n) % k
+        p = centres[:, label] + 0.01 * g.standard_normal((d, n))
+        u = g.standard_normal((d, k))
+        u /= np.sqrt(np.sum(u * u, axis=0))
+        params["label"] = label
+        params["direction"] = u
+    else:
+        raise ValueError(f"unknown family {family!r}")
+    perm = g.permutation(n)
+    p = p[:, perm]
+    for key in ("side", "label"):
+        if key in params:
+            params[key] = params[key][perm]
+    return p, params
+
+
+def make_trajectory(family: str, n: int, d: int, steps: int, eps: float, seed) -> Trajectory:
+    """Seeded trajectory of ``steps`` transitions; ``seed`` is an int or a tuple of ints."""
+    key = seed if isinstance(seed, tuple) else (seed,)
+    g = rng(*key)
+    p64, params = initial_positions(family, n, d, g)
+    frames = np.empty((steps + 1, d, n), dtype=np.float32)
+    frames[0] = _f32(p64)
+    centre = 0.5
+    omega = (0.5 * eps) / 0.4
+    c, s = math.cos(omega), math.sin(omega)
+    for t in range(steps):
+        cur = frames[t].astype(np.float64)
+        if family == "uniform_brownian":
+            nxt = cur + _brownian(g, d, n, eps)
+        elif family == "ring_rotation":
+            x = cur[0] - centre
+            y = cur[1] - centre
+            nxt = cur.copy()
+            nxt[0] = centre + (c * x - s * y)
+            nxt[1] = centre + (s * x + c * y)
+            nxt += _brownian(g, d, n, 0.5 * eps)
+        elif family == "adversarial_crossing":
+            nxt = cur.copy()
+            nxt[0] += params["side"] * eps
+        elif family == "clustered_drift":
+            nxt = cur + eps * params["direction"][:, params["label"]]
+        elif family == "shear_band":
+            nxt = cur.copy()
+            nxt[0] += (cur[1] - 0.5) * eps
+        else:  # pragma: no cover - rejected by initial_positions
+            raise ValueError(family)
+        frames[t + 1] = _f32(nxt)
+    return Trajectory(family, d, n, eps, frames)
+
+
+# --- the workload configurations -------------------------------------------------
+
+def config1(steps: int = 50) -> Trajectory:
+    """N = 1000 uniform points in the unit square, Brownian steps clipped to 1e-3."""
+    return make_trajectory("uniform_brownian", 1000, 2, steps, 1e-3, 1)
+
+
+def config2(family: str, n: int = 16000, steps: int = 200) -> Trajectory:
+    """N = 16000 points in the unit cube, eps = 5e-4, one of the five families."""
+    return make_trajectory(family, n, 3, steps, 5e-4, 2000 + FAMILIES.index(family))
+
+
+@dataclass
+class BatchSpec:
+    n: np.ndarray       # int64 [scenes]
+    d: np.ndarray       # int32 [scenes]
+    family: list        # str per scene
+
+
+def batch_spec(scenes: int = 512, lo: int = 500, hi: int = 20000, seed: int = 4000) -> BatchSpec:
+    """Scene sizes log-uniform in [lo, hi], d uniform over {2, 3}, family uniform."""
+    g = rng(seed)
+    n = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), scenes))).astype(np.int64)
+    d = np.where(g.random(scenes) < 0.5, 2, 3).astype(np.int32)
+    fam = [FAMILIES[int(k)] for k in g.integers(0, len(FAMILIES), scenes)]
+    return BatchSpec(n, d, fam)
+
+
+def batch_trajectories(spec: BatchSpec, steps: int, eps: float = 5e-4, seed: int = 4000):
+    """One trajectory per scene, scene s keyed by (seed, s)."""
+    return [make_trajectory(spec.family[s], int(spec.n[s]), int(spec.d[s]), steps, eps, (seed, s))
+            for s in range(len(spec.n))]
+
+
+def concat_frame(trajs, t: int) -> np.ndarray:
+    """Concatenate frame t of every scene: scene s's block is [d_s][N_s] SoA."""
+    return np.concatenate([tr.frames[t].reshape(-1) for tr in trajs]).astype(np.float32)

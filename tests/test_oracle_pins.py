@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: the binary32 formula is checked
+against an exact rational emulation, the real-number certificate against exact
+brute force, the state machine against hand-derived constructions from the
+appendix, closed forms of the entropy, invariants that hold at any size, and
+special cases whose answer is known without computing it.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, model
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -24
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# --- binary32 arithmetic of the certificate -----------------------------------------
+
+def test_round_f32_agrees_with_hardware_conversion():
+    g = np.random.default_rng(7)
+    vals = np.concatenate([g.standard_normal(2000) * 10.0 ** g.integers(-40, 30, 2000),
+                           [1e-45, 3e-39, 1.17549435e-38, 0.5, 1.0, 3.4e38]])
+    for v in vals:
+        assert exact.round_f32(Fraction(float(v))) == Fraction(float(np.float32(v)))
+
+
+def test_sqrt_f32_agrees_with_hardware_sqrt():
+    g = np.random.default_rng(8)
+    vals = np.abs(g.standard_normal(3000).astype(np.float32)) * np.float32(2.0) ** g.integers(-60, 60, 3000)
+    for v in vals.astype(np.float32):
+        assert exact.sqrt_f32(exact.exact(v)) == exact.exact(np.sqrt(v))
+
+
+def _random_scene(g, n, d, kind):
+    if kind == "uniform":
+        p = g.random((d, n))
+    elif kind == "lattice":        # exact ties everywhere
+        p = g.integers(0, 4, (d, n)) / 8.0
+    elif kind == "tiny":           # distances near the subnormal range
+        p = 0.5 + g.standard_normal((d, n)) * 1e-19
+    elif kind == "duplicates":
+        p = g.random((d, n))
+        p[:, n // 2:] = p[:, : n - n // 2]
+    else:
+        p = g.standard_normal((d, n)) * 100.0
+    return np.ascontiguousarray(p, dtype=np.float32)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("kind", ["uniform", "lattice", "tiny", "duplicates", "wide"])
+def test_c_certificate_is_the_binary32_formula_bit_for_bit(d, kind):
+    g = np.random.default_rng(100 + d * 10 + len(kind))
+    for n in (1, 2, 3, 17, 33):
+        pos = _random_scene(g, n, d, kind)
+        nn, d1, d2 = model.top2(pos)
+        P = exact.coords(pos)
+        for i in range(n):
+            enn, ed1, ed2 = exact.top2_f32(P, i)
+            assert nn[i] == enn
+            assert (d1[i] == np.inf) if ed1 is None else exact.exact(d1[i]) == ed1
+            assert (d2[i] == np.inf) if ed2 is None else exact.exact(d2[i]) == ed2
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_binary32_nn_is_the_real_nn_up_to_rounding(d):
+    """Where binary32 picks another neighbour than exact arithmetic, it is a near-tie."""
+    g = np.random.default_rng(200 + d)
+    for _ in range(6):
+        pos = _random_scene(g, 40, d, "uniform")
+        nn, d1, d2 = model.top2(pos)
+        P = exact.coords(pos)
+        for i in range(pos.shape[1]):
+            rnn, S1, S2 = exact.top2_real(P, i)
+            if nn[i] != rnn:
+                s_other = exact.sqdist_real(P, i, int(nn[i]))
+                assert abs(s_other - S1) <= Fraction(16) * Fraction(U) * S1
+            # d1, d2 within a few units in the last place of the exact distances
+            for dv, Sv in ((d1[i], S1), (d2[i], S2)):
+                assert abs(exact.exact(dv) ** 2 - Sv) <= Fraction(8) * Fraction(U) * Sv
+
+
+def test_distance_is_symmetric():
+    g = np.random.default_rng(3)
+    pos = _random_scene(g, 500, 3, "wide")
+    a = g.integers(0, 500, 5000)
+    b = g.integers(0, 500, 5000)
+    assert np.array_equal(model.pair_sqdist32(pos, a, b).view(np.uint32),
+                          model.pair_sqdist32(pos, b, a).view(np.uint32))
+
+
+def test_binary64_audit_routine_is_exact_brute_force():
+    g = np.random.default_rng(4)
+    pos = _random_scene(g, 30, 3, "uniform")
+    nn64, s64 = model.nn_f64(pos)
+    P = exact.coords(pos)
+    for i in range(30):
+        rnn, S1, _ = exact.top2_real(P, i)
+        assert nn64[i] == rnn
+        assert abs(Fraction(float(s64[i])) - S1) <= Fraction(4) * Fraction(2.0 ** -53) * S1
+
+
+# --- the pieces of the step ---------------------------------------------------------
+
+def test_cell_formula_against_exact_arithmetic():
+    G = 15
+    vals = [0.0, -0.0, 1.0, -1e-30, -3.0, 1.0000001, 7.0, 2.0 ** -149]
+    vals += [k / G for k in range(G + 1)]
+    vals += list(np.nextafter(np.float32([k / G for k in range(1, G)]), np.float32(0)))
+    vals += list(np.nextafter(np.float32([k / G for k in range(1, G)]), np.float32(2)))
+    xs = np.array(vals, dtype=np.float32)
+    pos = np.stack([xs, xs[::-1].copy()])
+    got = model.cells(pos, G)
+    for j in range(xs.size):
+        want = 0
+        for k in (1, 0):
+            q = exact.round_f32(exact.exact(pos[k, j]) * G)
+            g = min(max(math.floor(q), 0), G - 1)
+            want = g + G * want
+        assert got[j] == want
+
+
+def test_cell_rejects_nan():
+    with pytest.raises(FloatingPointError):
+        model.cells(np.array([[0.5, np.nan], [0.1, 0.2]], np.float32), 4)
+
+
+def test_max_step_is_sqrt_of_the_largest_binary32_squared_displacement():
+    g = np.random.default_rng(5)
+    for d in (2, 3):
+        a = _random_scene(g, 25, d, "uniform")
+        b = (a + g.standard_normal(a.shape).astype(np.float32) * np.float32(1e-3)).astype(np.float32)
+        eps = model.max_step(a, b)
+        A, B = exact.coords(a), exact.coords(b)
+        best = Fraction(0)
+        for j in range(25):
+            s = None
+            for k in range(d):
+                dk = exact.round_f32(B[k][j] - A[k][j])
+                sq = exact.round_f32(dk * dk)
+                s = sq if s is None else exact.round_f32(s + sq)
+            best = max(best, s)
+        assert exact.exact(eps) == exact.sqrt_f32(best)
+
+
+def test_expiry_key_is_the_guarded_validity_radius():
+    g = np.random.default_rng(6)
+    d1 = np.abs(g.standard_normal(200)).astype(np.float32)
+    d2 = (d1 + np.abs(g.standard_normal(200)).astype(np.float32)).astype(np.float32)
+    for guard in (0.0, model.GUARD_DEFAULT):
+        S = 0.125
+        e = model.expiry_key(S, d1, d2, guard)
+        for k in range(200):
+            c = exact.round_f32(exact.exact(d2[k]) - exact.exact(d1[k]))
+            real = Fraction(S) + (c - Fraction(guard) * exact.exact(d2[k])) / (4 + 4 * Fraction(guard))
+            assert abs(Fraction(float(e[k])) - real) <= Fraction(2.0 ** -50) * (abs(real) + 1)
+    # no second neighbour: never expires
+    assert model.expiry_key(0.0, np.float32([1.0]), np.float32([np.inf]), 0.0)[0] == np.inf
+
+
+# --- the appendix's tightness construction -----------------------------------------
+
+def _line_scene(eta, order, d1, eps, d):
+    """i = point 0 at the origin, a at d1, k at -(d1 + eta*eps), on the x axis."""
+    xi, xa, xk = 0.0, d1, -(d1 + eta * eps)
+    ia, ik = (1, 2) if order == "a<k" else (2, 1)
+    x0 = np.zeros(3)
+    x0[0], x0[ia], x0[ik] = xi, xa, xk
+    x1 = x0.copy()
+    x1[0] -= eps           # i toward k
+    x1[ia] += eps          # a away from i
+    x1[ik] += eps          # k toward i
+    p0 = np.full((d, 3), 0.5)
+    p1 = np.full((d, 3), 0.5)
+    p0[0] += x0
+    p1[0] += x1
+    return p0.astype(np.float32), p1.astype(np.float32), ia, ik
+
+
+@pytest.mark.parametrize("guard", [0.0, model.GUARD_DEFAULT])
+@pytest.mark.parametrize("d", [2, 3])
+def test_theorem2_tightness_construction(guard, d):
+    fx = _golden("thm2_tightness.json")
+    for case in fx["cases"]:
+        p0, p1, ia, ik = _line_scene(case["eta"], case["order"], fx["d1"], fx["eps"], d)
+        sc = model.OracleScene(d=d, n=3, G=4, guard=guard)
+        sc.init_certificates(p0)
+        assert sc.nn[0] == ia
+        c = float(sc.d2[0]) - float(sc.d1[0])
+        assert c == case["eta"] * fx["eps"]
+        res = sc.step(p1)
+        assert float(res.eps) == fx["eps"]
+        assert (0 in set(res.candidates.tolist())) == case["candidate"]
+        sc.repair()
+        assert bool(sc.fail[0]) == case["nn_changes"]
+        assert sc.nn[0] == (ik if case["nn_changes"] else ia)
+        assert sc.audit().size == 0
+
+
+# --- exhaustive lattice enumeration ------------------------------------------------
+
+def _lattice_cases_2d():
+    sites = [(x, y) for x in (0.0, 0.5, 1.0) for y in (0.0, 0.5, 1.0)]
+    moves = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)]
+    for trip in itertools.permutations(sites, 3):
+        for mv in itertools.product(moves, repeat=3):
+            p0 = np.array(trip, dtype=np.float64).T
+            p1 = p0 + np.array(mv, dtype=np.float64).T / 8.0
+            yield p0.astype(np.float32), p1.astype(np.float32)
+
+
+def test_lattice_enumeration_no_missed_failure_and_superset():
+    """Every ordered 3-point configuration of a 3x3 lattice (spacing 1/2) under every
+    combination of axis moves of length 1/8 (or none): all arithmetic is exact in
+    binary32, ties are everywhere, and the filter must still contain every failure."""
+    n_cases = n_fail = n_boundary = 0
+    for p0, p1 in _lattice_cases_2d():
+        sc = model.OracleScene(d=2, n=3, G=2, guard=0.0)
+        sc.init_certificates(p0)
+        c = (sc.d2 - sc.d1).astype(np.float64)
+        nn_before = sc.nn.copy()
+        res = sc.step(p1)
+        cand = set(res.candidates.tolist())
+        nn_after, _, _ = model.top2(p1)
+        failed = set(np.flatnonzero(nn_after != nn_before).tolist())
+        assert failed <= cand
+        sc.repair()
+        assert np.array_equal(sc.nn, nn_after)
+        n_cases += 1
+        n_fail += len(failed)
+        n_boundary += int(np.sum(c == 4.0 * float(res.eps)))
+    assert n_cases == 504 * 125
+    assert n_fail > 1000 and n_boundary > 1000    # the enumeration does reach the boundary
+
+
+# --- special cases -----------------------------------------------------------------
+
+def test_zero_motion_breaks_nothing():
+    tr = synth.config1(steps=1)
+    sc = model.OracleScene(d=2, n=1000, G=15)
+    sc.init_certificates(tr.frames[0])
+    res = sc.step(tr.frames[0])
+    assert res.eps == 0 and res.S == 0.0
+    c = (sc.d2 - sc.d1).astype(np.float64)
+    assert set(res.candidates.tolist()) == set(np.flatnonzero(c <= model.GUARD_DEFAULT * sc.d2).tolist())
+    sc.repair()
+    assert not sc.fail.any()
+
+
+def test_rigid_dyadic_translation_breaks_nothing():
+    g = np.random.default_rng(9)
+    for d in (2, 3):
+        p0 = (g.integers(0, 1024, (d, 3000)) / 1024.0).astype(np.float32)
+        p1 = p0.copy()
+        p1[0] += np.float32(1.0 / 1024.0)         # every difference is preserved exactly
+        sc = model.OracleScene(d=d, n=3000, G=8)
+        sc.init_certificates(p0)
+        sc.step(p1)
+        sc.repair()
+        assert not sc.fail.any()
+        assert sc.audit().size == 0
+
+
+def test_tiny_scenes():
+    for n in (0, 1, 2):
+        p = np.random.default_rng(n).random((3, n)).astype(np.float32)
+        sc = model.OracleScene(d=3, n=n, G=3)
+        sc.init_certificates(p)
+        if n == 1:
+            assert sc.nn[0] == -1 and np.isinf(sc.d1[0]) and np.isinf(sc.d2[0])
+        if n == 2:
+            assert list(sc.nn) == [1, 0] and np.all(np.isinf(sc.d2))
+        assert np.all(np.isinf(sc.e))
+        res = sc.step(p + np.float32(0.01))
+        assert res.candidates.size == 0
+
+
+# --- the whole state machine on the workloads -------------------------------------
+
+def test_config1_every_step_no_miss_and_fail_set_is_the_true_change():
+    tr = synth.config1()
+    sc = model.OracleScene(d=2, n=1000, G=15)
+    sc.init_certificates(tr.frames[0])
+    prev_nn = model.top2(tr.frames[0])[0]
+    for t in range(1, tr.steps + 1):
+        res = sc.step(tr.frames[t])
+        sc.repair()
+        nn_now = model.top2(tr.frames[t])[0]
+        assert np.array_equal(sc.nn, nn_now)                       # no missed failure
+        assert set(np.flatnonzero(sc.fail)) == set(np.flatnonzero(nn_now != prev_nn))
+        assert set(np.flatnonzero(sc.fail)) <= set(res.candidates.tolist())
+        prev_nn = nn_now
+
+
+@pytest.mark.parametrize("family", synth.FAMILIES)
+def test_config2_families_no_miss_reduced(family):
+    tr = synth.make_trajectory(family, 3000, 3, 25, 5e-4, 2000 + synth.FAMILIES.index(family))
+    sc = model.OracleScene(d=3, n=3000, G=9)
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, tr.steps + 1):
+        sc.step(tr.frames[t])
+        if t % 5 == 0:
+            sc.rebuild()
+        else:
+            sc.repair()
+        assert sc.audit().size == 0
+
+
+def test_literal_algorithm_with_stale_certificates_misses_failures():
+    """Read step by step with the clearance of possibly stale certificates, the
+    filter of Algorithm 1 does miss failures; the appendix's clock does not."""
+    tr = synth.config1()
+    literal = model.OracleScene(d=2, n=1000, G=15, rule="literal")
+    clock = model.OracleScene(d=2, n=1000, G=15)
+    literal.init_certificates(tr.frames[0])
+    clock.init_certificates(tr.frames[0])
+    misses_literal = misses_clock = 0
+    for t in range(1, tr.steps + 1):
+        for sc in (literal, clock):
+            sc.step(tr.frames[t])
+            sc.repair()
+        misses_literal += literal.audit().size
+        misses_clock += clock.audit().size
+    assert misses_clock == 0
+    assert misses_literal > 100
+
+
+def test_first_step_literal_equals_clock_without_guard():
+    tr = synth.config1(steps=1)
+    a = model.OracleScene(d=2, n=1000, G=15, rule="literal", guard=0.0)
+    b = model.OracleScene(d=2, n=1000, G=15, rule="clock", guard=0.0)
+    a.init_certificates(tr.frames[0])
+    b.init_certificates(tr.frames[0])
+    ra, rb = a.step(tr.frames[1]), b.step(tr.frames[1])
+    assert np.array_equal(ra.candidates, rb.candidates)
+
+
+# --- entropy -----------------------------------------------------------------------
+
+def test_entropy_closed_forms():
+    for case in _golden("entropy_closed_forms.json")["cases"]:
+        H, m, C, F = model.entropy(np.array(case["members"], bool), np.array(case["cells"], np.int32))
+        assert (m, C, F) == (case["m"], case["C"], case["F"]), case["name"]
+        assert abs(H - case["H"]) <= 1e-12, case["name"]
+
+
+def test_entropy_lower_bounds_touched_cells_theorem4():
+    g = np.random.default_rng(11)
+    for _ in range(300):
+        n = int(g.integers(1, 400))
+        cell = g.integers(0, int(g.integers(1, 60)), n).astype(np.int32)
+        members = g.random(n) < g.random()
+        H, m, C, F = model.entropy(members, cell)
+        assert 0.0 <= H <= 1.0 + 1e-12
+        if F:
+            assert m >= C ** H * (1 - 1e-12)
