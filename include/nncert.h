@@ -1,0 +1,192 @@
+/*
+ * nncert: exact nearest-neighbour certificates for moving points on MI355X.
+ *
+ * The operation (Section 2): every point i of a set of N points in R^d
+ * (d = 2 or 3) keeps a certificate (nn_i, d1_i, d2_i) -- its nearest neighbour
+ * and the two smallest neighbour distances (Definition 1) -- and the grid cell
+ * that holds it.  Each step the points move; a certificate with clearance
+ * c_i = d2_i - d1_i larger than four times the motion since it was computed
+ * cannot have failed (Lemma 1, Theorem 2), so only the others -- the repair
+ * frontier -- are recomputed (Algorithm 1).  Motion is accumulated on a clock
+ * S = sum of per-step maximum displacements, and certificate i, computed at
+ * clock S_i, is a repair candidate once S reaches its expiry key
+ * S_i + c_i / 4 (appendix, per-step cost).  Competitors: a full O(N) grid
+ * rebuild and an exact all-pairs brute force.
+ *
+ * Arithmetic, fixed so that results are reproducible bit for bit:
+ *   squared distance s = ((dx*dx) + (dy*dy)) + (dz*dz), dx = x_j - x_i, every
+ *   operation binary32 round-to-nearest-even, no fused multiply-add;
+ *   nn = argmin_j s over j != i, ties to the lowest index; s2 = the second
+ *   smallest value of {s(i,j)}; d1 = sqrtf(s1), d2 = sqrtf(s2) correctly
+ *   rounded; +inf for missing neighbours, nn = -1 when N = 1;
+ *   eps_t = sqrtf(max_i s(p_i(t-1), p_i(t)));  S_t = S_{t-1} + eps_t (binary64);
+ *   expiry e_i = S_i + (c_i - g*d2_i) * K, K = 1/(4 + 4g), binary64, with a
+ *   guard g (default 2^-18) that absorbs binary32 rounding; g = 0 is the
+ *   paper's key;  candidate iff S_t >= e_i;
+ *   cell of a point: per axis floor(fl32(x * G)) clamped to [0, G-1], linear id
+ *   gx + G*(gy + G*gz) over the box [0,1]^d (points outside go to edge cells).
+ *
+ * Conventions for every call:
+ *   - return 0 on success or a negative NNC_E_* code; no exception crosses the ABI;
+ *   - pointers documented "device" are device (HBM) addresses, e.g. the
+ *     data_ptr() of a contiguous float32 CUDA tensor; positions are
+ *     structure-of-arrays: pos[k*N + i] is coordinate k of point i;
+ *   - work is ordered on the context's HIP stream; only calls that return host
+ *     values synchronise with it (stated per call);
+ *   - errors found on the device (a non-finite coordinate, a declared eps
+ *     below the measured one) are latched in a device error word and returned
+ *     by the next synchronising call;
+ *   - a context is not thread-safe: one context per stream, one thread at a time.
+ */
+#ifndef NNCERT_H
+#define NNCERT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define NNC_OK           0
+#define NNC_E_INVAL     -1   /* bad argument or configuration */
+#define NNC_E_NOMEM     -2   /* device allocation failed */
+#define NNC_E_HIP       -3   /* a HIP runtime call failed */
+#define NNC_E_EPS       -4   /* measured eps_t exceeded the declared bound */
+#define NNC_E_NONFINITE -5   /* a coordinate was NaN or infinite */
+#define NNC_E_STATE     -6   /* call out of order (e.g. repair without a pending step) */
+#define NNC_E_DEVICE    -7   /* a device-side bounded wait expired (internal error) */
+
+/* ---- configuration flags ------------------------------------------------ */
+#define NNC_COPY_POSITIONS 1u  /* keep a private copy of each position frame */
+#define NNC_SYNC           2u  /* nnc_step synchronises and fills count_host */
+
+/* nnc_frontier_entropy: which set */
+#define NNC_FAILED     0      /* certificates whose nearest neighbour changed (Definition 2) */
+#define NNC_CANDIDATES 1      /* the repair candidates of the last step */
+
+typedef struct nnc_ctx nnc_ctx;
+typedef struct nnc_snap nnc_snap;
+
+typedef struct {
+    int32_t  d;           /* 2 or 3 */
+    int32_t  grid_g;      /* cells per axis over [0,1]^d; 0 = occupancy rule below */
+    int64_t  n;           /* number of points, 0 <= n < 2^31 */
+    double   guard;       /* expiry guard g; negative = default 2^-18 */
+    double   refresh;     /* loose-grid refresh when accumulated motion since the last
+                             index build exceeds refresh * cell width; <= 0 = 0.25 */
+    void    *stream;      /* hipStream_t to order work on; NULL = the null stream */
+    uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC */
+    int32_t  block;       /* threads per workgroup for point-parallel kernels; 0 = 256 */
+} nnc_config;
+
+/* Default grid_g: cell width w = 2/sqrt(N) (d = 2) or (4/N)^(1/3) (d = 3) and
+ * G = max(1, floor(1/w)), a small constant mean occupancy (Section 2). */
+
+typedef struct {
+    const int32_t *idx_dev;    /* device: ascending candidate indices (library-owned,
+                                  valid until the next step/repair/rebuild) */
+    const int32_t *count_dev;  /* device: number of candidates */
+    int32_t count_host;        /* filled when NNC_SYNC is set, else -1 */
+    int32_t step;              /* step number t (1 = first step after init) */
+} nnc_frontier;
+
+typedef struct {
+    const int32_t *nn;    /* device [n] */
+    const float   *d1;    /* device [n] */
+    const float   *d2;    /* device [n] */
+    const double  *e;     /* device [n], expiry keys */
+    const int32_t *cell;  /* device [n], current cell ids */
+    const uint8_t *fail;  /* device [n], 1 if nn changed at the last repair/rebuild */
+    int64_t n;
+    int32_t d, grid_g;
+} nnc_state;
+
+typedef struct {
+    int64_t n_checked;        /* points whose nn was compared */
+    int64_t n_detect;         /* candidates of the last step */
+    int64_t n_true_fail;      /* points whose nn changed at the last step */
+    int64_t n_missed;         /* points whose kept nn differs from brute force (must be 0) */
+    int64_t n_false;          /* candidates that did not fail */
+    int64_t n_value_mismatch; /* fresh certificates whose d1/d2 differ from brute force */
+    uint64_t nn_hash;         /* 64-bit hash of nn[] (order-dependent, deterministic) */
+} nnc_audit;
+
+typedef struct {
+    double  eps;      /* eps_t of the last step */
+    double  S;        /* clock S_t */
+    double  H;        /* normalised entropy of the chosen set */
+    int32_t m;        /* occupied cells the set meets */
+    int32_t C;        /* occupied cells */
+    int32_t count;    /* |set| */
+} nnc_entropy;
+
+/* Create a context for cfg->n points in cfg->d dimensions; allocates all state.
+ * Errors: NNC_E_INVAL (d not 2/3, n out of range, G^d over 2^24), NNC_E_NOMEM. */
+int nnc_create(nnc_ctx **out, const nnc_config *cfg);
+
+/* Release every buffer of the context (after draining its stream). */
+void nnc_destroy(nnc_ctx *ctx);
+
+/* Certificates of every point at positions pos (device, float32 [d][n]) by a full
+ * grid build and 2-NN query; clock S = 0.  pos is borrowed: it must stay
+ * unchanged until the next nnc_step returns (or is copied with
+ * NNC_COPY_POSITIONS).  Asynchronous. */
+int nnc_init_certificates(nnc_ctx *ctx, const float *pos);
+
+/* One step of Algorithm 1 up to its repair loop: measure eps_t against the
+ * previous frame, advance the clock, bring every cell id up to date, and
+ * compact the candidates S_t >= e_i into an ascending list (out).
+ * pos_new (device, float32 [d][n]) is borrowed like in init.  eps_declared < 0:
+ * no check; else a measured eps_t > eps_declared * (1 + 2^-16) + 2^-20 (the
+ * slack covers rounding of coordinates to binary32) is reported as NNC_E_EPS;
+ * the step still uses the measured eps_t, so certificates stay exact.  The
+ * declared bound also paces the refresh of the grid index.  Asynchronous unless NNC_SYNC.  A step must be followed by exactly
+ * one nnc_repair or nnc_rebuild before the next step (NNC_E_STATE otherwise). */
+int nnc_step(nnc_ctx *ctx, const float *pos_new, float eps_declared, nnc_frontier *out);
+
+/* Recompute the certificates of the pending step's candidates (f == NULL) or of
+ * an explicit list (f->idx_dev, f->count_dev device pointers; any order,
+ * duplicates not allowed), against the current positions through the grid
+ * index, widening each query until its second neighbour is provably enclosed
+ * (Corollary 1).  Sets fail flags, S_i = S_t, and the failure histogram used
+ * by nnc_frontier_entropy.  Asynchronous. */
+int nnc_repair(nnc_ctx *ctx, const nnc_frontier *f);
+
+/* The competitor: rebin all n points and recompute every certificate
+ * (O(N) grid rebuild), in place of nnc_repair for the pending step.  Asynchronous. */
+int nnc_rebuild(nnc_ctx *ctx);
+
+/* Exact tiled all-pairs top-2 of the current positions on the GPU, compared with
+ * the state: nn of every point, d1/d2 bitwise of points certified at the last
+ * step.  Synchronises. */
+int nnc_oracle_verify(nnc_ctx *ctx, nnc_audit *out);
+
+/* Normalised entropy (Definition 2) of the failed set or of the last step's
+ * candidates, over the current cells.  Synchronises. */
+int nnc_frontier_entropy(nnc_ctx *ctx, int which, nnc_entropy *out);
+
+/* Read-only device views of the state arrays.  Does not synchronise. */
+int nnc_get_state(nnc_ctx *ctx, nnc_state *v);
+
+/* Device-side copy of the whole state (for timing two strategies on one step). */
+int nnc_snapshot(nnc_ctx *ctx, nnc_snap **out);
+int nnc_restore(nnc_ctx *ctx, const nnc_snap *snap);
+void nnc_snap_free(nnc_snap *snap);
+
+/* Standalone exact all-pairs top-2 (the brute-force competitor and ground truth):
+ * for every point of pos (device float32 [d][n]) -- or for the nq listed points
+ * when qidx (device int32 [nq]) is not NULL -- write nn (int32), d1, d2 (float32)
+ * to device arrays of length n (or nq).  stream: hipStream_t or NULL.
+ * Asynchronous. */
+int nnc_allpairs_top2(const float *pos, int64_t n, int32_t d, const int32_t *qidx, int64_t nq,
+                      int32_t *nn, float *d1, float *d2, void *stream);
+
+/* Human-readable text of an error code. */
+const char *nnc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNCERT_H */

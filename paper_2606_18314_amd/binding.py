@@ -1,0 +1,261 @@
+"""Python binding of libnncert (ctypes): argument marshalling only.
+
+Every step of the maintenance path runs in the library's HIP kernels.  PyTorch
+is used for device memory and streams: callers pass contiguous CUDA tensors and
+the binding hands their data pointers and the current stream to the C ABI.
+
+torch must be imported before the library is loaded so that both use the one
+HIP runtime that torch ships (they share its soname); this module does so.
+If the built library is missing, loading raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnncert.so")
+
+NNC_OK = 0
+NNC_E_INVAL = -1
+NNC_E_NOMEM = -2
+NNC_E_HIP = -3
+NNC_E_EPS = -4
+NNC_E_NONFINITE = -5
+NNC_E_STATE = -6
+NNC_E_DEVICE = -7
+
+NNC_COPY_POSITIONS = 1
+NNC_SYNC = 2
+
+NNC_FAILED = 0
+NNC_CANDIDATES = 1
+
+EXPORTS = (
+    "nnc_create", "nnc_destroy", "nnc_init_certificates", "nnc_step", "nnc_repair", "nnc_rebuild",
+    "nnc_oracle_verify", "nnc_frontier_entropy", "nnc_get_state", "nnc_snapshot", "nnc_restore",
+    "nnc_snap_free", "nnc_allpairs_top2", "nnc_strerror",
+)
+
+
+class NNCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("grid_g", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("guard", ctypes.c_double), ("refresh", ctypes.c_double), ("stream", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("block", ctypes.c_int32)]
+
+
+class Frontier(ctypes.Structure):
+    _fields_ = [("idx_dev", ctypes.c_void_p), ("count_dev", ctypes.c_void_p),
+                ("count_host", ctypes.c_int32), ("step", ctypes.c_int32)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("nn", ctypes.c_void_p), ("d1", ctypes.c_void_p), ("d2", ctypes.c_void_p),
+                ("e", ctypes.c_void_p), ("cell", ctypes.c_void_p), ("fail", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("grid_g", ctypes.c_int32)]
+
+
+class Audit(ctypes.Structure):
+    _fields_ = [("n_checked", ctypes.c_int64), ("n_detect", ctypes.c_int64), ("n_true_fail", ctypes.c_int64),
+                ("n_missed", ctypes.c_int64), ("n_false", ctypes.c_int64), ("n_value_mismatch", ctypes.c_int64),
+                ("nn_hash", ctypes.c_uint64)]
+
+
+class Entropy(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("S", ctypes.c_double), ("H", ctypes.c_double),
+                ("m", ctypes.c_int32), ("C", ctypes.c_int32), ("count", ctypes.c_int32)]
+
+
+_lib = None
+_hip = None
+
+
+def load():
+    """Load libnncert.so (built in-tree); raises if it has not been built."""
+    global _lib, _hip
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           f"or python paper_2606_18314_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.nnc_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(Config)]
+    lib.nnc_destroy.argtypes = [P]
+    lib.nnc_destroy.restype = None
+    lib.nnc_init_certificates.argtypes = [P, P]
+    lib.nnc_step.argtypes = [P, P, ctypes.c_float, ctypes.POINTER(Frontier)]
+    lib.nnc_repair.argtypes = [P, ctypes.POINTER(Frontier)]
+    lib.nnc_rebuild.argtypes = [P]
+    lib.nnc_oracle_verify.argtypes = [P, ctypes.POINTER(Audit)]
+    lib.nnc_frontier_entropy.argtypes = [P, ctypes.c_int, ctypes.POINTER(Entropy)]
+    lib.nnc_get_state.argtypes = [P, ctypes.POINTER(State)]
+    lib.nnc_snapshot.argtypes = [P, ctypes.POINTER(P)]
+    lib.nnc_restore.argtypes = [P, P]
+    lib.nnc_snap_free.argtypes = [P]
+    lib.nnc_snap_free.restype = None
+    lib.nnc_allpairs_top2.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P, P, P]
+    lib.nnc_strerror.argtypes = [ctypes.c_int]
+    lib.nnc_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def hip():
+    """The HIP runtime torch loaded (same soname), for raw device copies."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so.7")
+        _hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                        ctypes.c_void_p]
+    return _hip
+
+
+def strerror(code: int) -> str:
+    return load().nnc_strerror(code).decode()
+
+
+def check(code: int, where: str) -> None:
+    if code != NNC_OK:
+        raise NNCError(code, where)
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def copy_from_device(dst: torch.Tensor, src_ptr: int, nbytes: int) -> torch.Tensor:
+    """Copy nbytes of library-owned device memory into a CUDA tensor (stream-ordered)."""
+    if nbytes:
+        rc = hip().hipMemcpyAsync(dst.data_ptr(), src_ptr, nbytes, 3, _stream())  # 3 = device to device
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+    return dst
+
+
+def allpairs_top2(pos: torch.Tensor, qidx: torch.Tensor | None = None):
+    """Exact all-pairs top-2 of float32 [d, n] positions: (nn, d1, d2) CUDA tensors."""
+    d, n = pos.shape
+    nq = n if qidx is None else qidx.numel()
+    dev = pos.device
+    nn = torch.empty(nq, dtype=torch.int32, device=dev)
+    d1 = torch.empty(nq, dtype=torch.float32, device=dev)
+    d2 = torch.empty(nq, dtype=torch.float32, device=dev)
+    check(load().nnc_allpairs_top2(_ptr(pos), n, d, _ptr(qidx), nq, _ptr(nn), _ptr(d1), _ptr(d2), _stream()),
+          "nnc_allpairs_top2")
+    return nn, d1, d2
+
+
+class Snapshot:
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.nnc_snap_free(self.handle)
+            self.handle = 0
+
+
+class NNCert:
+    """One moving point set and its certificates, on the current CUDA stream."""
+
+    def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
+                 copy_positions: bool = False, sync: bool = False, stream: int | None = None):
+        lib = load()
+        self.n, self.d = int(n), int(d)
+        self.stream = _stream() if stream is None else stream
+        cfg = Config(d=self.d, grid_g=int(grid_g), n=self.n, guard=float(guard), refresh=float(refresh),
+                     stream=self.stream,
+                     flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0), block=0)
+        h = ctypes.c_void_p()
+        check(lib.nnc_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_create")
+        self.h = h.value
+        self._keep = []  # borrowed position tensors stay alive while referenced by the library
+        st = State()
+        check(lib.nnc_get_state(self.h, ctypes.byref(st)), "nnc_get_state")
+        self.grid_g = st.grid_g
+        self._state = st
+        self.frontier = Frontier()
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.nnc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _hold(self, pos):
+        self._keep = (self._keep + [pos])[-2:]
+
+    def init_certificates(self, pos: torch.Tensor) -> None:
+        self._hold(pos)
+        check(_lib.nnc_init_certificates(self.h, _ptr(pos)), "nnc_init_certificates")
+
+    def step(self, pos: torch.Tensor, eps_declared: float = -1.0) -> Frontier:
+        self._hold(pos)
+        check(_lib.nnc_step(self.h, _ptr(pos), float(eps_declared), ctypes.byref(self.frontier)), "nnc_step")
+        return self.frontier
+
+    def repair(self, idx: torch.Tensor | None = None, count: torch.Tensor | None = None) -> None:
+        if idx is None:
+            check(_lib.nnc_repair(self.h, None), "nnc_repair")
+        else:
+            f = Frontier(idx_dev=_ptr(idx), count_dev=_ptr(count), count_host=-1, step=0)
+            check(_lib.nnc_repair(self.h, ctypes.byref(f)), "nnc_repair")
+
+    def rebuild(self) -> None:
+        check(_lib.nnc_rebuild(self.h), "nnc_rebuild")
+
+    def oracle_verify(self) -> dict:
+        a = Audit()
+        check(_lib.nnc_oracle_verify(self.h, ctypes.byref(a)), "nnc_oracle_verify")
+        return {k: getattr(a, k) for k, _ in Audit._fields_}
+
+    def frontier_entropy(self, which: int = NNC_FAILED) -> dict:
+        e = Entropy()
+        check(_lib.nnc_frontier_entropy(self.h, which, ctypes.byref(e)), "nnc_frontier_entropy")
+        return {k: getattr(e, k) for k, _ in Entropy._fields_}
+
+    def frontier_indices(self) -> torch.Tensor:
+        """The last step's candidate list as a CUDA int32 tensor (synchronises)."""
+        cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+        copy_from_device(cnt, self.frontier.count_dev, 4)
+        k = int(cnt.item())
+        out = torch.empty(k, dtype=torch.int32, device="cuda")
+        return copy_from_device(out, self.frontier.idx_dev, 4 * k)
+
+    def state(self) -> dict:
+        """Copies of the state arrays as CUDA tensors."""
+        st, n = self._state, self.n
+        spec = [("nn", torch.int32, 4), ("d1", torch.float32, 4), ("d2", torch.float32, 4),
+                ("e", torch.float64, 8), ("cell", torch.int32, 4), ("fail", torch.uint8, 1)]
+        out = {}
+        for name, dt, sz in spec:
+            t = torch.empty(n, dtype=dt, device="cuda")
+            out[name] = copy_from_device(t, getattr(st, name), n * sz)
+        return out
+
+    def snapshot(self) -> Snapshot:
+        h = ctypes.c_void_p()
+        check(_lib.nnc_snapshot(self.h, ctypes.byref(h)), "nnc_snapshot")
+        return Snapshot(h.value)
+
+    def restore(self, snap: Snapshot) -> None:
+        check(_lib.nnc_restore(self.h, snap.handle), "nnc_restore")

@@ -1,0 +1,380 @@
+// C ABI of libnncert: context lifetime, the maintenance step, repair, rebuild,
+// verification, entropy and snapshots.  Host code only; every computation is
+// in the kernels of grid.hip and allpairs.hip.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "internal.hpp"
+
+using nnc::DevScalars;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxCells = 1 << 24;
+constexpr int kRefreshSteps = 8;   // grid refresh interval when no eps bound is declared
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carver {
+    char *base;
+    size_t off;
+    template <class T>
+    T *take(size_t count)
+    {
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off = align_up(off + count * sizeof(T));
+        return p;
+    }
+};
+
+// Lay out every buffer of the context in one arena (base == nullptr: measure).
+// The state that a snapshot must copy comes first.
+size_t carve(nnc_ctx *c, char *base)
+{
+    const size_t n = (size_t)c->n > 0 ? (size_t)c->n : 1;
+    const size_t nc = (size_t)c->ncell;
+    Carver k{base, 0};
+    c->sc = k.take<DevScalars>(1);
+    c->nn = k.take<int32_t>(n);
+    c->cell = k.take<int32_t>(n);
+    c->stamp = k.take<int32_t>(n);
+    c->d1 = k.take<float>(n);
+    c->d2 = k.take<float>(n);
+    c->e = k.take<double>(n);
+    c->fail = k.take<uint8_t>(n);
+    c->frontier = k.take<int32_t>(n);
+    c->grid.counts = k.take<int>(nc);
+    c->grid.cell_start = k.take<int>(nc + 1);
+    c->grid.perm = k.take<int>(n);
+    c->grid.sorted = k.take<float>(n * (size_t)c->d);
+    c->hist_fail = k.take<int32_t>(nc);
+    c->hist_cand = k.take<int32_t>(nc);
+    c->state_bytes = k.off;
+    c->grid.cursor = k.take<int>(nc);
+    c->touched_fail = k.take<int32_t>(n);
+    c->touched_cand = k.take<int32_t>(n);
+    const size_t tiles = ((n > nc ? n : nc) + 2047) / 2048 + 1;
+    c->nstatus = (int)tiles;
+    c->status = k.take<unsigned long long>(tiles);
+    c->a_nn = k.take<int32_t>(n);
+    c->a_d1 = k.take<float>(n);
+    c->a_d2 = k.take<float>(n);
+    if (c->flags & NNC_COPY_POSITIONS) {
+        c->pos_copy[0] = k.take<float>(n * (size_t)c->d);
+        c->pos_copy[1] = k.take<float>(n * (size_t)c->d);
+    } else {
+        c->pos_copy[0] = c->pos_copy[1] = nullptr;
+    }
+    return k.off;
+}
+
+int default_grid(int64_t n, int d)
+{
+    if (n <= 0) return 1;
+    const double w = d == 2 ? 2.0 / sqrt((double)n) : cbrt(4.0 / (double)n);
+    const double g = floor(1.0 / w);
+    return g < 1.0 ? 1 : (int)g;
+}
+
+int sync_scalars(nnc_ctx *c, DevScalars *h)
+{
+    if (hipMemcpyAsync(h, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return NNC_E_HIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return NNC_E_HIP;
+    return NNC_OK;
+}
+
+// Map and clear latched device errors.
+int take_error(nnc_ctx *c, const DevScalars &h)
+{
+    if (h.err == 0u) return NNC_OK;
+    const unsigned zero = 0u;
+    (void)hipMemcpyAsync(&c->sc->err, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (h.err & nnc::kErrNonFinite) return NNC_E_NONFINITE;
+    if (h.err & nnc::kErrEps) return NNC_E_EPS;
+    return NNC_E_DEVICE;
+}
+
+const float *adopt_positions(nnc_ctx *c, const float *pos)
+{
+    if (!(c->flags & NNC_COPY_POSITIONS)) return pos;
+    float *dst = c->pos_copy[c->copy_slot];
+    c->copy_slot ^= 1;
+    (void)hipMemcpyAsync(dst, pos, (size_t)c->n * (size_t)c->d * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    return dst;
+}
+
+int build_grid(nnc_ctx *c)
+{
+    const int rc = nnc::launch_grid_build(c, c->pos_cur);
+    c->grid_fresh = 1;
+    c->drift_host = 0.0;
+    c->steps_since_grid = 0;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nnc_strerror(int code)
+{
+    switch (code) {
+    case NNC_OK: return "ok";
+    case NNC_E_INVAL: return "invalid argument";
+    case NNC_E_NOMEM: return "device allocation failed";
+    case NNC_E_HIP: return "HIP runtime error";
+    case NNC_E_EPS: return "measured step exceeds the declared eps";
+    case NNC_E_NONFINITE: return "non-finite coordinate";
+    case NNC_E_STATE: return "call out of order";
+    case NNC_E_DEVICE: return "device-side wait expired";
+    default: return "unknown error";
+    }
+}
+
+int nnc_create(nnc_ctx **out, const nnc_config *cfg)
+{
+    if (!out || !cfg) return NNC_E_INVAL;
+    *out = nullptr;
+    if (cfg->d != 2 && cfg->d != 3) return NNC_E_INVAL;
+    if (cfg->n < 0 || cfg->n >= (int64_t)1 << 31) return NNC_E_INVAL;
+    const int G = cfg->grid_g > 0 ? cfg->grid_g : default_grid(cfg->n, cfg->d);
+    const double cells = pow((double)G, (double)cfg->d);
+    if (G < 1 || cells > (double)kMaxCells) return NNC_E_INVAL;
+    nnc_ctx *c = new (std::nothrow) nnc_ctx();
+    if (!c) return NNC_E_NOMEM;
+    c->d = cfg->d;
+    c->n = cfg->n;
+    c->G = G;
+    c->ncell = (int)cells;
+    c->block = cfg->block > 0 ? cfg->block : 256;
+    c->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
+    c->K = 1.0 / (4.0 + 4.0 * c->guard);
+    c->refresh_w = (cfg->refresh > 0.0 ? cfg->refresh : 0.25) / (double)G;
+    c->stream = (hipStream_t)cfg->stream;
+    c->flags = cfg->flags;
+    c->grid.G = G;
+    c->grid.ncell = c->ncell;
+    c->arena_bytes = carve(c, nullptr);
+    if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return NNC_E_NOMEM;
+    }
+    carve(c, (char *)c->arena);
+    if (hipMemsetAsync(c->arena, 0, c->arena_bytes, c->stream) != hipSuccess) {
+        (void)hipFree(c->arena);
+        delete c;
+        return NNC_E_HIP;
+    }
+    c->epoch = 0u;
+    *out = c;
+    return NNC_OK;
+}
+
+void nnc_destroy(nnc_ctx *c)
+{
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    (void)hipFree(c->arena);
+    delete c;
+}
+
+int nnc_init_certificates(nnc_ctx *c, const float *pos)
+{
+    if (!c || (!pos && c->n > 0)) return NNC_E_INVAL;
+    c->pos_cur = adopt_positions(c, pos);
+    c->pos_prev = nullptr;
+    c->t = 0;
+    c->pending = 0;
+    // everything but the status words (whose epochs keep increasing) starts at zero
+    if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
+    int rc = nnc::launch_cells_init(c, c->pos_cur);
+    if (rc == NNC_OK) rc = build_grid(c);
+    if (rc == NNC_OK) rc = nnc::launch_query(c, nullptr, nullptr, 1, 1);
+    c->inited = rc == NNC_OK;
+    return rc;
+}
+
+int nnc_step(nnc_ctx *c, const float *pos_new, float eps_declared, nnc_frontier *out)
+{
+    if (!c || (!pos_new && c->n > 0)) return NNC_E_INVAL;
+    if (!c->inited || c->pending) return NNC_E_STATE;
+    c->t += 1;
+    c->pos_prev = c->pos_cur;
+    c->pos_cur = adopt_positions(c, pos_new);
+    int rc = nnc::launch_ingest(c, c->pos_prev, c->pos_cur);
+    if (rc == NNC_OK) rc = nnc::launch_filter(c, eps_declared);
+    if (rc != NNC_OK) return rc;
+    c->grid_fresh = 0;
+    if (eps_declared >= 0.0f && c->drift_host >= 0.0)
+        c->drift_host += (double)eps_declared * (1.0 + 0x1p-16) + 0x1p-20;
+    else
+        c->drift_host = -1.0;
+    c->pending = 1;
+    if (out) {
+        out->idx_dev = c->frontier;
+        out->count_dev = &c->sc->nfront;
+        out->count_host = -1;
+        out->step = (int32_t)c->t;
+    }
+    if (c->flags & NNC_SYNC) {
+        DevScalars h;
+        rc = sync_scalars(c, &h);
+        if (rc != NNC_OK) return rc;
+        if (out) out->count_host = h.nfront;
+        return take_error(c, h);
+    }
+    return NNC_OK;
+}
+
+int nnc_repair(nnc_ctx *c, const nnc_frontier *f)
+{
+    if (!c) return NNC_E_INVAL;
+    if (!c->pending) return NNC_E_STATE;
+    if (f && (!f->idx_dev || !f->count_dev)) return NNC_E_INVAL;
+    int rc = NNC_OK;
+    const bool refresh = c->drift_host < 0.0 ? c->steps_since_grid >= kRefreshSteps : c->drift_host > c->refresh_w;
+    if (refresh) rc = build_grid(c);
+    if (rc == NNC_OK)
+        rc = nnc::launch_query(c, f ? f->idx_dev : c->frontier, f ? f->count_dev : &c->sc->nfront, 0, 0);
+    if (rc == NNC_OK) rc = nnc::launch_entropy(c, 0);
+    c->pending = 0;
+    c->steps_since_grid += 1;
+    return rc;
+}
+
+int nnc_rebuild(nnc_ctx *c)
+{
+    if (!c) return NNC_E_INVAL;
+    if (!c->pending) return NNC_E_STATE;
+    int rc = build_grid(c);
+    if (rc == NNC_OK) rc = nnc::launch_query(c, nullptr, nullptr, 1, 0);
+    if (rc == NNC_OK) rc = nnc::launch_entropy(c, 0);
+    c->pending = 0;
+    return rc;
+}
+
+int nnc_oracle_verify(nnc_ctx *c, nnc_audit *out)
+{
+    if (!c || !out) return NNC_E_INVAL;
+    if (!c->inited) return NNC_E_STATE;
+    int rc = nnc::launch_allpairs(c->pos_cur, c->n, c->d, nullptr, c->n, c->a_nn, c->a_d1, c->a_d2, c->stream);
+    if (rc != NNC_OK) return rc;
+    if (hipMemsetAsync(c->sc->audit, 0, sizeof(c->sc->audit), c->stream) != hipSuccess) return NNC_E_HIP;
+    rc = nnc::launch_audit(c);
+    if (rc != NNC_OK) return rc;
+    DevScalars h;
+    rc = sync_scalars(c, &h);
+    if (rc != NNC_OK) return rc;
+    out->n_checked = c->n;
+    out->n_detect = h.nfront;
+    out->n_true_fail = (int64_t)h.audit[2];
+    out->n_missed = (int64_t)h.audit[0];
+    out->n_false = (int64_t)h.nfront - (int64_t)h.audit[5];
+    out->n_value_mismatch = (int64_t)h.audit[1];
+    out->nn_hash = h.audit[4];
+    return take_error(c, h);
+}
+
+int nnc_frontier_entropy(nnc_ctx *c, int which, nnc_entropy *out)
+{
+    if (!c || !out || (which != NNC_FAILED && which != NNC_CANDIDATES)) return NNC_E_INVAL;
+    if (!c->inited) return NNC_E_STATE;
+    int rc = NNC_OK;
+    if (which == NNC_CANDIDATES) {
+        rc = nnc::launch_cand_hist(c);
+        if (rc == NNC_OK) rc = nnc::launch_entropy(c, 1);
+        if (rc != NNC_OK) return rc;
+    }
+    DevScalars h;
+    rc = sync_scalars(c, &h);
+    if (rc != NNC_OK) return rc;
+    out->eps = h.eps;
+    out->S = h.S[c->t & 1];
+    out->H = h.H[which];
+    out->m = h.m[which];
+    out->C = h.Cres[which];
+    out->count = h.F[which];
+    return take_error(c, h);
+}
+
+int nnc_get_state(nnc_ctx *c, nnc_state *v)
+{
+    if (!c || !v) return NNC_E_INVAL;
+    v->nn = c->nn;
+    v->d1 = c->d1;
+    v->d2 = c->d2;
+    v->e = c->e;
+    v->cell = c->cell;
+    v->fail = c->fail;
+    v->n = c->n;
+    v->d = c->d;
+    v->grid_g = c->G;
+    return NNC_OK;
+}
+
+int nnc_snapshot(nnc_ctx *c, nnc_snap **out)
+{
+    if (!c || !out) return NNC_E_INVAL;
+    nnc_snap *s = new (std::nothrow) nnc_snap();
+    if (!s) return NNC_E_NOMEM;
+    s->bytes = c->state_bytes;
+    if (hipMalloc(&s->dev, s->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return NNC_E_NOMEM;
+    }
+    if (hipMemcpyAsync(s->dev, c->arena, s->bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+        (void)hipFree(s->dev);
+        delete s;
+        return NNC_E_HIP;
+    }
+    s->t = c->t;
+    s->pending = c->pending;
+    s->grid_fresh = c->grid_fresh;
+    s->drift_host = c->drift_host;
+    s->steps_since_grid = c->steps_since_grid;
+    s->pos_cur = c->pos_cur;
+    s->pos_prev = c->pos_prev;
+    *out = s;
+    return NNC_OK;
+}
+
+int nnc_restore(nnc_ctx *c, const nnc_snap *s)
+{
+    if (!c || !s || s->bytes != c->state_bytes) return NNC_E_INVAL;
+    if (hipMemcpyAsync(c->arena, s->dev, s->bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return NNC_E_HIP;
+    c->t = s->t;
+    c->pending = s->pending;
+    c->grid_fresh = s->grid_fresh;
+    c->drift_host = s->drift_host;
+    c->pos_cur = s->pos_cur;
+    c->pos_prev = s->pos_prev;
+    c->steps_since_grid = s->steps_since_grid;
+    return NNC_OK;
+}
+
+void nnc_snap_free(nnc_snap *s)
+{
+    if (!s) return;
+    (void)hipFree(s->dev);
+    delete s;
+}
+
+int nnc_allpairs_top2(const float *pos, int64_t n, int32_t d, const int32_t *qidx, int64_t nq, int32_t *nn,
+                      float *d1, float *d2, void *stream)
+{
+    if ((d != 2 && d != 3) || n < 0 || n >= (int64_t)1 << 31 || nq < 0) return NNC_E_INVAL;
+    if (!qidx && nq != n) return NNC_E_INVAL;
+    if (nq > 0 && (!pos || !nn || !d1 || !d2)) return NNC_E_INVAL;
+    return nnc::launch_allpairs(pos, n, d, qidx, nq, nn, d1, d2, (hipStream_t)stream);
+}
+
+}  // extern "C"

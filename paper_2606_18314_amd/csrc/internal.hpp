@@ -1,0 +1,129 @@
+// Internal declarations of libnncert: the context, the device scalar block and
+// the host-side launchers of each kernel family.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nncert.h"
+
+namespace nnc {
+
+// Bits of the device error word.
+enum : unsigned { kErrNonFinite = 1u, kErrEps = 2u, kErrSpin = 4u, kErrOverflow = 8u };
+
+// Scalars that live on the device so that a step never waits for the host.
+// The clock and the displacement maximum are double-buffered by step parity:
+// step t reads S[(t-1)&1], writes S[t&1]; its ingest accumulates into dmax[t&1].
+struct DevScalars {
+    double S[2];
+    double S_grid;           // clock when the grid index was last built
+    double eps;              // eps_t of the last step
+    unsigned dmax[2];        // largest squared displacement (float bits), per parity
+    int C;                   // occupied cells
+    int nfront;              // candidates of the last step
+    int nfail;               // failures of the last repair/rebuild
+    int ntouched;            // cells met by those failures
+    int ncand_touched;       // cells met by the candidates (on demand)
+    unsigned err;            // kErr* bits
+    unsigned tile_ctr;       // look-back scan ticket
+    int pad;
+    // results of the entropy kernel: [0] failures, [1] candidates
+    double H[2];
+    int m[2];
+    int F[2];
+    int Cres[2];
+    // audit counters
+    unsigned long long audit[6];
+};
+
+struct Grid {
+    int G, ncell;
+    int *counts;        // [ncell] occupancy of current cells
+    int *cell_start;    // [ncell+1]
+    int *cursor;        // [ncell] scatter cursors
+    int *perm;          // [n] grid order -> point index
+    float *sorted;      // [d][n] coordinates in grid order at build time
+};
+
+// Query-side description of one scene (single-scene or one scene of a batch).
+struct SceneView {
+    const float *pos;   // current positions [d][n]
+    int n, G;
+    const int *cell_start, *perm;
+    const float *sorted;      // coordinates in grid order (valid when fresh)
+};
+
+}  // namespace nnc
+
+struct nnc_snap {
+    size_t bytes;
+    void *dev;
+    int64_t t;
+    int pending;
+    int grid_fresh;
+    double drift_host;
+    int steps_since_grid;
+    const float *pos_cur;
+    const float *pos_prev;
+};
+
+struct nnc_ctx {
+    int d, G, ncell, block;
+    int64_t n;
+    double guard, K, refresh_w;
+    hipStream_t stream;
+    uint32_t flags;
+
+    // state, original point order
+    int32_t *nn, *cell, *stamp;
+    float *d1, *d2;
+    double *e;
+    uint8_t *fail;
+    // grid index
+    nnc::Grid grid;
+    // frontier and histograms
+    int32_t *frontier;
+    int32_t *hist_fail, *touched_fail;
+    int32_t *hist_cand, *touched_cand;
+    unsigned long long *status;   // look-back tile descriptors
+    int nstatus;
+    nnc::DevScalars *sc;
+    // audit scratch
+    int32_t *a_nn;
+    float *a_d1, *a_d2;
+    // one arena holds every buffer above
+    void *arena;
+    size_t arena_bytes;
+    size_t state_bytes;           // prefix of the arena that a snapshot copies
+
+    const float *pos_cur, *pos_prev;
+    float *pos_copy[2];
+    int copy_slot;
+
+    int64_t t;
+    int pending;
+    int grid_fresh;               // grid built at the current step (sorted coords current)
+    double drift_host;            // accumulated declared eps since the grid build; <0 unknown
+    int steps_since_grid;
+    unsigned epoch;
+    int inited;
+};
+
+namespace nnc {
+
+// grid.hip
+int launch_cells_init(nnc_ctx *c, const float *pos);
+int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew);
+int launch_filter(nnc_ctx *c, float eps_declared);
+int launch_grid_build(nnc_ctx *c, const float *pos);
+int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init);
+int launch_entropy(nnc_ctx *c, int which);
+int launch_cand_hist(nnc_ctx *c);
+int launch_audit(nnc_ctx *c);
+int launch_fill(void *p, int value, size_t count, hipStream_t s);
+
+// allpairs.hip
+int launch_allpairs(const float *pos, int64_t n, int d, const int32_t *qidx, int64_t nq,
+                    int32_t *nn, float *d1, float *d2, hipStream_t s);
+
+}  // namespace nnc

@@ -17,8 +17,9 @@ these definitions:
   displacement of per-axis scale eps/sqrt(d), its Euclidean length clipped to eps.
 * ``ring_rotation``: a ring of radius 0.4 about the box centre (in the z = 0.5
   plane for d = 3) with static Gaussian thickness 1e-3; each step rotates the set
-  rigidly about the centre at rim speed eps/2 and adds Brownian jitter clipped
-  to eps/2.
+  rigidly about the centre by the angle that moves radius 0.45 (beyond the
+  ring's support) by eps/2, and adds Brownian jitter clipped to eps/2, so eps
+  bounds every step.
 * ``adversarial_crossing``: two Gaussian blobs (sigma 0.05) centred at x = 0.45
   and x = 0.55 translate toward each other by eps per step along x (they cross
   after 0.05/eps steps).
@@ -130,7 +131,7 @@ def make_trajectory(family: str, n: int, d: int, steps: int, eps: float, seed) -
     frames = np.empty((steps + 1, d, n), dtype=np.float32)
     frames[0] = _f32(p64)
     centre = 0.5
-    omega = (0.5 * eps) / 0.4
+    omega = (0.5 * eps) / 0.45
     c, s = math.cos(omega), math.sin(omega)
     for t in range(steps):
         cur = frames[t].astype(np.float64)

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Integer and index results (nn, cells, candidate lists, failure flags) and the
+binary32 certificate values (d1, d2) must be identical; the binary64 expiry keys
+and clock are identical too (same operations, no contraction).  Only the
+entropy H, a binary64 sum in a different order, has a tolerance (1e-12 relative).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import model
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+H_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def nnc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_18314_amd as p
+    p.load()
+    return p
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def assert_state_equal(gs, sc, tag):
+    assert np.array_equal(host(gs["nn"]), sc.nn), tag
+    assert np.array_equal(bits(host(gs["d1"])), bits(sc.d1)), tag
+    assert np.array_equal(bits(host(gs["d2"])), bits(sc.d2)), tag
+    assert np.array_equal(bits(host(gs["e"])), bits(sc.e)), tag
+    assert np.array_equal(host(gs["cell"]), sc.cell), tag
+    assert np.array_equal(host(gs["fail"]).astype(bool), sc.fail), tag
+
+
+# --- all-pairs top-2 ---------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1000, 4097])
+def test_allpairs_matches_oracle(nnc, d, n):
+    g = np.random.default_rng(n * 10 + d)
+    pos = g.random((d, n)).astype(np.float32)
+    if n > 8:
+        pos[:, 5] = pos[:, 3]                  # a duplicate: exact tie at distance 0
+        pos[:, 7] = (g.integers(0, 4, d) / 8).astype(np.float32)
+        pos[:, 8] = pos[:, 7] + np.float32(0.125)
+    nn, d1, d2 = nnc.allpairs_top2(dev(pos))
+    onn, od1, od2 = model.top2(pos)
+    assert np.array_equal(host(nn), onn)
+    assert np.array_equal(bits(host(d1)), bits(od1))
+    assert np.array_equal(bits(host(d2)), bits(od2))
+
+
+def test_allpairs_lattice_ties(nnc):
+    """Points on a lattice: every certificate has exact ties; lowest index must win."""
+    g = np.random.default_rng(5)
+    for d in (2, 3):
+        pos = (g.integers(0, 6, (d, 3000)) / 8.0).astype(np.float32)
+        nn, d1, d2 = nnc.allpairs_top2(dev(pos))
+        onn, od1, od2 = model.top2(pos)
+        assert np.array_equal(host(nn), onn)
+        assert np.array_equal(bits(host(d2)), bits(od2))
+
+
+def test_allpairs_subset_mode(nnc):
+    g = np.random.default_rng(6)
+    pos = g.random((3, 5000)).astype(np.float32)
+    q = np.sort(g.choice(5000, 777, replace=False)).astype(np.int32)
+    nn, d1, d2 = nnc.allpairs_top2(dev(pos), dev(q))
+    onn, od1, od2 = model.top2(pos, q)
+    assert np.array_equal(host(nn), onn)
+    assert np.array_equal(bits(host(d1)), bits(od1))
+    assert np.array_equal(bits(host(d2)), bits(od2))
+
+
+def test_allpairs_config2_size(nnc):
+    tr = synth.config2("clustered_drift", steps=1)
+    pos = tr.frames[1]
+    nn, d1, d2 = nnc.allpairs_top2(dev(pos))
+    onn, od1, od2 = model.top2(pos)
+    assert np.array_equal(host(nn), onn)
+    assert np.array_equal(bits(host(d1)), bits(od1))
+    assert np.array_equal(bits(host(d2)), bits(od2))
+
+
+# --- the state machine ---------------------------------------------------------------
+
+def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1):
+    d, n = traj.d, traj.n
+    frames = [dev(f) for f in traj.frames]
+    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard)
+    assert ctx.grid_g == G
+    sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard)
+    ctx.init_certificates(frames[0])
+    sc.init_certificates(traj.frames[0])
+    assert_state_equal(ctx.state(), sc, "init")
+    T = traj.steps if steps is None else steps
+    for t in range(1, T + 1):
+        ctx.step(frames[t], traj.eps)
+        res = sc.step(traj.frames[t])
+        cand = host(ctx.frontier_indices())
+        assert np.array_equal(cand, res.candidates), f"candidates step {t}"
+        ent_c = ctx.frontier_entropy(nnc.NNC_CANDIDATES)
+        assert ent_c["eps"] == float(res.eps)
+        assert ent_c["S"] == res.S
+        H, m, C, F = sc.frontier_entropy(model.CANDIDATES, res.candidates)
+        assert (ent_c["m"], ent_c["C"], ent_c["count"]) == (m, C, F)
+        assert abs(ent_c["H"] - H) <= H_TOL * max(1.0, abs(H))
+        use = strategy if strategy != "alternate" else ("rebuild" if t % 4 == 0 else "repair")
+        if use == "repair":
+            ctx.repair()
+            sc.repair()
+        else:
+            ctx.rebuild()
+            sc.rebuild()
+        if t % check_every == 0 or t == T:
+            assert_state_equal(ctx.state(), sc, f"step {t}")
+            ent = ctx.frontier_entropy(nnc.NNC_FAILED)
+            H, m, C, F = sc.frontier_entropy(model.FAILED)
+            assert (ent["m"], ent["C"], ent["count"]) == (m, C, F), f"step {t}"
+            assert abs(ent["H"] - H) <= H_TOL * max(1.0, abs(H))
+    audit = ctx.oracle_verify()
+    assert audit["n_missed"] == 0
+    assert audit["n_value_mismatch"] == 0
+    ctx.close()
+    return audit
+
+
+def test_config1_every_step(nnc):
+    run_parity(nnc, synth.config1(), G=15)
+
+
+def test_config1_rebuild_every_step(nnc):
+    run_parity(nnc, synth.config1(steps=20), G=15, strategy="rebuild")
+
+
+@pytest.mark.parametrize("family", synth.FAMILIES)
+def test_config2_families_reduced(nnc, family):
+    tr = synth.make_trajectory(family, 4000, 3, 40, 5e-4, 2000 + synth.FAMILIES.index(family))
+    run_parity(nnc, tr, G=9, strategy="alternate")
+
+
+@pytest.mark.parametrize("family", synth.FAMILIES)
+def test_config2_families_full_size(nnc, family):
+    """N = 16000, d = 3 at the default grid (G = 15), first 6 steps, every array checked."""
+    tr = synth.config2(family, steps=6)
+    run_parity(nnc, tr, G=15)
+
+
+def test_guard_zero_literal_key(nnc):
+    run_parity(nnc, synth.config1(steps=15), G=15, guard=0.0)
+
+
+# --- edge cases ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5])
+def test_tiny_scenes(nnc, n):
+    g = np.random.default_rng(n)
+    tr = synth.Trajectory("custom", 3, n, -1.0,
+                          np.cumsum(g.random((4, 3, n)).astype(np.float32) * np.float32(0.01), axis=0)
+                          .astype(np.float32))
+    run_parity(nnc, tr, G=3)
+
+
+def test_isolated_point_forces_widening(nnc):
+    """One point far from a tight cluster: its neighbours lie many rings away."""
+    g = np.random.default_rng(1)
+    n = 2000
+    p = np.empty((2, n))
+    p[:, :-1] = 0.1 + 0.02 * g.random((2, n - 1))
+    p[:, -1] = (0.95, 0.93)
+    frames = [p]
+    for _ in range(5):
+        q = frames[-1] + g.standard_normal((2, n)) * 1e-4
+        frames.append(q)
+    tr = synth.Trajectory("custom", 2, n, -1.0, np.array(frames, dtype=np.float32))
+    run_parity(nnc, tr, G=40)
+
+
+def test_points_outside_the_box_and_one_cell(nnc):
+    g = np.random.default_rng(2)
+    n = 600
+    p = g.standard_normal((3, n)) * 2.0            # mostly outside [0,1]^3
+    frames = [p + k * 1e-3 for k in range(4)]
+    tr = synth.Trajectory("custom", 3, n, -1.0, np.array(frames, dtype=np.float32))
+    run_parity(nnc, tr, G=4)
+    tr1 = synth.Trajectory("custom", 3, n, -1.0, np.array(frames, dtype=np.float32))
+    run_parity(nnc, tr1, G=1)
+
+
+def test_lattice_scene_with_ties(nnc):
+    g = np.random.default_rng(3)
+    n = 1500
+    p0 = g.integers(0, 64, (2, n)) / 64.0
+    frames = [p0]
+    for _ in range(6):
+        mv = g.integers(-1, 2, (2, n)) / 512.0
+        frames.append(frames[-1] + mv)
+    tr = synth.Trajectory("custom", 2, n, -1.0, np.array(frames, dtype=np.float32))
+    run_parity(nnc, tr, G=20)
+
+
+# --- API behaviour --------------------------------------------------------------------
+
+def test_error_paths(nnc):
+    tr = synth.config1(steps=2)
+    ctx = nnc.NNCert(1000, 2, grid_g=15)
+    with pytest.raises(nnc.NNCError) as ei:
+        ctx.repair()
+    assert ei.value.code == -6
+    ctx.init_certificates(dev(tr.frames[0]))
+    ctx.step(dev(tr.frames[1]), 1e-5)                  # declared bound below the measured step
+    with pytest.raises(nnc.NNCError) as ei:
+        ctx.frontier_entropy(nnc.NNC_FAILED)
+    assert ei.value.code == -4
+    with pytest.raises(nnc.NNCError):
+        ctx.step(dev(tr.frames[2]))                    # pending step not repaired
+    ctx.repair()
+    bad = tr.frames[2].copy()
+    bad[0, 17] = np.nan
+    ctx.step(dev(bad))
+    ctx.repair()
+    with pytest.raises(nnc.NNCError) as ei:
+        ctx.oracle_verify()
+    assert ei.value.code == -5
+    with pytest.raises(nnc.NNCError):
+        nnc.NNCert(10, 4)
+    ctx.close()
+
+
+def test_snapshot_restore_and_determinism(nnc):
+    tr = synth.config2("uniform_brownian", n=4000, steps=6)
+    frames = [dev(f) for f in tr.frames]
+    ctx = nnc.NNCert(4000, 3, grid_g=9)
+    ctx.init_certificates(frames[0])
+    for t in range(1, 5):
+        ctx.step(frames[t], tr.eps)
+        ctx.repair()
+    ctx.step(frames[5], tr.eps)
+    snap = ctx.snapshot()
+    ctx.repair()
+    a = ctx.state()
+    ctx.restore(snap)
+    ctx.rebuild()
+    b = ctx.state()
+    ctx.restore(snap)
+    ctx.repair()
+    c = ctx.state()
+    for k in ("nn", "cell"):
+        assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k])
+    for k in ("d1", "d2", "e", "fail"):
+        assert torch.equal(a[k], c[k])
+    ctx.close()
+
+
+def test_forced_frontier_list(nnc):
+    tr = synth.config1(steps=1)
+    ctx = nnc.NNCert(1000, 2, grid_g=15)
+    sc = model.OracleScene(d=2, n=1000, G=15)
+    ctx.init_certificates(dev(tr.frames[0]))
+    sc.init_certificates(tr.frames[0])
+    ctx.step(dev(tr.frames[1]))
+    sc.step(tr.frames[1])
+    forced = np.arange(0, 1000, 7, dtype=np.int32)
+    ctx.repair(dev(forced), dev(np.array([forced.size], np.int32)))
+    sc.repair(forced)
+    assert_state_equal(ctx.state(), sc, "forced")
+    ctx.close()
