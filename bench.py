@@ -1,0 +1,364 @@
+#!/usr/bin/env python3
+"""Benchmark of the certificate-maintenance step on one MI355X.
+
+Workload (the headline configuration): N = 16000 points in the unit cube,
+d = 3, the five motion families (uniform Brownian, ring rotation, adversarial
+crossing, clustered drift, shear band), eps = 5e-4, seeded synthetic
+trajectories resident in HBM before timing.  One bench step advances all five
+scenes by one transition through the whole maintenance path: ingest
+(eps_t, cells), safety filter and ordered compaction, grid repair of the
+candidates (with the amortised grid refresh) and the failure-entropy reduction.
+
+Legs, all on the same inputs:
+  repair    the method (Algorithm 1 with the clock), captured once in a HIP graph
+            and replayed: the headline value;
+  repair_eager  the same steps launched one call at a time;
+  rebuild   the O(N) grid rebuild competitor in place of the repair;
+  allpairs  the exact all-pairs top-2 competitor;
+plus a certification pass (every step audited by the GPU all-pairs oracle:
+zero missed failures and bitwise-equal fresh certificates), a kernel-timing
+pass (HIP events around the dominant kernel on the library's stream), and the
+CPU oracle timed on a bounded sample.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "certified point-steps/s (N=16k, d=3): repair vs rebuild vs batched; % roofline"
+N, D, EPS = 16000, 3, 5e-4
+HBM_PEAK_GBS = 8000.0
+# FP32 VALU issue rate without FMA and without packed FP32:
+# 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 operations/s.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=190)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--legs", default="repair,rebuild,allpairs")
+    ap.add_argument("--grid", default="auto", help="'auto' (tuned per family) or an integer G for all")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-certify", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    return ap.parse_args()
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2606_18314_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_tag, current_hash):
+    """HBM bytes per dispatch from a committed rocprofv3 --pmc summary, or None when
+    the summary is missing or was taken from a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != current_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the maintenance path of this "
+              f"build is single-GPU, see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2606_18314_amd as nnc
+    from paper_2606_18314_amd import autotune
+
+    nnc.load()
+    W, K = args.warmup, args.steps
+    T = W + K
+    dev = torch.device("cuda:0")
+    fams = list(synth.FAMILIES)
+    t_gen = time.time()
+    trajs = {f: synth.config2(f, n=N, steps=T) for f in fams}
+    frames = {f: torch.from_numpy(trajs[f].frames).to(dev) for f in fams}   # resident in HBM
+    torch.cuda.synchronize()
+    gen_s = time.time() - t_gen
+    stream = torch.cuda.Stream()
+    s_ptr = stream.cuda_stream
+
+    tuning = {}
+    if args.grid == "auto":
+        grids = {}
+        for f in fams:   # tuned on the first warm-up frames, outside every timed region
+            grids[f], tuning[f] = autotune.tune_grid([frames[f][t] for t in range(min(T, 8) + 1)], D, EPS,
+                                                     steps=min(T, 8))
+    else:
+        grids = {f: int(args.grid) for f in fams}
+
+    def make_ctxs():
+        ctxs = {}
+        with torch.cuda.stream(stream):
+            for f in fams:
+                c = nnc.NNCert(N, D, grid_g=grids[f], stream=s_ptr)
+                c.init_certificates(frames[f][0])
+                ctxs[f] = c
+        return ctxs
+
+    def run_steps(ctxs, t0, t1, strategy):
+        for t in range(t0, t1):
+            for f in fams:
+                c = ctxs[f]
+                c.step(frames[f][t], EPS)
+                if strategy == "repair":
+                    c.repair()
+                else:
+                    c.rebuild()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    out = {"metric": METRIC, "unit": "point-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic"}
+    legs = {}
+    legs_req = set(args.legs.split(","))
+    pts_per_step = N * len(fams)
+
+    # ---- repair and rebuild: eager, graph, kernel timing -------------------------------
+    kernel_avg = {}
+    audits = {}
+    for strategy in ("repair", "rebuild"):
+        if strategy not in legs_req:
+            continue
+        ctxs = make_ctxs()
+        with torch.cuda.stream(stream):
+            run_steps(ctxs, 1, W + 1, strategy)
+        torch.cuda.synchronize()
+        snaps = {f: ctxs[f].snapshot() for f in fams}
+        # eager timed region
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            run_steps(ctxs, W + 1, T + 1, strategy)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        eager_ms = e0.elapsed_time(e1)
+        # graph: capture the K steps once, replay as the timed region
+        with torch.cuda.stream(stream):
+            for f in fams:
+                ctxs[f].restore(snaps[f])
+        torch.cuda.synchronize()
+        # capture records the K steps without running them: afterwards the device
+        # state is still that of step W while the host side has advanced to step T,
+        # and the replay brings the device to step T as well
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            run_steps(ctxs, W + 1, T + 1, strategy)
+        torch.cuda.synchronize()
+        g0, g1 = ev(), ev()
+        g0.record(stream)
+        with torch.cuda.stream(stream):
+            g.replay()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1)
+        # after the replay the state is at step T: audit every scene against all-pairs
+        end_audit = {f: ctxs[f].oracle_verify() for f in fams}
+        # kernel timing pass (eager, HIP events on the library stream)
+        with torch.cuda.stream(stream):
+            for f in fams:
+                ctxs[f].restore(snaps[f])
+                ctxs[f].profile_enable(True)
+            run_steps(ctxs, W + 1, T + 1, strategy)
+        prof = {}
+        fam_q = {}
+        for f in fams:
+            for name, (ms, cnt) in ctxs[f].profile_read().items():
+                a = prof.setdefault(name, [0.0, 0])
+                a[0] += ms
+                a[1] += cnt
+                if name == "query" and cnt:
+                    fam_q[f] = round(ms * 1e3 / cnt, 2)
+            ctxs[f].profile_enable(False)
+        kernel_avg[strategy] = {k: (v[0] / v[1] if v[1] else 0.0, v[1]) for k, v in prof.items()}
+        # certification pass: every step audited by the exact GPU all-pairs oracle
+        cert = None
+        if not args.no_certify:
+            with torch.cuda.stream(stream):
+                for f in fams:
+                    ctxs[f].restore(snaps[f])
+            tot = {"steps": 0, "n_missed": 0, "n_value_mismatch": 0, "n_detect": 0, "n_true_fail": 0,
+                   "H_fail_sum": 0.0, "H_cand_sum": 0.0}
+            for t in range(W + 1, T + 1):
+                for f in fams:
+                    c = ctxs[f]
+                    with torch.cuda.stream(stream):
+                        c.step(frames[f][t], EPS)
+                    hc = c.frontier_entropy(nnc.NNC_CANDIDATES)
+                    with torch.cuda.stream(stream):
+                        c.repair() if strategy == "repair" else c.rebuild()
+                    hf = c.frontier_entropy(nnc.NNC_FAILED)
+                    a = c.oracle_verify()
+                    tot["steps"] += 1
+                    tot["n_missed"] += a["n_missed"]
+                    tot["n_value_mismatch"] += a["n_value_mismatch"]
+                    tot["n_detect"] += a["n_detect"]
+                    tot["n_true_fail"] += a["n_true_fail"]
+                    tot["H_fail_sum"] += hf["H"]
+                    tot["H_cand_sum"] += hc["H"]
+            cert = {"scene_steps": tot["steps"], "n_missed": tot["n_missed"],
+                    "n_value_mismatch": tot["n_value_mismatch"],
+                    "candidate_fraction": tot["n_detect"] / (tot["steps"] * N),
+                    "failure_fraction": tot["n_true_fail"] / (tot["steps"] * N),
+                    "mean_H_fail": tot["H_fail_sum"] / tot["steps"],
+                    "mean_H_candidates": tot["H_cand_sum"] / tot["steps"]}
+        audits[strategy] = cert
+        legs[strategy] = {
+            "value": pts_per_step * K / (graph_ms / 1e3),
+            "ms_per_step": graph_ms / K,
+            "eager_value": pts_per_step * K / (eager_ms / 1e3),
+            "eager_ms_per_step": eager_ms / K,
+            "end_state_missed": sum(a["n_missed"] for a in end_audit.values()),
+            "kernels_avg_us": {k: round(v[0] * 1e3, 3) for k, v in kernel_avg[strategy].items()},
+            "query_avg_us_per_family": fam_q,
+            "kernel_launches": {k: v[1] for k, v in kernel_avg[strategy].items()},
+            "certification": cert,
+        }
+        for f in fams:
+            ctxs[f].close()
+        del g
+
+    # ---- all-pairs competitor -----------------------------------------------------------
+    if "allpairs" in legs_req:
+        ksteps = min(K, 40)
+        with torch.cuda.stream(stream):
+            for t in range(1, 3):
+                for f in fams:
+                    nnc.allpairs_top2(frames[f][t])
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            for t in range(W + 1, W + 1 + ksteps):
+                for f in fams:
+                    nnc.allpairs_top2(frames[f][t])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        launch_us = ms * 1e3 / (ksteps * len(fams))
+        ops = (3 * D) * N * (N - 1)           # 3d-1 distance operations + 1 comparison per pair
+        legs["allpairs"] = {"value": pts_per_step * ksteps / (ms / 1e3), "ms_per_step": ms / ksteps,
+                            "steps": ksteps, "pairs_per_s": N * (N - 1) * ksteps * len(fams) / (ms / 1e3),
+                            "kernel_avg_us": launch_us,
+                            "roofline": {"bound": "alu", "achieved": ops / (launch_us * 1e-6) / 1e12,
+                                         "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
+                                         "frac": ops / (launch_us * 1e-6) / 1e12 / VALU_PEAK_TOPS,
+                                         "traffic": None}}
+
+    # ---- headline ------------------------------------------------------------------------
+    head = legs.get("repair")
+    if head is not None:
+        out["value"] = head["value"]
+        out["ms_per_step"] = head["ms_per_step"]
+        q_us, q_cnt = kernel_avg["repair"]["query"]
+        q_us *= 1e3
+        cand = audits["repair"]["candidate_fraction"] if audits.get("repair") else None
+        G = grids
+        # algorithmic bytes of one repair query launch (per scene): each candidate reads its
+        # coordinates and list entry and writes its certificate (nn, d1, d2, stamp 4 B each,
+        # expiry 8 B, fail flag 1 B); every point of the visited blocks is read once
+        # (coordinates + grid slot); the cell-start table is read once.
+        mean_cells = sum(g ** D for g in G.values()) / len(G)
+        if cand is not None:
+            per_launch = cand * N * (4 * D + 4 + 25) + N * (4 * D + 4) + 4 * (mean_cells + 1)
+        else:
+            per_launch = None
+        roof = None
+        if per_launch is not None and q_us > 0:
+            achieved = per_launch / (q_us * 1e-6) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": read_traffic("query_repair_config2", src_hash("grid.hip", "device_common.hpp")),
+                    "kernel": "k_query (repair of the candidates)", "avg_launch_us": q_us,
+                    "bytes_per_launch": per_launch}
+        out["roofline"] = roof
+    out["config"] = {"workload": "config2: N=16000 points, d=3, five motion families, eps=5e-4, "
+                                 f"{K} timed steps after {W} warm-up steps, HIP-graph replay",
+                     "families": fams, "grid_g": grids, "grid_tuning_ms": tuning, "strategy": "repair",
+                     "generator_seconds": round(gen_s, 2)}
+    out["strategies"] = legs
+
+    if "repair" in legs and audits.get("repair"):
+        a = audits["repair"]
+        out["certified"] = a["n_missed"] == 0 and a["n_value_mismatch"] == 0 and legs["repair"][
+            "end_state_missed"] == 0
+
+    # ---- counter calibration copy ----------------------------------------------------------
+    if args.copy_mib:
+        nbytes = args.copy_mib * 2 ** 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
+
+    # ---- CPU oracle baseline -------------------------------------------------------------
+    if not args.no_cpu_baseline:
+        from oracle import model
+        done = 0
+        spent = 0.0
+        fam_i = 0
+        per_fam_steps = {}
+        while spent < args.cpu_seconds and fam_i < len(fams):
+            f = fams[fam_i]
+            sc = model.OracleScene(d=D, n=N, G=grids[f])
+            sc.init_certificates(trajs[f].frames[0])
+            t = 1
+            while spent < args.cpu_seconds and t <= min(T, 8):
+                t0 = time.perf_counter()
+                sc.step(trajs[f].frames[t])
+                sc.repair()
+                spent += time.perf_counter() - t0
+                done += 1
+                t += 1
+            per_fam_steps[f] = t - 1
+            fam_i += 1
+        out["cpu_baseline"] = {"value": done * N / spent, "unit": "point-steps/s", "cores": model.threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle step + repair (brute-force certificates of the candidates), "
+                                         f"first steps of each family: {per_fam_steps}, {spent:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -78,7 +78,8 @@ typedef struct {
                              index build exceeds refresh * cell width; <= 0 = 0.25 */
     void    *stream;      /* hipStream_t to order work on; NULL = the null stream */
     uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC */
-    int32_t  block;       /* threads per workgroup for point-parallel kernels; 0 = 256 */
+    int32_t  block;       /* lanes that share one 2-NN query: 16, 32 or 64; 0 = 32 for
+                             d = 3 and 16 for d = 2 */
 } nnc_config;
 
 /* Default grid_g: cell width w = 2/sqrt(N) (d = 2) or (4/N)^(1/3) (d = 3) and
@@ -182,6 +183,29 @@ void nnc_snap_free(nnc_snap *snap);
  * Asynchronous. */
 int nnc_allpairs_top2(const float *pos, int64_t n, int32_t d, const int32_t *qidx, int64_t nq,
                       int32_t *nn, float *d1, float *d2, void *stream);
+
+/* ---- kernel timing ------------------------------------------------------ */
+/* Kernel classes timed by the profiler. */
+#define NNC_K_INGEST  0   /* displacement, eps_t, cell update */
+#define NNC_K_FILTER  1   /* clock, safety filter, ordered compaction */
+#define NNC_K_GRID    2   /* cell-start scan and counting-sort scatter */
+#define NNC_K_QUERY   3   /* 2-NN queries: repair of candidates or rebuild of all */
+#define NNC_K_ENTROPY 4   /* failure histogram entropy */
+#define NNC_K_COUNT   5
+
+typedef struct {
+    double  ms[NNC_K_COUNT];     /* summed kernel durations, milliseconds */
+    int64_t count[NNC_K_COUNT];  /* number of timed launches */
+} nnc_profile;
+
+/* Enable (1) or disable (0) HIP-event timing of every kernel the context
+ * launches, per class.  Events are recorded on the context's stream around each
+ * launch; enabling adds an event pair per launch, so use it for measurement
+ * passes only.  Not for use under stream capture. */
+int nnc_profile_enable(nnc_ctx *ctx, int enable);
+
+/* Synchronise, add up the recorded durations into out, and clear them if reset. */
+int nnc_profile_read(nnc_ctx *ctx, nnc_profile *out, int reset);
 
 /* Human-readable text of an error code. */
 const char *nnc_strerror(int code);

@@ -81,9 +81,15 @@ def lib():
                                     i32p, f64p]
         _lib.orc_pair_sqdist64.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, i64p,
                                            ctypes.c_int64, f64p]
+        _lib.orc_threads.restype = ctypes.c_int
         _lib.orc_pair_sqdist32.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, i64p,
                                            ctypes.c_int64, f32p]
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads used by the brute-force loops."""
+    return int(lib().orc_threads())
 
 
 def _ptr(a: np.ndarray, ctype):

@@ -36,8 +36,11 @@ NNC_CANDIDATES = 1
 EXPORTS = (
     "nnc_create", "nnc_destroy", "nnc_init_certificates", "nnc_step", "nnc_repair", "nnc_rebuild",
     "nnc_oracle_verify", "nnc_frontier_entropy", "nnc_get_state", "nnc_snapshot", "nnc_restore",
-    "nnc_snap_free", "nnc_allpairs_top2", "nnc_strerror",
+    "nnc_snap_free", "nnc_allpairs_top2", "nnc_strerror", "nnc_profile_enable", "nnc_profile_read",
 )
+
+K_INGEST, K_FILTER, K_GRID, K_QUERY, K_ENTROPY = range(5)
+KERNEL_CLASSES = ("ingest", "filter", "grid", "query", "entropy")
 
 
 class NNCError(RuntimeError):
@@ -74,6 +77,10 @@ class Entropy(ctypes.Structure):
                 ("m", ctypes.c_int32), ("C", ctypes.c_int32), ("count", ctypes.c_int32)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("count", ctypes.c_int64 * 5)]
+
+
 _lib = None
 _hip = None
 
@@ -103,6 +110,8 @@ def load():
     lib.nnc_snap_free.argtypes = [P]
     lib.nnc_snap_free.restype = None
     lib.nnc_allpairs_top2.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P, P, P]
+    lib.nnc_profile_enable.argtypes = [P, ctypes.c_int]
+    lib.nnc_profile_read.argtypes = [P, ctypes.POINTER(Profile), ctypes.c_int]
     lib.nnc_strerror.argtypes = [ctypes.c_int]
     lib.nnc_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -140,10 +149,11 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
-def copy_from_device(dst: torch.Tensor, src_ptr: int, nbytes: int) -> torch.Tensor:
-    """Copy nbytes of library-owned device memory into a CUDA tensor (stream-ordered)."""
+def copy_from_device(dst: torch.Tensor, src_ptr: int, nbytes: int, stream: int | None = None) -> torch.Tensor:
+    """Copy nbytes of library-owned device memory into a CUDA tensor, ordered on ``stream``."""
     if nbytes:
-        rc = hip().hipMemcpyAsync(dst.data_ptr(), src_ptr, nbytes, 3, _stream())  # 3 = device to device
+        s = _stream() if stream is None else stream
+        rc = hip().hipMemcpyAsync(dst.data_ptr(), src_ptr, nbytes, 3, s)  # 3 = device to device
         if rc != 0:
             raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
     return dst
@@ -236,10 +246,13 @@ class NNCert:
     def frontier_indices(self) -> torch.Tensor:
         """The last step's candidate list as a CUDA int32 tensor (synchronises)."""
         cnt = torch.empty(1, dtype=torch.int32, device="cuda")
-        copy_from_device(cnt, self.frontier.count_dev, 4)
+        copy_from_device(cnt, self.frontier.count_dev, 4, self.stream)
+        torch.cuda.synchronize()
         k = int(cnt.item())
         out = torch.empty(k, dtype=torch.int32, device="cuda")
-        return copy_from_device(out, self.frontier.idx_dev, 4 * k)
+        copy_from_device(out, self.frontier.idx_dev, 4 * k, self.stream)
+        torch.cuda.synchronize()
+        return out
 
     def state(self) -> dict:
         """Copies of the state arrays as CUDA tensors."""
@@ -249,8 +262,18 @@ class NNCert:
         out = {}
         for name, dt, sz in spec:
             t = torch.empty(n, dtype=dt, device="cuda")
-            out[name] = copy_from_device(t, getattr(st, name), n * sz)
+            out[name] = copy_from_device(t, getattr(st, name), n * sz, self.stream)
+        torch.cuda.synchronize()
         return out
+
+    def profile_enable(self, on: bool = True) -> None:
+        check(_lib.nnc_profile_enable(self.h, 1 if on else 0), "nnc_profile_enable")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """Per kernel class: (total ms, launches) of the timed launches (synchronises)."""
+        p = Profile()
+        check(_lib.nnc_profile_read(self.h, ctypes.byref(p), 1 if reset else 0), "nnc_profile_read")
+        return {name: (p.ms[k], p.count[k]) for k, name in enumerate(KERNEL_CLASSES)}
 
     def snapshot(self) -> Snapshot:
         h = ctypes.c_void_p()

@@ -50,10 +50,12 @@ size_t carve(nnc_ctx *c, char *base)
     c->grid.counts = k.take<int>(nc);
     c->grid.cell_start = k.take<int>(nc + 1);
     c->grid.perm = k.take<int>(n);
+    c->grid.rank = k.take<int>(n);
     c->grid.sorted = k.take<float>(n * (size_t)c->d);
     c->hist_fail = k.take<int32_t>(nc);
     c->hist_cand = k.take<int32_t>(nc);
     c->state_bytes = k.off;
+    c->sync = k.take<nnc::DevSync>(1);
     c->grid.cursor = k.take<int>(nc);
     c->touched_fail = k.take<int32_t>(n);
     c->touched_cand = k.take<int32_t>(n);
@@ -109,9 +111,38 @@ const float *adopt_positions(nnc_ctx *c, const float *pos)
     return dst;
 }
 
+void prof_fold(nnc_ctx *c)
+{
+    if (c->prof_used == 0) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < c->prof_used; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->prof_ev[2 * k], c->prof_ev[2 * k + 1]) == hipSuccess) {
+            c->prof_ms[c->prof_cls[k]] += (double)ms;
+            c->prof_cnt[c->prof_cls[k]] += 1;
+        }
+    }
+    c->prof_used = 0;
+}
+
+// Run one launcher, bracketed by timing events when profiling is on.
+template <class F>
+int timed(nnc_ctx *c, int cls, F &&launch)
+{
+    if (!c->prof_on) return launch();
+    if (c->prof_used == c->prof_cap) prof_fold(c);
+    const int k = c->prof_used;
+    (void)hipEventRecord(c->prof_ev[2 * k], c->stream);
+    const int rc = launch();
+    (void)hipEventRecord(c->prof_ev[2 * k + 1], c->stream);
+    c->prof_cls[k] = cls;
+    c->prof_used = k + 1;
+    return rc;
+}
+
 int build_grid(nnc_ctx *c)
 {
-    const int rc = nnc::launch_grid_build(c, c->pos_cur);
+    const int rc = timed(c, NNC_K_GRID, [&] { return nnc::launch_grid_build(c, c->pos_cur); });
     c->grid_fresh = 1;
     c->drift_host = 0.0;
     c->steps_since_grid = 0;
@@ -152,7 +183,8 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
     c->n = cfg->n;
     c->G = G;
     c->ncell = (int)cells;
-    c->block = cfg->block > 0 ? cfg->block : 256;
+    c->block = 256;
+    c->lanes = cfg->block == 16 || cfg->block == 32 || cfg->block == 64 ? cfg->block : (cfg->d == 3 ? 32 : 16);
     c->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
     c->K = 1.0 / (4.0 + 4.0 * c->guard);
     c->refresh_w = (cfg->refresh > 0.0 ? cfg->refresh : 0.25) / (double)G;
@@ -172,7 +204,6 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
         delete c;
         return NNC_E_HIP;
     }
-    c->epoch = 0u;
     *out = c;
     return NNC_OK;
 }
@@ -180,7 +211,12 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
 void nnc_destroy(nnc_ctx *c)
 {
     if (!c) return;
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->prof_ev) {
+        for (int k = 0; k < 2 * c->prof_cap; ++k) (void)hipEventDestroy(c->prof_ev[k]);
+        free(c->prof_ev);
+        free(c->prof_cls);
+    }
     (void)hipFree(c->arena);
     delete c;
 }
@@ -196,7 +232,7 @@ int nnc_init_certificates(nnc_ctx *c, const float *pos)
     if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
     int rc = nnc::launch_cells_init(c, c->pos_cur);
     if (rc == NNC_OK) rc = build_grid(c);
-    if (rc == NNC_OK) rc = nnc::launch_query(c, nullptr, nullptr, 1, 1);
+    if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query(c, nullptr, nullptr, 1, 1); });
     c->inited = rc == NNC_OK;
     return rc;
 }
@@ -208,8 +244,8 @@ int nnc_step(nnc_ctx *c, const float *pos_new, float eps_declared, nnc_frontier 
     c->t += 1;
     c->pos_prev = c->pos_cur;
     c->pos_cur = adopt_positions(c, pos_new);
-    int rc = nnc::launch_ingest(c, c->pos_prev, c->pos_cur);
-    if (rc == NNC_OK) rc = nnc::launch_filter(c, eps_declared);
+    int rc = timed(c, NNC_K_INGEST, [&] { return nnc::launch_ingest(c, c->pos_prev, c->pos_cur); });
+    if (rc == NNC_OK) rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_filter(c, eps_declared); });
     if (rc != NNC_OK) return rc;
     c->grid_fresh = 0;
     if (eps_declared >= 0.0f && c->drift_host >= 0.0)
@@ -242,8 +278,10 @@ int nnc_repair(nnc_ctx *c, const nnc_frontier *f)
     const bool refresh = c->drift_host < 0.0 ? c->steps_since_grid >= kRefreshSteps : c->drift_host > c->refresh_w;
     if (refresh) rc = build_grid(c);
     if (rc == NNC_OK)
-        rc = nnc::launch_query(c, f ? f->idx_dev : c->frontier, f ? f->count_dev : &c->sc->nfront, 0, 0);
-    if (rc == NNC_OK) rc = nnc::launch_entropy(c, 0);
+        rc = timed(c, NNC_K_QUERY, [&] {
+            return nnc::launch_query(c, f ? f->idx_dev : c->frontier, f ? f->count_dev : &c->sc->nfront, 0, 0);
+        });
+    if (rc == NNC_OK) rc = timed(c, NNC_K_ENTROPY, [&] { return nnc::launch_entropy(c, 0); });
     c->pending = 0;
     c->steps_since_grid += 1;
     return rc;
@@ -254,8 +292,8 @@ int nnc_rebuild(nnc_ctx *c)
     if (!c) return NNC_E_INVAL;
     if (!c->pending) return NNC_E_STATE;
     int rc = build_grid(c);
-    if (rc == NNC_OK) rc = nnc::launch_query(c, nullptr, nullptr, 1, 0);
-    if (rc == NNC_OK) rc = nnc::launch_entropy(c, 0);
+    if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query(c, nullptr, nullptr, 1, 0); });
+    if (rc == NNC_OK) rc = timed(c, NNC_K_ENTROPY, [&] { return nnc::launch_entropy(c, 0); });
     c->pending = 0;
     return rc;
 }
@@ -366,6 +404,38 @@ void nnc_snap_free(nnc_snap *s)
     if (!s) return;
     (void)hipFree(s->dev);
     delete s;
+}
+
+int nnc_profile_enable(nnc_ctx *c, int enable)
+{
+    if (!c) return NNC_E_INVAL;
+    if (enable && !c->prof_ev) {
+        const int cap = 256;
+        c->prof_ev = (hipEvent_t *)calloc(2 * cap, sizeof(hipEvent_t));
+        c->prof_cls = (int *)calloc(cap, sizeof(int));
+        if (!c->prof_ev || !c->prof_cls) return NNC_E_NOMEM;
+        for (int k = 0; k < 2 * cap; ++k)
+            if (hipEventCreate(&c->prof_ev[k]) != hipSuccess) return NNC_E_HIP;
+        c->prof_cap = cap;
+    }
+    if (!enable) prof_fold(c);
+    c->prof_on = enable ? 1 : 0;
+    return NNC_OK;
+}
+
+int nnc_profile_read(nnc_ctx *c, nnc_profile *out, int reset)
+{
+    if (!c || !out) return NNC_E_INVAL;
+    prof_fold(c);
+    for (int k = 0; k < NNC_K_COUNT; ++k) {
+        out->ms[k] = c->prof_ms[k];
+        out->count[k] = c->prof_cnt[k];
+        if (reset) {
+            c->prof_ms[k] = 0.0;
+            c->prof_cnt[k] = 0;
+        }
+    }
+    return NNC_OK;
 }
 
 int nnc_allpairs_top2(const float *pos, int64_t n, int32_t d, const int32_t *qidx, int64_t nq, int32_t *nn,

@@ -1,20 +1,24 @@
 // Single-scene kernels of the maintenance step (Algorithm 1 with the appendix's
 // clock) and of the O(N) grid rebuild, for gfx950.
 //
-//   k_ingest       eps_t candidates + cell update: squared displacement of every
-//                  point, wave max -> one atomic per wave; new cell id; occupancy
-//                  counts and the occupied-cell count C kept incrementally.
-//   k_filter       clock advance and safety filter S_t >= e_i with an
-//                  order-preserving compaction (wave ballot + mbcnt, a per-tile
-//                  scan in LDS, decoupled look-back across tiles) -> ascending
-//                  candidate list.  Also clears the failure flags.
+//   k_ingest       per point: squared displacement (wave max -> one atomic per
+//                  wave), new cell id, occupancy counts and the occupied-cell
+//                  count C kept incrementally, and the point's current
+//                  coordinates written to its grid slot.
+//   k_filter*      clock advance and safety filter S_t >= e_i with an
+//                  order-preserving compaction into an ascending candidate
+//                  list (wave ballot + mbcnt, a per-tile scan in LDS; across
+//                  tiles a decoupled look-back, or one workgroup for small N).
 //   k_scan_cells   exclusive scan of the occupancy counts -> cell-start table.
-//   k_scatter      counting-sort scatter: grid order (perm) and the coordinates
-//                  in grid order.
-//   k_query        exact 2-NN of each query through the grid: the 3^d block
-//                  around its cell, widened ring by ring until the second
-//                  neighbour is provably enclosed (Corollary 1), then the new
-//                  certificate, expiry key, failure flag and failure histogram.
+//   k_scatter      counting-sort scatter: slot order (perm, rank) and the
+//                  coordinates in slot order.
+//   k_query        exact 2-NN of each query through the grid, one group of L
+//                  lanes per query: the 3^d block's rows are spread over the
+//                  lanes (contiguous slots, coalesced loads), partial top-2s
+//                  are merged by a butterfly, and the search widens ring by
+//                  ring until the second neighbour is provably enclosed
+//                  (Corollary 1); then the new certificate, expiry key,
+//                  failure flag and failure histogram.
 //   k_entropy      normalised entropy (Definition 2) over the touched cells.
 #include <math.h>
 
@@ -28,10 +32,12 @@ namespace {
 constexpr int kB = 256;            // threads per point-parallel workgroup
 constexpr int kRows = 8;           // items per thread in the tile scans
 constexpr int kTile = kB * kRows;  // items per look-back tile
+constexpr int kSmallB = 1024;      // one-workgroup filter: threads
+constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
-constexpr double kFuzz = 0x1p-20;       // cell-boundary rounding allowance (coordinates)
-constexpr double kRel = 0x1p-20;        // relative allowance on drift and distances
+constexpr double kFuzz = 0x1p-20;  // cell-boundary rounding allowance (coordinates)
+constexpr double kRel = 0x1p-20;   // relative allowance on drift and distances
 
 __device__ __forceinline__ unsigned long long pack_status(unsigned epoch, int flag, unsigned v)
 {
@@ -72,7 +78,26 @@ __device__ unsigned lookback(unsigned long long *status, int tile, unsigned agg,
     return excl;
 }
 
-// Exclusive scan of one value per thread over a 256-thread workgroup.
+// Ticket and epoch for a look-back scan.  The holder of the last ticket
+// retires both: by the time its look-back ends every tile has published at
+// least its aggregate, so every tile has read the epoch.
+__device__ __forceinline__ void take_ticket(DevSync *sy, int *s_tile, unsigned *s_epoch)
+{
+    if (threadIdx.x == 0) {
+        *s_tile = (int)atomicAdd(&sy->tile_ctr, 1u);
+        *s_epoch = __hip_atomic_load(&sy->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void retire_ticket(DevSync *sy, unsigned epoch)
+{
+    sy->tile_ctr = 0u;
+    __hip_atomic_store(&sy->epoch, epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive scan of one value per thread over a workgroup of NT threads.
+template <int NT>
 __device__ __forceinline__ int block_excl_scan(int v, int *s_w, int &total)
 {
     const int lane = (int)lane_id(), w = threadIdx.x >> 6;
@@ -86,7 +111,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *s_w, int &total)
     __syncthreads();
     int wbase = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < kB / 64; ++k) {
+    for (int k = 0; k < NT / 64; ++k) {
         const int t = s_w[k];
         wbase += (k < w) ? t : 0;
         tot += t;
@@ -102,73 +127,95 @@ __global__ void k_fill(int *p, int value, size_t count)
         p[i] = value;
 }
 
+// Add a per-lane change of the occupied-cell count with one atomic per wave.
+__device__ __forceinline__ void add_C(DevScalars *sc, int delta)
+{
+    const int w = wave_sum(delta);
+    if (lane_id() == 0 && w != 0) atomicAdd(&sc->C, w);
+}
+
 template <int D>
 __global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos, int n, int G,
                                                    int *__restrict__ cell, int *__restrict__ counts,
                                                    DevScalars *sc)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
-    if (i >= n) return;
-    const float x = pos[i], y = pos[(size_t)n + i], z = D == 3 ? pos[2 * (size_t)n + i] : 0.f;
-    if (!all_finite<D>(x, y, z)) {
-        atomicOr(&sc->err, kErrNonFinite);
-        cell[i] = 0;
-        if (atomicAdd(&counts[0], 1) == 0) atomicAdd(&sc->C, 1);
-        return;
+    int dC = 0;
+    if (i < n) {
+        const float x = pos[i], y = pos[(size_t)n + i], z = D == 3 ? pos[2 * (size_t)n + i] : 0.f;
+        int c = 0;
+        if (all_finite<D>(x, y, z))
+            c = cell_id<D>(x, y, z, G);
+        else
+            atomicOr(&sc->err, kErrNonFinite);
+        cell[i] = c;
+        dC = atomicAdd(&counts[c], 1) == 0;
     }
-    const int c = cell_id<D>(x, y, z, G);
-    cell[i] = c;
-    if (atomicAdd(&counts[c], 1) == 0) atomicAdd(&sc->C, 1);
+    add_C(sc, dC);
 }
 
 template <int D>
 __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, const float *__restrict__ pnew,
                                                int n, int G, int *__restrict__ cell, int *__restrict__ counts,
+                                               const int *__restrict__ rank, float *__restrict__ sorted,
                                                DevScalars *sc, int parity)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
     float s = 0.0f;
+    int dC = 0;
     if (i < n) {
         const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
         const float x0 = pold[i], y0 = pold[n1 + i], z0 = D == 3 ? pold[n2 + i] : 0.f;
         const float x1 = pnew[i], y1 = pnew[n1 + i], z1 = D == 3 ? pnew[n2 + i] : 0.f;
+        const int k = rank[i];
+        sorted[k] = x1;
+        sorted[n1 + k] = y1;
+        if constexpr (D == 3) sorted[n2 + k] = z1;
         if (all_finite<D>(x1, y1, z1) && all_finite<D>(x0, y0, z0)) {
             s = sqdist<D>(x0, y0, z0, x1, y1, z1);
             const int c = cell_id<D>(x1, y1, z1, G);
             const int old = cell[i];
             if (c != old) {
                 cell[i] = c;
-                if (atomicSub(&counts[old], 1) == 1) atomicSub(&sc->C, 1);
-                if (atomicAdd(&counts[c], 1) == 0) atomicAdd(&sc->C, 1);
+                dC -= atomicSub(&counts[old], 1) == 1;
+                dC += atomicAdd(&counts[c], 1) == 0;
             }
         } else {
             atomicOr(&sc->err, kErrNonFinite);
         }
     }
+    add_C(sc, dC);
     s = wave_max(s);
     if (lane_id() == 0 && s > 0.0f) atomicMax(&sc->dmax[parity], __float_as_uint(s));
 }
 
-__global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int n, DevScalars *sc, int parity,
-                                               float eps_decl, int *__restrict__ frontier,
-                                               uint8_t *__restrict__ fail, unsigned long long *status,
-                                               unsigned epoch)
+// Clock advance shared by both filter variants: every workgroup derives S_t
+// from the same two words; one leader publishes it.
+__device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, float eps_decl, bool leader)
 {
-    __shared__ int s_tile;
-    __shared__ int s_cnt[kRows][kB / 64];
-    __shared__ unsigned s_base;
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(&sc->tile_ctr, 1u);
-    __syncthreads();
-    const int tile = s_tile;
     const float eps = sqrtf(__uint_as_float(sc->dmax[parity]));
     const double St = sc->S[parity ^ 1] + (double)eps;
-    if (tile == 0 && threadIdx.x == 0) {
+    if (leader) {
         sc->S[parity] = St;
         sc->eps = (double)eps;
         sc->dmax[parity ^ 1] = 0u;
         if (eps_decl >= 0.0f && (double)eps > (double)eps_decl * (1.0 + 0x1p-16) + 0x1p-20)
             atomicOr(&sc->err, kErrEps);
     }
+    return St;
+}
+
+__global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int n, DevScalars *sc, DevSync *sy,
+                                               int parity, float eps_decl, int *__restrict__ frontier,
+                                               uint8_t *__restrict__ fail, unsigned long long *status)
+{
+    __shared__ int s_tile;
+    __shared__ unsigned s_epoch;
+    __shared__ int s_cnt[kRows][kB / 64];
+    __shared__ unsigned s_base;
+    take_ticket(sy, &s_tile, &s_epoch);
+    const int tile = s_tile;
+    const double St = advance_clock(sc, parity, eps_decl, tile == 0 && threadIdx.x == 0);
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
     const long long base = (long long)tile * kTile;
@@ -193,11 +240,11 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
                 s_cnt[k][v] = run;
                 run += c;
             }
-        const unsigned excl = lookback(status, tile, (unsigned)run, epoch, &sc->err);
+        const unsigned excl = lookback(status, tile, (unsigned)run, s_epoch, &sc->err);
         s_base = excl;
         if (tile == (int)gridDim.x - 1) {
             sc->nfront = (int)(excl + (unsigned)run);
-            sc->tile_ctr = 0u;
+            retire_ticket(sy, s_epoch);
         }
     }
     __syncthreads();
@@ -211,16 +258,70 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
     }
 }
 
+// One workgroup filters and compacts all n <= kSmallB * kSmallRows points: no
+// inter-workgroup communication at all.
+__global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restrict__ e, int n, DevScalars *sc,
+                                                          int parity, float eps_decl, int *__restrict__ frontier,
+                                                          uint8_t *__restrict__ fail)
+{
+    constexpr int NW = kSmallB / 64;
+    constexpr int NC = kSmallRows * NW;                 // (row, wave) counts, index order
+    constexpr int PER = (NC + kSmallB - 1) / kSmallB;   // counts scanned per thread
+    __shared__ int s_cnt[NC];
+    __shared__ int s_w[NW];
+    const double St = advance_clock(sc, parity, eps_decl, threadIdx.x == 0);
+    const int w = threadIdx.x >> 6;
+    const unsigned lane = lane_id();
+    unsigned long long masks[kSmallRows];
+#pragma unroll
+    for (int k = 0; k < kSmallRows; ++k) {
+        const int i = k * kSmallB + threadIdx.x;
+        bool cand = false;
+        if (i < n) {
+            cand = St >= e[i];
+            fail[i] = 0;
+        }
+        masks[k] = __ballot(cand);
+        if (lane == 0) s_cnt[k * NW + w] = __popcll(masks[k]);
+    }
+    __syncthreads();
+    int v[PER];
+    int loc = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x * PER + u;
+        v[u] = idx < NC ? s_cnt[idx] : 0;
+        loc += v[u];
+    }
+    int tot;
+    int ex = block_excl_scan<kSmallB>(loc, s_w, tot);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x * PER + u;
+        if (idx < NC) s_cnt[idx] = ex;
+        ex += v[u];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sc->nfront = tot;
+#pragma unroll
+    for (int k = 0; k < kSmallRows; ++k) {
+        if ((masks[k] >> lane) & 1ull) {
+            const int i = k * kSmallB + threadIdx.x;
+            frontier[s_cnt[k * NW + w] + rank_below(masks[k])] = i;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ counts, int ncell,
                                                    int *__restrict__ cell_start, int *__restrict__ cursor,
-                                                   DevScalars *sc, int parity, unsigned long long *status,
-                                                   unsigned epoch)
+                                                   DevScalars *sc, DevSync *sy, int parity,
+                                                   unsigned long long *status)
 {
     __shared__ int s_tile;
+    __shared__ unsigned s_epoch;
     __shared__ int s_w[kB / 64];
     __shared__ unsigned s_base;
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(&sc->tile_ctr, 1u);
-    __syncthreads();
+    take_ticket(sy, &s_tile, &s_epoch);
     const int tile = s_tile;
     const long long base = (long long)tile * kTile;
     int pref[kRows];
@@ -230,16 +331,16 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
         const long long c = base + (long long)k * kB + threadIdx.x;
         const int v = c < ncell ? counts[c] : 0;
         int tot;
-        const int ex = block_excl_scan(v, s_w, tot);
+        const int ex = block_excl_scan<kB>(v, s_w, tot);
         pref[k] = run + ex;
         run += tot;
     }
     if (threadIdx.x == 0) {
-        const unsigned excl = lookback(status, tile, (unsigned)run, epoch, &sc->err);
+        const unsigned excl = lookback(status, tile, (unsigned)run, s_epoch, &sc->err);
         s_base = excl;
         if (tile == (int)gridDim.x - 1) {
             cell_start[ncell] = (int)(excl + (unsigned)run);
-            sc->tile_ctr = 0u;
+            retire_ticket(sy, s_epoch);
         }
         if (tile == 0) sc->S_grid = sc->S[parity];
     }
@@ -258,13 +359,18 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
 template <int D>
 __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, const int *__restrict__ cell, int n,
                                                 int *__restrict__ cursor, int *__restrict__ perm,
-                                                float *__restrict__ sorted)
+                                                int *__restrict__ rank, float *__restrict__ sorted,
+                                                DevScalars *sc)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
     const int k = atomicAdd(&cursor[cell[i]], 1);
-    if (k >= n) return;  // unreachable while counts match cells
+    if (k >= n) {  // unreachable while the counts match the cells
+        atomicOr(&sc->err, kErrOverflow);
+        return;
+    }
     perm[k] = i;
+    rank[i] = k;
     sorted[k] = pos[i];
     sorted[(size_t)n + k] = pos[(size_t)n + i];
     if constexpr (D == 3) sorted[2 * (size_t)n + k] = pos[2 * (size_t)n + i];
@@ -272,10 +378,10 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
 
 struct QueryArgs {
     const float *pos;          // current coordinates, point order
-    const float *sorted;       // coordinates in grid order (current when fresh)
+    const float *sorted;       // current coordinates, slot order
     const int *cell_start, *perm, *cell;
     const int *list, *count_dev;
-    int n, G, all, init, fresh, t, parity;
+    int n, G, all, init, t, parity;
     int *nn, *stamp, *hist, *touched;
     float *d1, *d2;
     double *e;
@@ -284,31 +390,9 @@ struct QueryArgs {
     double guard, K;
 };
 
-template <int D, bool FRESH>
-__device__ __forceinline__ void visit(const QueryArgs &a, int k0, int k1, float x, float y, float z, int i,
-                                      Top2 &t)
-{
-    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
-    for (int k = k0; k < k1; ++k) {
-        const int j = a.perm[k];
-        float xj, yj, zj = 0.f;
-        if constexpr (FRESH) {
-            xj = a.sorted[k];
-            yj = a.sorted[n1 + k];
-            if constexpr (D == 3) zj = a.sorted[n2 + k];
-        } else {
-            xj = a.pos[j];
-            yj = a.pos[n1 + j];
-            if constexpr (D == 3) zj = a.pos[n2 + j];
-        }
-        const float s = sqdist<D>(x, y, z, xj, yj, zj);
-        if (j != i) t.push(s, j);
-    }
-}
-
-// Lower bound on the distance from (x,y,z) to any point binned outside the
-// box of cells [g-r, g+r]^d (sides at the grid edge are open: no cell lies
-// beyond them).  Returns +inf when the box covers the whole grid.
+// Lower bound on the distance from (x,y,z) to any point whose build-time cell
+// lies outside the box of cells [g-r, g+r]^d; sides at the grid edge are open
+// (no cell lies beyond them).  +inf when the box covers the whole grid.
 template <int D>
 __device__ __forceinline__ double outside_bound(float x, float y, float z, int gx, int gy, int gz, int r, int G)
 {
@@ -324,77 +408,193 @@ __device__ __forceinline__ double outside_bound(float x, float y, float z, int g
     return B;
 }
 
-template <int D, bool FRESH>
-__device__ void search(const QueryArgs &a, float x, float y, float z, int i, double margin, Top2 &t)
+template <int L>
+__device__ __forceinline__ void group_reduce(Top2 &t)
+{
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        const float o1 = __shfl_xor(t.s1, off, L);
+        const float o2 = __shfl_xor(t.s2, off, L);
+        const int on = __shfl_xor(t.nn, off, L);
+        t.merge(o1, o2, on);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void visit_slot(const QueryArgs &a, int k, float x, float y, float z, int i, Top2 &t)
+{
+    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
+    const float xj = a.sorted[k];
+    const float yj = a.sorted[n1 + k];
+    const float zj = D == 3 ? a.sorted[n2 + k] : 0.0f;
+    const int j = a.perm[k];
+    const float s = sqdist<D>(x, y, z, xj, yj, zj);
+    if (j != i) t.push(s, j);
+}
+
+// Cells of the 3^d block around (gx,gy,gz), clipped to the grid: 3^(d-1) rows,
+// each a contiguous run of slots.  Lanes first fetch one row's bounds each,
+// then walk the concatenated slots with stride L.
+template <int D, int L>
+__device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
+                                           int gz, int lane, Top2 &t)
+{
+    constexpr int R = D == 3 ? 9 : 3;
+    static_assert(L >= R, "a group needs one lane per row");
+    const int G = a.G;
+    int rs = 0, rl = 0;
+    if (lane < R) {
+        const int cy = gy + lane % 3 - 1;
+        const int cz = D == 3 ? gz + lane / 3 - 1 : 0;
+        if (cy >= 0 && cy < G && cz >= 0 && cz < (D == 3 ? G : 1)) {
+            const int row = (cz * G + cy) * G;
+            const int xlo = max(gx - 1, 0), xhi = min(gx + 1, G - 1);
+            rs = a.cell_start[row + xlo];
+            rl = a.cell_start[row + xhi + 1] - rs;
+        }
+    }
+    int incl = rl;
+#pragma unroll
+    for (int off = 1; off < R; off <<= 1) {
+        const int v = __shfl_up(incl, off, L);
+        if (lane >= off) incl += v;
+    }
+    const int total = __shfl(incl, R - 1, L);
+    int rstart[R], rpre[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        rstart[r] = __shfl(rs, r, L);
+        rpre[r] = __shfl(incl - rl, r, L);
+    }
+#pragma unroll 2
+    for (int k = lane; k < total; k += L) {
+        int sr = rstart[0], pr = rpre[0];
+#pragma unroll
+        for (int u = 1; u < R; ++u) {
+            const bool in = k >= rpre[u];
+            sr = in ? rstart[u] : sr;
+            pr = in ? rpre[u] : pr;
+        }
+        visit_slot<D>(a, sr + (k - pr), x, y, z, i, t);
+    }
+}
+
+// The cells at Chebyshev distance exactly r >= 2 from (gx,gy,gz), spread over
+// the lanes.  A ring of side m = 2r+1 is enumerated face by face: in d = 3 the
+// two z faces (m*m cells each), then the two y faces of the middle layers
+// (m*(m-2)), then the two x faces of the rest ((m-2)^2); in d = 2 the two y
+// rows (m) and the two x columns (m-2).
+template <int D, int L>
+__device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
+                                          int gz, int r, int lane, Top2 &t)
+{
+    const int G = a.G;
+    const int m = 2 * r + 1, m2 = m - 2;
+    const int total = D == 3 ? 2 * m * m + 2 * m * m2 + 2 * m2 * m2 : 2 * m + 2 * m2;
+    for (int c = lane; c < total; c += L) {
+        int dx, dy, dz = 0;
+        if constexpr (D == 3) {
+            if (c < 2 * m * m) {
+                const int f = c / (m * m), rem = c % (m * m);
+                dz = f ? r : -r;
+                dy = rem / m - r;
+                dx = rem % m - r;
+            } else if (c < 2 * m * m + 2 * m * m2) {
+                const int c2 = c - 2 * m * m;
+                const int f = c2 / (m * m2), rem = c2 % (m * m2);
+                dy = f ? r : -r;
+                dz = rem / m - (r - 1);
+                dx = rem % m - r;
+            } else {
+                const int c3 = c - 2 * m * m - 2 * m * m2;
+                const int f = c3 / (m2 * m2), rem = c3 % (m2 * m2);
+                dx = f ? r : -r;
+                dz = rem / m2 - (r - 1);
+                dy = rem % m2 - (r - 1);
+            }
+        } else {
+            if (c < 2 * m) {
+                dy = c < m ? -r : r;
+                dx = (c % m) - r;
+            } else {
+                const int c2 = c - 2 * m;
+                dx = c2 < m2 ? -r : r;
+                dy = (c2 % m2) - (r - 1);
+            }
+        }
+        const int cx = gx + dx, cy = gy + dy, cz = gz + dz;
+        if (cx < 0 || cx >= G || cy < 0 || cy >= G) continue;
+        if (D == 3 && (cz < 0 || cz >= G)) continue;
+        const int cell = (cz * G + cy) * G + cx;
+        const int k1 = a.cell_start[cell + 1];
+        for (int k = a.cell_start[cell]; k < k1; ++k) visit_slot<D>(a, k, x, y, z, i, t);
+    }
+}
+
+template <int D, int L>
+__device__ void group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, int lane,
+                             Top2 &t)
 {
     const int G = a.G;
     const int gx = cell_axis(x, G), gy = cell_axis(y, G), gz = D == 3 ? cell_axis(z, G) : 0;
+    scan_block<D, L>(a, x, y, z, i, gx, gy, gz, lane, t);
+    group_reduce<L>(t);
     for (int r = 1;; ++r) {
-        const int zlo = D == 3 ? max(gz - r, 0) : 0, zhi = D == 3 ? min(gz + r, G - 1) : 0;
-        const int ylo = max(gy - r, 0), yhi = min(gy + r, G - 1);
-        const int xlo = max(gx - r, 0), xhi = min(gx + r, G - 1);
-        for (int cz = zlo; cz <= zhi; ++cz) {
-            const bool zface = (D == 3) && (cz - gz == r || gz - cz == r);
-            for (int cy = ylo; cy <= yhi; ++cy) {
-                const int row = (cz * G + cy) * G;
-                if (r == 1 || zface || cy - gy == r || gy - cy == r) {
-                    visit<D, FRESH>(a, a.cell_start[row + xlo], a.cell_start[row + xhi + 1], x, y, z, i, t);
-                } else {
-                    if (gx - r >= 0) {
-                        const int c = row + gx - r;
-                        visit<D, FRESH>(a, a.cell_start[c], a.cell_start[c + 1], x, y, z, i, t);
-                    }
-                    if (gx + r <= G - 1) {
-                        const int c = row + gx + r;
-                        visit<D, FRESH>(a, a.cell_start[c], a.cell_start[c + 1], x, y, z, i, t);
-                    }
-                }
-            }
-        }
         const double B = outside_bound<D>(x, y, z, gx, gy, gz, r, G);
         if (__builtin_isinf(B)) break;  // the whole grid has been visited
         const double Be = B - margin;
         if (Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel)) break;
+        // every lane holds the merged result: keep it in lane 0 only, so that the
+        // next merge combines disjoint sets
+        if (lane != 0) t.init();
+        scan_ring<D, L>(a, x, y, z, i, gx, gy, gz, r + 1, lane, t);
+        group_reduce<L>(t);
     }
 }
 
-template <int D, bool FRESH>
+template <int D, int L>
 __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 {
     const int count = a.all ? a.n : min(*a.count_dev, a.n);
     const double St = a.sc->S[a.parity];
-    const double drift = FRESH ? 0.0 : St - a.sc->S_grid;
+    const double drift = St - a.sc->S_grid;
     const double margin = kFuzz + drift * (1.0 + kRel);
     const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
-    for (int q = blockIdx.x * kB + threadIdx.x; q < count; q += gridDim.x * kB) {
-        const int i = a.all ? a.perm[q] : a.list[q];
-        if (i < 0 || i >= a.n) continue;  // caller-supplied lists are checked
+    const int lane = threadIdx.x & (L - 1);
+    constexpr int GPB = kB / L;
+    for (int q = blockIdx.x * GPB + (int)(threadIdx.x / L); q < count; q += gridDim.x * GPB) {
+        int i;
         float x, y, z = 0.f;
-        if (FRESH && a.all) {
+        if (a.all) {
+            i = a.perm[q];
             x = a.sorted[q];
             y = a.sorted[n1 + q];
             if constexpr (D == 3) z = a.sorted[n2 + q];
         } else {
+            i = a.list[q];
+            if (i < 0 || i >= a.n) continue;  // caller-supplied lists are checked
             x = a.pos[i];
             y = a.pos[n1 + i];
             if constexpr (D == 3) z = a.pos[n2 + i];
         }
         Top2 t;
         t.init();
-        search<D, FRESH>(a, x, y, z, i, margin, t);
-        const int old = a.nn[i];
-        const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
-        a.nn[i] = t.nn;
-        a.d1[i] = d1;
-        a.d2[i] = d2;
-        a.e[i] = expiry(St, d1, d2, a.guard, a.K);
-        a.stamp[i] = a.t;
-        const bool f = !a.init && t.nn != old;
-        a.fail[i] = f ? 1 : 0;
-        if (f) {
-            atomicAdd(&a.sc->nfail, 1);
-            const int c = a.cell[i];
-            if (atomicAdd(&a.hist[c], 1) == 0) a.touched[atomicAdd(&a.sc->ntouched, 1)] = c;
+        group_search<D, L>(a, x, y, z, i, margin, lane, t);
+        if (lane == 0) {
+            const int old = a.nn[i];
+            const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
+            a.nn[i] = t.nn;
+            a.d1[i] = d1;
+            a.d2[i] = d2;
+            a.e[i] = expiry(St, d1, d2, a.guard, a.K);
+            a.stamp[i] = a.t;
+            const bool f = !a.init && t.nn != old;
+            a.fail[i] = f ? 1 : 0;
+            if (f) {
+                atomicAdd(&a.sc->nfail, 1);
+                const int c = a.cell[i];
+                if (atomicAdd(&a.hist[c], 1) == 0) a.touched[atomicAdd(&a.sc->ntouched, 1)] = c;
+            }
         }
     }
 }
@@ -492,19 +692,16 @@ __global__ void __launch_bounds__(kB) k_audit_cand(const int *__restrict__ front
 
 inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per); }
 
-inline int grid_cap(long long n)
-{
-    const long long b = (n + kB - 1) / kB;
-    return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
-}
-
 inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP; }
 
-inline unsigned next_epoch(nnc_ctx *c)
+template <int D, int L>
+void launch_query_t(const QueryArgs &a, long long maxq, hipStream_t s)
 {
-    c->epoch = (c->epoch + 1u) & 0x3fffffffu;
-    if (c->epoch == 0u) c->epoch = 1u;
-    return c->epoch;
+    constexpr int GPB = kB / L;
+    long long blocks = (maxq + GPB - 1) / GPB;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL((k_query<D, L>), dim3((unsigned)blocks), dim3(kB), 0, s, a);
 }
 
 }  // namespace
@@ -537,19 +734,24 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
     const int blocks = blocks_for(c->n, kB);
     if (c->d == 2)
         hipLaunchKernelGGL(k_ingest<2>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->cell,
-                           c->grid.counts, c->sc, parity);
+                           c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
     else
         hipLaunchKernelGGL(k_ingest<3>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->cell,
-                           c->grid.counts, c->sc, parity);
+                           c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
     return check();
 }
 
 int launch_filter(nnc_ctx *c, float eps_declared)
 {
     const int parity = (int)(c->t & 1);
-    const int tiles = c->n > 0 ? blocks_for(c->n, kTile) : 1;
-    hipLaunchKernelGGL(k_filter, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc, parity, eps_declared,
-                       c->frontier, c->fail, c->status, next_epoch(c));
+    if (c->n <= (int64_t)kSmallB * kSmallRows) {
+        hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(kSmallB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
+                           eps_declared, c->frontier, c->fail);
+    } else {
+        const int tiles = blocks_for(c->n, kTile);
+        hipLaunchKernelGGL(k_filter, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc, c->sync, parity,
+                           eps_declared, c->frontier, c->fail, c->status);
+    }
     return check();
 }
 
@@ -558,15 +760,15 @@ int launch_grid_build(nnc_ctx *c, const float *pos)
     const int parity = (int)(c->t & 1);
     const int tiles = blocks_for(c->ncell, kTile);
     hipLaunchKernelGGL(k_scan_cells, dim3(tiles), dim3(kB), 0, c->stream, c->grid.counts, c->ncell,
-                       c->grid.cell_start, c->grid.cursor, c->sc, parity, c->status, next_epoch(c));
+                       c->grid.cell_start, c->grid.cursor, c->sc, c->sync, parity, c->status);
     if (c->n > 0) {
         const int blocks = blocks_for(c->n, kB);
         if (c->d == 2)
             hipLaunchKernelGGL(k_scatter<2>, dim3(blocks), dim3(kB), 0, c->stream, pos, c->cell, (int)c->n,
-                               c->grid.cursor, c->grid.perm, c->grid.sorted);
+                               c->grid.cursor, c->grid.perm, c->grid.rank, c->grid.sorted, c->sc);
         else
             hipLaunchKernelGGL(k_scatter<3>, dim3(blocks), dim3(kB), 0, c->stream, pos, c->cell, (int)c->n,
-                               c->grid.cursor, c->grid.perm, c->grid.sorted);
+                               c->grid.cursor, c->grid.perm, c->grid.rank, c->grid.sorted, c->sc);
     }
     return check();
 }
@@ -586,7 +788,6 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
     a.G = c->G;
     a.all = all;
     a.init = init;
-    a.fresh = c->grid_fresh;
     a.t = (int)c->t;
     a.parity = (int)(c->t & 1);
     a.nn = c->nn;
@@ -600,17 +801,15 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
     a.sc = c->sc;
     a.guard = c->guard;
     a.K = c->K;
-    const int blocks = grid_cap(c->n);
+    const long long maxq = c->n;
     if (c->d == 2) {
-        if (c->grid_fresh)
-            hipLaunchKernelGGL((k_query<2, true>), dim3(blocks), dim3(kB), 0, c->stream, a);
-        else
-            hipLaunchKernelGGL((k_query<2, false>), dim3(blocks), dim3(kB), 0, c->stream, a);
+        if (c->lanes == 64) launch_query_t<2, 64>(a, maxq, c->stream);
+        else if (c->lanes == 32) launch_query_t<2, 32>(a, maxq, c->stream);
+        else launch_query_t<2, 16>(a, maxq, c->stream);
     } else {
-        if (c->grid_fresh)
-            hipLaunchKernelGGL((k_query<3, true>), dim3(blocks), dim3(kB), 0, c->stream, a);
-        else
-            hipLaunchKernelGGL((k_query<3, false>), dim3(blocks), dim3(kB), 0, c->stream, a);
+        if (c->lanes == 64) launch_query_t<3, 64>(a, maxq, c->stream);
+        else if (c->lanes == 32) launch_query_t<3, 32>(a, maxq, c->stream);
+        else launch_query_t<3, 16>(a, maxq, c->stream);
     }
     return check();
 }
@@ -626,7 +825,8 @@ int launch_entropy(nnc_ctx *c, int which)
 
 int launch_cand_hist(nnc_ctx *c)
 {
-    hipLaunchKernelGGL(k_cand_hist, dim3(grid_cap(c->n)), dim3(kB), 0, c->stream, c->frontier, c->cell, c->hist_cand,
+    const int blocks = c->n > 0 ? (blocks_for(c->n, kB) < 4096 ? blocks_for(c->n, kB) : 4096) : 1;
+    hipLaunchKernelGGL(k_cand_hist, dim3(blocks), dim3(kB), 0, c->stream, c->frontier, c->cell, c->hist_cand,
                        c->touched_cand, c->sc);
     return check();
 }
@@ -634,9 +834,11 @@ int launch_cand_hist(nnc_ctx *c)
 int launch_audit(nnc_ctx *c)
 {
     if (c->n == 0) return NNC_OK;
-    hipLaunchKernelGGL(k_audit, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, (int)c->n, c->nn, c->d1, c->d2,
-                       c->stamp, (int)c->t, c->fail, c->a_nn, c->a_d1, c->a_d2, c->sc);
-    hipLaunchKernelGGL(k_audit_cand, dim3(grid_cap(c->n)), dim3(kB), 0, c->stream, c->frontier, c->fail, c->sc);
+    const int blocks = blocks_for(c->n, kB);
+    hipLaunchKernelGGL(k_audit, dim3(blocks), dim3(kB), 0, c->stream, (int)c->n, c->nn, c->d1, c->d2, c->stamp,
+                       (int)c->t, c->fail, c->a_nn, c->a_d1, c->a_d2, c->sc);
+    hipLaunchKernelGGL(k_audit_cand, dim3(blocks < 4096 ? blocks : 4096), dim3(kB), 0, c->stream, c->frontier,
+                       c->fail, c->sc);
     return check();
 }
 

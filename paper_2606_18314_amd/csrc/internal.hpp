@@ -25,8 +25,7 @@ struct DevScalars {
     int ntouched;            // cells met by those failures
     int ncand_touched;       // cells met by the candidates (on demand)
     unsigned err;            // kErr* bits
-    unsigned tile_ctr;       // look-back scan ticket
-    int pad;
+    int pad0, pad1;
     // results of the entropy kernel: [0] failures, [1] candidates
     double H[2];
     int m[2];
@@ -36,21 +35,26 @@ struct DevScalars {
     unsigned long long audit[6];
 };
 
+// Ticket counter and epoch of the look-back scans.  Kept outside the state that
+// init clears and snapshots copy: the epoch only ever increases, so tile
+// descriptors left by earlier scans (or earlier graph replays) never match.
+struct DevSync {
+    unsigned epoch;
+    unsigned tile_ctr;
+};
+
+// Loose uniform grid: slots are grouped by the cell each point had when the grid
+// was last built; sorted[] holds the points' CURRENT coordinates in slot order
+// (ingest rewrites them every step through rank[]), and queries widen their
+// search by the motion accumulated since the build.
 struct Grid {
     int G, ncell;
     int *counts;        // [ncell] occupancy of current cells
-    int *cell_start;    // [ncell+1]
+    int *cell_start;    // [ncell+1] slot ranges of the build-time cells
     int *cursor;        // [ncell] scatter cursors
-    int *perm;          // [n] grid order -> point index
-    float *sorted;      // [d][n] coordinates in grid order at build time
-};
-
-// Query-side description of one scene (single-scene or one scene of a batch).
-struct SceneView {
-    const float *pos;   // current positions [d][n]
-    int n, G;
-    const int *cell_start, *perm;
-    const float *sorted;      // coordinates in grid order (valid when fresh)
+    int *perm;          // [n] slot -> point index
+    int *rank;          // [n] point index -> slot
+    float *sorted;      // [d][n] current coordinates in slot order
 };
 
 }  // namespace nnc
@@ -88,6 +92,7 @@ struct nnc_ctx {
     unsigned long long *status;   // look-back tile descriptors
     int nstatus;
     nnc::DevScalars *sc;
+    nnc::DevSync *sync;
     // audit scratch
     int32_t *a_nn;
     float *a_d1, *a_d2;
@@ -105,8 +110,15 @@ struct nnc_ctx {
     int grid_fresh;               // grid built at the current step (sorted coords current)
     double drift_host;            // accumulated declared eps since the grid build; <0 unknown
     int steps_since_grid;
-    unsigned epoch;
+    int lanes;                    // lanes per query (16, 32 or 64)
     int inited;
+
+    // kernel timing (nnc_profile_enable)
+    int prof_on, prof_cap, prof_used;
+    hipEvent_t *prof_ev;
+    int *prof_cls;
+    double prof_ms[NNC_K_COUNT];
+    int64_t prof_cnt[NNC_K_COUNT];
 };
 
 namespace nnc {
