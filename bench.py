@@ -114,35 +114,61 @@ def main():
     s_ptr = stream.cuda_stream
 
     tuning = {}
+    lanes = {}
     if args.grid == "auto":
         grids = {}
         for f in fams:   # tuned on the first warm-up frames, outside every timed region
-            grids[f], tuning[f] = autotune.tune_grid([frames[f][t] for t in range(min(T, 8) + 1)], D, EPS,
-                                                     steps=min(T, 8))
+            (grids[f], lanes[f]), tuning[f] = autotune.tune_grid(
+                [frames[f][t] for t in range(min(T, 8) + 1)], D, EPS, steps=min(T, 8))
     else:
         grids = {f: int(args.grid) for f in fams}
+        lanes = {f: 0 for f in fams}
 
-    def make_ctxs():
+    # one stream per scene: the five scenes are independent, so their step chains
+    # may run side by side (the graph holds one branch per scene)
+    fstreams = {f: torch.cuda.Stream() for f in fams}
+
+    def make_ctxs(per_scene_streams):
         ctxs = {}
-        with torch.cuda.stream(stream):
-            for f in fams:
-                c = nnc.NNCert(N, D, grid_g=grids[f], stream=s_ptr)
+        for f in fams:
+            st = fstreams[f] if per_scene_streams else stream
+            with torch.cuda.stream(st):
+                c = nnc.NNCert(N, D, grid_g=grids[f], stream=st.cuda_stream, lanes=lanes[f])
                 c.init_certificates(frames[f][0])
-                ctxs[f] = c
+            ctxs[f] = (c, st)
+        torch.cuda.synchronize()
         return ctxs
 
     def run_steps(ctxs, t0, t1, strategy):
         for t in range(t0, t1):
             for f in fams:
-                c = ctxs[f]
-                c.step(frames[f][t], EPS)
-                if strategy == "repair":
-                    c.repair()
-                else:
-                    c.rebuild()
+                c, st = ctxs[f]
+                with torch.cuda.stream(st):
+                    c.step(frames[f][t], EPS)
+                    if strategy == "repair":
+                        c.repair()
+                    else:
+                        c.rebuild()
+
+    def fork(ctxs):
+        for f in fams:
+            ctxs[f][1].wait_stream(stream)
+
+    def join(ctxs):
+        for f in fams:
+            stream.wait_stream(ctxs[f][1])
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
 
     out = {"metric": METRIC, "unit": "point-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -151,110 +177,108 @@ def main():
     legs_req = set(args.legs.split(","))
     pts_per_step = N * len(fams)
 
-    # ---- repair and rebuild: eager, graph, kernel timing -------------------------------
+    # ---- repair and rebuild: graph replays (per-scene streams and one stream), eager,
+    # kernel timing, certification ------------------------------------------------------
     kernel_avg = {}
     audits = {}
     for strategy in ("repair", "rebuild"):
         if strategy not in legs_req:
             continue
-        ctxs = make_ctxs()
-        with torch.cuda.stream(stream):
+        leg = {}
+        for mode in ("streams", "serial"):
+            ctxs = make_ctxs(mode == "streams")
+            fork(ctxs)
             run_steps(ctxs, 1, W + 1, strategy)
-        torch.cuda.synchronize()
-        snaps = {f: ctxs[f].snapshot() for f in fams}
-        # eager timed region
-        e0, e1 = ev(), ev()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        with torch.cuda.stream(stream):
-            run_steps(ctxs, W + 1, T + 1, strategy)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        eager_ms = e0.elapsed_time(e1)
-        # graph: capture the K steps once, replay as the timed region
-        with torch.cuda.stream(stream):
+            join(ctxs)
+            torch.cuda.synchronize()
+            snaps = {f: ctxs[f][0].snapshot() for f in fams}
+            torch.cuda.synchronize()
+
+            def eager():
+                fork(ctxs)
+                run_steps(ctxs, W + 1, T + 1, strategy)
+                join(ctxs)
+            eager_ms = timed(eager)
             for f in fams:
-                ctxs[f].restore(snaps[f])
-        torch.cuda.synchronize()
-        # capture records the K steps without running them: afterwards the device
-        # state is still that of step W while the host side has advanced to step T,
-        # and the replay brings the device to step T as well
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
-            run_steps(ctxs, W + 1, T + 1, strategy)
-        torch.cuda.synchronize()
-        g0, g1 = ev(), ev()
-        g0.record(stream)
-        with torch.cuda.stream(stream):
-            g.replay()
-        g1.record(stream)
-        torch.cuda.synchronize()
-        graph_ms = g0.elapsed_time(g1)
-        # after the replay the state is at step T: audit every scene against all-pairs
-        end_audit = {f: ctxs[f].oracle_verify() for f in fams}
-        # kernel timing pass (eager, HIP events on the library stream)
-        with torch.cuda.stream(stream):
+                ctxs[f][0].restore(snaps[f])
+            torch.cuda.synchronize()
+            # capture records the K steps without running them: afterwards the device
+            # state is still that of step W while the host side has advanced to step T;
+            # the replay brings the device to step T as well
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                fork(ctxs)
+                run_steps(ctxs, W + 1, T + 1, strategy)
+                join(ctxs)
+            torch.cuda.synchronize()
+
+            def replay():
+                with torch.cuda.stream(stream):
+                    g.replay()
+            graph_ms = timed(replay)
+            end_audit = {f: ctxs[f][0].oracle_verify() for f in fams}
+            leg[mode] = {"value": pts_per_step * K / (graph_ms / 1e3), "ms_per_step": graph_ms / K,
+                         "eager_value": pts_per_step * K / (eager_ms / 1e3), "eager_ms_per_step": eager_ms / K,
+                         "end_state_missed": sum(a["n_missed"] for a in end_audit.values()),
+                         "end_state_value_mismatch": sum(a["n_value_mismatch"] for a in end_audit.values())}
+            del g
+            if mode == "serial":
+                # kernel timing pass (eager, HIP events on the library stream)
+                for f in fams:
+                    ctxs[f][0].restore(snaps[f])
+                    ctxs[f][0].profile_enable(True)
+                run_steps(ctxs, W + 1, T + 1, strategy)
+                prof = {}
+                fam_q = {}
+                for f in fams:
+                    for name, (ms, cnt) in ctxs[f][0].profile_read().items():
+                        acc = prof.setdefault(name, [0.0, 0])
+                        acc[0] += ms
+                        acc[1] += cnt
+                        if name == "query" and cnt:
+                            fam_q[f] = round(ms * 1e3 / cnt, 2)
+                    ctxs[f][0].profile_enable(False)
+                kernel_avg[strategy] = {k: (v[0] / v[1] if v[1] else 0.0, v[1]) for k, v in prof.items()}
+                leg["kernels_avg_us"] = {k: round(v[0] * 1e3, 3) for k, v in kernel_avg[strategy].items()}
+                leg["kernel_launches"] = {k: v[1] for k, v in kernel_avg[strategy].items()}
+                leg["query_avg_us_per_family"] = fam_q
+                # certification pass: every step audited by the exact GPU all-pairs oracle
+                cert = None
+                if not args.no_certify:
+                    for f in fams:
+                        ctxs[f][0].restore(snaps[f])
+                    tot = {"steps": 0, "n_missed": 0, "n_value_mismatch": 0, "n_detect": 0, "n_true_fail": 0,
+                           "H_fail_sum": 0.0, "H_cand_sum": 0.0}
+                    for t in range(W + 1, T + 1):
+                        for f in fams:
+                            c, st = ctxs[f]
+                            with torch.cuda.stream(st):
+                                c.step(frames[f][t], EPS)
+                            hc = c.frontier_entropy(nnc.NNC_CANDIDATES)
+                            with torch.cuda.stream(st):
+                                c.repair() if strategy == "repair" else c.rebuild()
+                            hf = c.frontier_entropy(nnc.NNC_FAILED)
+                            a = c.oracle_verify()
+                            tot["steps"] += 1
+                            tot["n_missed"] += a["n_missed"]
+                            tot["n_value_mismatch"] += a["n_value_mismatch"]
+                            tot["n_detect"] += a["n_detect"]
+                            tot["n_true_fail"] += a["n_true_fail"]
+                            tot["H_fail_sum"] += hf["H"]
+                            tot["H_cand_sum"] += hc["H"]
+                    cert = {"scene_steps": tot["steps"], "n_missed": tot["n_missed"],
+                            "n_value_mismatch": tot["n_value_mismatch"],
+                            "candidate_fraction": tot["n_detect"] / (tot["steps"] * N),
+                            "failure_fraction": tot["n_true_fail"] / (tot["steps"] * N),
+                            "mean_H_fail": tot["H_fail_sum"] / tot["steps"],
+                            "mean_H_candidates": tot["H_cand_sum"] / tot["steps"]}
+                audits[strategy] = cert
+                leg["certification"] = cert
             for f in fams:
-                ctxs[f].restore(snaps[f])
-                ctxs[f].profile_enable(True)
-            run_steps(ctxs, W + 1, T + 1, strategy)
-        prof = {}
-        fam_q = {}
-        for f in fams:
-            for name, (ms, cnt) in ctxs[f].profile_read().items():
-                a = prof.setdefault(name, [0.0, 0])
-                a[0] += ms
-                a[1] += cnt
-                if name == "query" and cnt:
-                    fam_q[f] = round(ms * 1e3 / cnt, 2)
-            ctxs[f].profile_enable(False)
-        kernel_avg[strategy] = {k: (v[0] / v[1] if v[1] else 0.0, v[1]) for k, v in prof.items()}
-        # certification pass: every step audited by the exact GPU all-pairs oracle
-        cert = None
-        if not args.no_certify:
-            with torch.cuda.stream(stream):
-                for f in fams:
-                    ctxs[f].restore(snaps[f])
-            tot = {"steps": 0, "n_missed": 0, "n_value_mismatch": 0, "n_detect": 0, "n_true_fail": 0,
-                   "H_fail_sum": 0.0, "H_cand_sum": 0.0}
-            for t in range(W + 1, T + 1):
-                for f in fams:
-                    c = ctxs[f]
-                    with torch.cuda.stream(stream):
-                        c.step(frames[f][t], EPS)
-                    hc = c.frontier_entropy(nnc.NNC_CANDIDATES)
-                    with torch.cuda.stream(stream):
-                        c.repair() if strategy == "repair" else c.rebuild()
-                    hf = c.frontier_entropy(nnc.NNC_FAILED)
-                    a = c.oracle_verify()
-                    tot["steps"] += 1
-                    tot["n_missed"] += a["n_missed"]
-                    tot["n_value_mismatch"] += a["n_value_mismatch"]
-                    tot["n_detect"] += a["n_detect"]
-                    tot["n_true_fail"] += a["n_true_fail"]
-                    tot["H_fail_sum"] += hf["H"]
-                    tot["H_cand_sum"] += hc["H"]
-            cert = {"scene_steps": tot["steps"], "n_missed": tot["n_missed"],
-                    "n_value_mismatch": tot["n_value_mismatch"],
-                    "candidate_fraction": tot["n_detect"] / (tot["steps"] * N),
-                    "failure_fraction": tot["n_true_fail"] / (tot["steps"] * N),
-                    "mean_H_fail": tot["H_fail_sum"] / tot["steps"],
-                    "mean_H_candidates": tot["H_cand_sum"] / tot["steps"]}
-        audits[strategy] = cert
-        legs[strategy] = {
-            "value": pts_per_step * K / (graph_ms / 1e3),
-            "ms_per_step": graph_ms / K,
-            "eager_value": pts_per_step * K / (eager_ms / 1e3),
-            "eager_ms_per_step": eager_ms / K,
-            "end_state_missed": sum(a["n_missed"] for a in end_audit.values()),
-            "kernels_avg_us": {k: round(v[0] * 1e3, 3) for k, v in kernel_avg[strategy].items()},
-            "query_avg_us_per_family": fam_q,
-            "kernel_launches": {k: v[1] for k, v in kernel_avg[strategy].items()},
-            "certification": cert,
-        }
-        for f in fams:
-            ctxs[f].close()
-        del g
+                ctxs[f][0].close()
+        leg["value"] = leg["streams"]["value"]
+        leg["ms_per_step"] = leg["streams"]["ms_per_step"]
+        legs[strategy] = leg
 
     # ---- all-pairs competitor -----------------------------------------------------------
     if "allpairs" in legs_req:
@@ -311,15 +335,16 @@ def main():
                     "bytes_per_launch": per_launch}
         out["roofline"] = roof
     out["config"] = {"workload": "config2: N=16000 points, d=3, five motion families, eps=5e-4, "
-                                 f"{K} timed steps after {W} warm-up steps, HIP-graph replay",
-                     "families": fams, "grid_g": grids, "grid_tuning_ms": tuning, "strategy": "repair",
+                                 f"{K} timed steps after {W} warm-up steps; the five independent scenes "
+                                 "advance on their own streams as branches of one HIP graph",
+                     "families": fams, "grid_g": grids, "lanes_per_query": lanes, "grid_tuning_ms": tuning, "strategy": "repair",
                      "generator_seconds": round(gen_s, 2)}
     out["strategies"] = legs
 
     if "repair" in legs and audits.get("repair"):
         a = audits["repair"]
-        out["certified"] = a["n_missed"] == 0 and a["n_value_mismatch"] == 0 and legs["repair"][
-            "end_state_missed"] == 0
+        out["certified"] = (a["n_missed"] == 0 and a["n_value_mismatch"] == 0 and
+                            all(legs["repair"][m]["end_state_missed"] == 0 for m in ("streams", "serial")))
 
     # ---- counter calibration copy ----------------------------------------------------------
     if args.copy_mib:

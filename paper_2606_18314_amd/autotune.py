@@ -6,8 +6,8 @@ from the mean over the box, so the resolution is chosen from the data:
 
 * ``pick_grid``  the smallest G whose occupied cells hold at most ``target``
                  points on average (C from the library's occupancy count);
-* ``tune_grid``  times a few maintenance steps at each candidate G with HIP
-                 events and keeps the fastest.
+* ``tune_grid``  times a few maintenance steps at each candidate G and number of
+                 lanes per query with HIP events and keeps the fastest.
 
 Both run the library's kernels only; results never depend on G (every
 certificate is exact at any resolution), only the time does.
@@ -61,15 +61,17 @@ def pick_grid(pos: torch.Tensor, d: int, target: float = 3.0) -> int:
     return best
 
 
-def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, stream=None) -> tuple[int, dict]:
-    """Fastest G over a short run of step + repair on frames[0..steps]; returns (G, {G: ms/step})."""
+def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(16, 32, 64),
+              stream=None) -> tuple[tuple[int, int], dict]:
+    """Fastest (G, lanes per query) over a short run of step + repair on frames[0..steps];
+    returns ((G, L), {"G/L": ms per step})."""
     n = frames[0].shape[1]
     grids = grids or candidates(n, d)
     s = stream or torch.cuda.Stream()
     times = {}
-    for G in grids:
+    for G, L in [(g, l) for g in grids for l in lanes]:
         with torch.cuda.stream(s):
-            ctx = binding.NNCert(n, d, grid_g=G, stream=s.cuda_stream)
+            ctx = binding.NNCert(n, d, grid_g=G, stream=s.cuda_stream, lanes=L)
             ctx.init_certificates(frames[0])
             ctx.step(frames[1], eps)
             ctx.repair()
@@ -83,7 +85,7 @@ def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, stream=Non
                 ctx.repair()
         e1.record(s)
         torch.cuda.synchronize()
-        times[G] = e0.elapsed_time(e1) / max(1, steps - 1)
+        times[(G, L)] = e0.elapsed_time(e1) / max(1, steps - 1)
         ctx.close()
     best = min(times, key=times.get)
-    return best, times
+    return best, {f"{g}/{l}": round(v, 5) for (g, l), v in times.items()}

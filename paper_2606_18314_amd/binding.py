@@ -186,13 +186,14 @@ class NNCert:
     """One moving point set and its certificates, on the current CUDA stream."""
 
     def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
-                 copy_positions: bool = False, sync: bool = False, stream: int | None = None):
+                 copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0):
         lib = load()
         self.n, self.d = int(n), int(d)
         self.stream = _stream() if stream is None else stream
         cfg = Config(d=self.d, grid_g=int(grid_g), n=self.n, guard=float(guard), refresh=float(refresh),
                      stream=self.stream,
-                     flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0), block=0)
+                     flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0),
+                     block=int(lanes))
         h = ctypes.c_void_p()
         check(lib.nnc_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_create")
         self.h = h.value

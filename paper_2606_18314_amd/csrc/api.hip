@@ -59,6 +59,7 @@ size_t carve(nnc_ctx *c, char *base)
     c->grid.cursor = k.take<int>(nc);
     c->touched_fail = k.take<int32_t>(n);
     c->touched_cand = k.take<int32_t>(n);
+    // one descriptor per look-back tile (2048 items of the filter or of the cell scan)
     const size_t tiles = ((n > nc ? n : nc) + 2047) / 2048 + 1;
     c->nstatus = (int)tiles;
     c->status = k.take<unsigned long long>(tiles);

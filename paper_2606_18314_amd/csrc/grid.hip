@@ -253,7 +253,11 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
     for (int k = 0; k < kRows; ++k) {
         if ((masks[k] >> lane) & 1ull) {
             const long long i = base + (long long)k * kB + threadIdx.x;
-            frontier[b + s_cnt[k][w] + rank_below(masks[k])] = (int)i;
+            const unsigned at = b + s_cnt[k][w] + rank_below(masks[k]);
+            if (at < (unsigned)n)
+                frontier[at] = (int)i;
+            else
+                atomicOr(&sc->err, kErrOverflow);
         }
     }
 }
@@ -272,16 +276,19 @@ __global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restri
     const double St = advance_clock(sc, parity, eps_decl, threadIdx.x == 0);
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
+    // all loads first, so that they are in flight together
+    double ev[kSmallRows];
+#pragma unroll
+    for (int k = 0; k < kSmallRows; ++k) {
+        const int i = k * kSmallB + threadIdx.x;
+        ev[k] = i < n ? e[i] : __builtin_inf();
+    }
     unsigned long long masks[kSmallRows];
 #pragma unroll
     for (int k = 0; k < kSmallRows; ++k) {
         const int i = k * kSmallB + threadIdx.x;
-        bool cand = false;
-        if (i < n) {
-            cand = St >= e[i];
-            fail[i] = 0;
-        }
-        masks[k] = __ballot(cand);
+        if (i < n) fail[i] = 0;
+        masks[k] = __ballot(St >= ev[k]);
         if (lane == 0) s_cnt[k * NW + w] = __popcll(masks[k]);
     }
     __syncthreads();
@@ -307,7 +314,11 @@ __global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restri
     for (int k = 0; k < kSmallRows; ++k) {
         if ((masks[k] >> lane) & 1ull) {
             const int i = k * kSmallB + threadIdx.x;
-            frontier[s_cnt[k * NW + w] + rank_below(masks[k])] = i;
+            const int at = s_cnt[k * NW + w] + rank_below(masks[k]);
+            if (at < n)
+                frontier[at] = i;
+            else
+                atomicOr(&sc->err, kErrOverflow);
         }
     }
 }
@@ -374,6 +385,44 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
     sorted[k] = pos[i];
     sorted[(size_t)n + k] = pos[(size_t)n + i];
     if constexpr (D == 3) sorted[2 * (size_t)n + k] = pos[2 * (size_t)n + i];
+}
+
+// Normalised entropy (Definition 2) of the failures (which = 0) or candidates
+// (which = 1) over the touched cells, computed by one workgroup of NT threads;
+// clears the histogram entries and counters it consumed.
+template <int NT>
+__device__ void entropy_block(int which, int *__restrict__ hist, const int *__restrict__ touched, DevScalars *sc)
+{
+    __shared__ double s_acc[NT / 64];
+    const int m = which == 0 ? sc->ntouched : sc->ncand_touched;
+    const int F = which == 0 ? sc->nfail : sc->nfront;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < m; k += NT) {
+        const int c = touched[k];
+        const int nk = hist[c];
+        hist[c] = 0;
+        acc += (double)nk * log((double)nk);
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_acc[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < NT / 64; ++k) tot += s_acc[k];
+        const int C = sc->C;
+        double H = 0.0;
+        if (F > 0 && C > 1) H = (log((double)F) - tot / (double)F) / log((double)C);
+        sc->H[which] = H;
+        sc->m[which] = m;
+        sc->F[which] = F;
+        sc->Cres[which] = C;
+        if (which == 0) {
+            sc->nfail = 0;
+            sc->ntouched = 0;
+        } else {
+            sc->ncand_touched = 0;
+        }
+    }
 }
 
 struct QueryArgs {
@@ -466,7 +515,7 @@ __device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y,
         rstart[r] = __shfl(rs, r, L);
         rpre[r] = __shfl(incl - rl, r, L);
     }
-#pragma unroll 2
+#pragma unroll 4
     for (int k = lane; k < total; k += L) {
         int sr = rstart[0], pr = rpre[0];
 #pragma unroll
@@ -479,55 +528,96 @@ __device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y,
     }
 }
 
-// The cells at Chebyshev distance exactly r >= 2 from (gx,gy,gz), spread over
-// the lanes.  A ring of side m = 2r+1 is enumerated face by face: in d = 3 the
-// two z faces (m*m cells each), then the two y faces of the middle layers
-// (m*(m-2)), then the two x faces of the rest ((m-2)^2); in d = 2 the two y
-// rows (m) and the two x columns (m-2).
+// One x-contiguous run of the ring of cells at Chebyshev distance exactly r
+// (r >= 2) from (gx,gy,gz): returns false when the run lies outside the grid.
+// With m = 2r+1, in d = 3 the runs are the 2m full rows of the two z faces,
+// the 2(m-2) full rows of the two y faces between them, and the 2(m-2)^2
+// single cells of the two x faces; in d = 2 the two full y rows and the
+// 2(m-2) single cells of the x sides.
+template <int D>
+__device__ __forceinline__ bool ring_run(int u, int r, int gx, int gy, int gz, int G, int &row, int &xlo, int &xhi)
+{
+    const int m = 2 * r + 1, m2 = m - 2;
+    int dy, dz = 0, x0, x1;
+    if constexpr (D == 3) {
+        if (u < 2 * m) {
+            dz = u < m ? -r : r;
+            dy = u % m - r;
+            x0 = -r;
+            x1 = r;
+        } else if (u < 2 * m + 2 * m2) {
+            const int v = u - 2 * m;
+            dy = v < m2 ? -r : r;
+            dz = v % m2 - (r - 1);
+            x0 = -r;
+            x1 = r;
+        } else {
+            const int v = u - 2 * m - 2 * m2;
+            const int f = v / (m2 * m2), rem = v % (m2 * m2);
+            dz = rem / m2 - (r - 1);
+            dy = rem % m2 - (r - 1);
+            x0 = x1 = f ? r : -r;
+        }
+    } else {
+        if (u < 2) {
+            dy = u ? r : -r;
+            x0 = -r;
+            x1 = r;
+        } else {
+            const int v = u - 2;
+            dy = v % m2 - (r - 1);
+            x0 = x1 = v < m2 ? -r : r;
+        }
+    }
+    const int cy = gy + dy, cz = gz + dz;
+    if (cy < 0 || cy >= G || (D == 3 && (cz < 0 || cz >= G))) return false;
+    xlo = max(gx + x0, 0);
+    xhi = min(gx + x1, G - 1);
+    if (xlo > xhi) return false;
+    row = (cz * G + cy) * G;
+    return true;
+}
+
+// Visit every slot of the ring r >= 2.  Runs are taken L at a time: each lane
+// fetches one run's slot range, a group scan concatenates them, and the lanes
+// walk the concatenation with stride L, finding each slot's run by a binary
+// search over the group (all loops are uniform over the group, so every
+// shuffle reads an active lane).
 template <int D, int L>
 __device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
                                           int gz, int r, int lane, Top2 &t)
 {
     const int G = a.G;
-    const int m = 2 * r + 1, m2 = m - 2;
-    const int total = D == 3 ? 2 * m * m + 2 * m * m2 + 2 * m2 * m2 : 2 * m + 2 * m2;
-    for (int c = lane; c < total; c += L) {
-        int dx, dy, dz = 0;
-        if constexpr (D == 3) {
-            if (c < 2 * m * m) {
-                const int f = c / (m * m), rem = c % (m * m);
-                dz = f ? r : -r;
-                dy = rem / m - r;
-                dx = rem % m - r;
-            } else if (c < 2 * m * m + 2 * m * m2) {
-                const int c2 = c - 2 * m * m;
-                const int f = c2 / (m * m2), rem = c2 % (m * m2);
-                dy = f ? r : -r;
-                dz = rem / m - (r - 1);
-                dx = rem % m - r;
-            } else {
-                const int c3 = c - 2 * m * m - 2 * m * m2;
-                const int f = c3 / (m2 * m2), rem = c3 % (m2 * m2);
-                dx = f ? r : -r;
-                dz = rem / m2 - (r - 1);
-                dy = rem % m2 - (r - 1);
-            }
-        } else {
-            if (c < 2 * m) {
-                dy = c < m ? -r : r;
-                dx = (c % m) - r;
-            } else {
-                const int c2 = c - 2 * m;
-                dx = c2 < m2 ? -r : r;
-                dy = (c2 % m2) - (r - 1);
-            }
+    const int m2 = 2 * r - 1;
+    const int nruns = D == 3 ? 2 * (2 * r + 1) + 2 * m2 + 2 * m2 * m2 : 2 + 2 * m2;
+    for (int c0 = 0; c0 < nruns; c0 += L) {
+        const int u = c0 + lane;
+        int rs = 0, rl = 0;
+        int row, xlo, xhi;
+        if (u < nruns && ring_run<D>(u, r, gx, gy, gz, G, row, xlo, xhi)) {
+            rs = a.cell_start[row + xlo];
+            rl = a.cell_start[row + xhi + 1] - rs;
         }
-        const int cx = gx + dx, cy = gy + dy, cz = gz + dz;
-        if (cx < 0 || cx >= G || cy < 0 || cy >= G) continue;
-        if (D == 3 && (cz < 0 || cz >= G)) continue;
-        const int cell = (cz * G + cy) * G + cx;
-        const int k1 = a.cell_start[cell + 1];
-        for (int k = a.cell_start[cell]; k < k1; ++k) visit_slot<D>(a, k, x, y, z, i, t);
+        int incl = rl;
+#pragma unroll
+        for (int off = 1; off < L; off <<= 1) {
+            const int v = __shfl_up(incl, off, L);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, L - 1, L);
+        const int pre = incl - rl;
+        for (int b = 0; b < total; b += L) {
+            const int k = b + lane;
+            const int kk = min(k, total - 1);
+            int lo = 0;
+#pragma unroll
+            for (int step = L / 2; step > 0; step >>= 1) {
+                const int p = __shfl(pre, lo + step, L);
+                if (p <= kk) lo += step;
+            }
+            const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
+            if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
+        }
     }
 }
 
@@ -577,11 +667,11 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
             y = a.pos[n1 + i];
             if constexpr (D == 3) z = a.pos[n2 + i];
         }
+        const int old = lane == 0 ? a.nn[i] : 0;  // fetched early, used at the end
         Top2 t;
         t.init();
         group_search<D, L>(a, x, y, z, i, margin, lane, t);
         if (lane == 0) {
-            const int old = a.nn[i];
             const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
             a.nn[i] = t.nn;
             a.d1[i] = d1;
@@ -602,36 +692,7 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 __global__ void __launch_bounds__(1024) k_entropy(int which, int *__restrict__ hist, const int *__restrict__ touched,
                                                   DevScalars *sc)
 {
-    __shared__ double s_acc[16];
-    const int m = which == 0 ? sc->ntouched : sc->ncand_touched;
-    const int F = which == 0 ? sc->nfail : sc->nfront;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < m; k += 1024) {
-        const int c = touched[k];
-        const int nk = hist[c];
-        hist[c] = 0;
-        acc += (double)nk * log((double)nk);
-    }
-    acc = wave_sum(acc);
-    if (lane_id() == 0) s_acc[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < 16; ++k) tot += s_acc[k];
-        const int C = sc->C;
-        double H = 0.0;
-        if (F > 0 && C > 1) H = (log((double)F) - tot / (double)F) / log((double)C);
-        sc->H[which] = H;
-        sc->m[which] = m;
-        sc->F[which] = F;
-        sc->Cres[which] = C;
-        if (which == 0) {
-            sc->nfail = 0;
-            sc->ntouched = 0;
-        } else {
-            sc->ncand_touched = 0;
-        }
-    }
+    entropy_block<1024>(which, hist, touched, sc);
 }
 
 __global__ void __launch_bounds__(kB) k_cand_hist(const int *__restrict__ frontier, const int *__restrict__ cell,
@@ -744,6 +805,7 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
 int launch_filter(nnc_ctx *c, float eps_declared)
 {
     const int parity = (int)(c->t & 1);
+    if (c->n > (int64_t)kSmallB * kSmallRows && blocks_for(c->n, kTile) > c->nstatus) return NNC_E_INVAL;
     if (c->n <= (int64_t)kSmallB * kSmallRows) {
         hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(kSmallB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
                            eps_declared, c->frontier, c->fail);
@@ -759,6 +821,7 @@ int launch_grid_build(nnc_ctx *c, const float *pos)
 {
     const int parity = (int)(c->t & 1);
     const int tiles = blocks_for(c->ncell, kTile);
+    if (tiles > c->nstatus) return NNC_E_INVAL;
     hipLaunchKernelGGL(k_scan_cells, dim3(tiles), dim3(kB), 0, c->stream, c->grid.counts, c->ncell,
                        c->grid.cell_start, c->grid.cursor, c->sc, c->sync, parity, c->status);
     if (c->n > 0) {

@@ -99,10 +99,10 @@ def test_allpairs_config2_size(nnc):
 
 # --- the state machine ---------------------------------------------------------------
 
-def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1):
+def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0):
     d, n = traj.d, traj.n
     frames = [dev(f) for f in traj.frames]
-    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard)
+    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes)
     assert ctx.grid_g == G
     sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard)
     ctx.init_certificates(frames[0])
@@ -154,6 +154,14 @@ def test_config2_families_reduced(nnc, family):
     run_parity(nnc, tr, G=9, strategy="alternate")
 
 
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("d", [2, 3])
+def test_lanes_per_query_and_fine_grids(nnc, lanes, d):
+    """Every lane-group width, on grids fine enough that most queries widen."""
+    tr = synth.make_trajectory("clustered_drift", 3000, d, 12, 5e-4, 77 + d)
+    run_parity(nnc, tr, G=64 if d == 3 else 200, lanes=lanes, strategy="alternate")
+
+
 @pytest.mark.parametrize("family", synth.FAMILIES)
 def test_config2_families_full_size(nnc, family):
     """N = 16000, d = 3 at the default grid (G = 15), first 6 steps, every array checked."""
@@ -189,6 +197,11 @@ def test_isolated_point_forces_widening(nnc):
         frames.append(q)
     tr = synth.Trajectory("custom", 2, n, -1.0, np.array(frames, dtype=np.float32))
     run_parity(nnc, tr, G=40)
+    for lanes in (16, 64):
+        run_parity(nnc, tr, G=40, lanes=lanes)
+    p3 = np.concatenate([np.array(frames), 0.1 + 0.02 * g.random((6, 1, n))], axis=1)
+    p3[:, 2, -1] = 0.97
+    run_parity(nnc, synth.Trajectory("custom", 3, n, -1.0, p3.astype(np.float32)), G=25, lanes=32)
 
 
 def test_points_outside_the_box_and_one_cell(nnc):
@@ -279,4 +292,72 @@ def test_forced_frontier_list(nnc):
     ctx.repair(dev(forced), dev(np.array([forced.size], np.int32)))
     sc.repair(forced)
     assert_state_equal(ctx.state(), sc, "forced")
+    ctx.close()
+
+
+def test_large_scene_uses_the_multi_tile_path(nnc):
+    """n above the fused single-launch limit: separate ingest and look-back filter."""
+    tr = synth.make_trajectory("uniform_brownian", 40000, 2, 3, 1e-3, 91)
+    run_parity(nnc, tr, G=100, strategy="alternate")
+
+
+def test_graph_replays_match_eager(nnc):
+    """A captured step sequence, replayed several times from the same restored state,
+    gives the eager result every time (the look-back epochs never repeat)."""
+    tr = synth.config2("adversarial_crossing", n=6000, steps=12)
+    frames = [dev(f) for f in tr.frames]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx = nnc.NNCert(6000, 3, grid_g=12, stream=s.cuda_stream)
+        ctx.init_certificates(frames[0])
+        for t in range(1, 4):
+            ctx.step(frames[t], tr.eps)
+            ctx.repair()
+    torch.cuda.synchronize()
+    snap = ctx.snapshot()
+    with torch.cuda.stream(s):
+        for t in range(4, 13):
+            ctx.step(frames[t], tr.eps)
+            ctx.repair() if t % 3 else ctx.rebuild()
+    torch.cuda.synchronize()
+    want = ctx.state()
+    ctx.restore(snap)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for t in range(4, 13):
+            ctx.step(frames[t], tr.eps)
+            ctx.repair() if t % 3 else ctx.rebuild()
+    for _ in range(3):
+        ctx.restore(snap)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        got = ctx.state()
+        for k in want:
+            assert torch.equal(want[k], got[k]), k
+        _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work in between
+    ctx.close()
+
+
+def test_audit_between_steps(nnc):
+    """Every step audited (the all-pairs scratch rewritten) between steps, at a cell
+    count so small that few look-back descriptors are allocated: regression test for
+    descriptor sizing (a step kernel once indexed the descriptors per workgroup)."""
+    tr = synth.config2("uniform_brownian", n=16000, steps=8)
+    frames = [dev(f) for f in tr.frames]
+    ctx = nnc.NNCert(16000, 3, grid_g=15)
+    sc = model.OracleScene(d=3, n=16000, G=15)
+    ctx.init_certificates(frames[0])
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, 9):
+        ctx.step(frames[t], tr.eps)
+        res = sc.step(tr.frames[t])
+        assert np.array_equal(host(ctx.frontier_indices()), res.candidates)
+        ctx.repair()
+        sc.repair()
+        a = ctx.oracle_verify()
+        assert a["n_missed"] == 0 and a["n_value_mismatch"] == 0
+    assert_state_equal(ctx.state(), sc, "end")
     ctx.close()
