@@ -168,12 +168,21 @@ int nnc_oracle_verify(nnc_ctx *ctx, nnc_audit *out);
  * candidates, over the current cells.  Synchronises. */
 int nnc_frontier_entropy(nnc_ctx *ctx, int which, nnc_entropy *out);
 
+/* The six selector features of the pending step (after nnc_step, before
+ * nnc_repair/nnc_rebuild), written to out (device float32 [NNC_FEATURES]):
+ * |F|/N, H of the candidates, ln N, d, cells met by the candidates / G^d, and
+ * eps_t / the median remaining motion budget e_i - S_{t-1} (median from a
+ * power-of-two histogram).  Asynchronous. */
+int nnc_features(nnc_ctx *ctx, float *out);
+
 /* Read-only device views of the state arrays.  Does not synchronise. */
 int nnc_get_state(nnc_ctx *ctx, nnc_state *v);
 
 /* Device-side copy of the whole state (for timing two strategies on one step). */
 int nnc_snapshot(nnc_ctx *ctx, nnc_snap **out);
 int nnc_restore(nnc_ctx *ctx, const nnc_snap *snap);
+/* Overwrite an existing snapshot of this context with the current state (no allocation). */
+int nnc_snapshot_update(nnc_ctx *ctx, nnc_snap *snap);
 void nnc_snap_free(nnc_snap *snap);
 
 /* Standalone exact all-pairs top-2 (the brute-force competitor and ground truth):
@@ -206,6 +215,104 @@ int nnc_profile_enable(nnc_ctx *ctx, int enable);
 
 /* Synchronise, add up the recorded durations into out, and clear them if reset. */
 int nnc_profile_read(nnc_ctx *ctx, nnc_profile *out, int reset);
+
+/* ---- many independent scenes in one step --------------------------------- */
+/* A batch advances S independent scenes of uneven size and dimension together:
+ * every kernel of the step spans all scenes (scene tiles for the per-point
+ * passes, one workgroup per scene for the filter, compaction, features and
+ * strategy decision, one persistent grid-stride launch for the 2-NN queries of
+ * all scenes).  Each scene follows exactly the single-scene semantics above;
+ * the strategy (repair or rebuild) is chosen per scene and per step. */
+typedef struct nnc_batch nnc_batch;
+
+#define NNC_POLICY_REPAIR    0   /* repair the candidates of every scene */
+#define NNC_POLICY_REBUILD   1   /* rebuild every scene */
+#define NNC_POLICY_THRESHOLD 2   /* rebuild a scene iff |F|/N >= tau */
+#define NNC_POLICY_LEARNED   3   /* the selector network decides; without loaded parameters,
+                                    or for a scene whose features are not finite, the
+                                    threshold rule decides */
+
+#define NNC_FEATURES        6      /* per scene-step: |F|/N, H(F), ln N, d, m/G^d, eps/radius */
+#define NNC_SELECTOR_PARAMS 4738   /* 6-64-64-2 network: W1 b1 W2 b2 W3 b3, row-major out x in */
+#define NNC_BATCH_MAX_N     32768  /* points per scene */
+
+typedef struct {
+    int32_t scenes;
+    const int64_t *n;        /* host [scenes]: points per scene, 0 <= n <= NNC_BATCH_MAX_N */
+    const int32_t *d;        /* host [scenes]: 2 or 3 */
+    const int32_t *grid_g;   /* host [scenes]: cells per axis; NULL or entries <= 0 = occupancy rule */
+    int32_t lanes;           /* lanes per query for all scenes: 16, 32 or 64; 0 = 16 */
+    double guard;            /* as in nnc_config */
+    double refresh;          /* as in nnc_config */
+    void *stream;            /* hipStream_t */
+} nnc_batch_config;
+
+typedef struct {
+    double  eps;             /* eps_t of the last step */
+    double  S;               /* clock */
+    double  H_fail;          /* entropy of the failures (Definition 2) */
+    double  H_cand;          /* entropy of the candidates */
+    int32_t n_cand;          /* |candidates| */
+    int32_t n_fail;          /* |failures| */
+    int32_t m_cand;          /* cells met by the candidates */
+    int32_t C;               /* occupied cells */
+    int32_t strategy;        /* 0 repair, 1 rebuild */
+    int32_t err;             /* NNC_OK or a negative code latched for this scene */
+    float   features[NNC_FEATURES];
+} nnc_scene_stats;
+
+/* Create a batch; allocates every buffer.  Scene s's coordinates occupy a
+ * float32 [d_s][n_s] block at offset coord_off[s] of the concatenated position
+ * arrays, and its per-point state the range [point_off[s], point_off[s] + n_s)
+ * of the concatenated state arrays (offsets from nnc_batch_offsets).
+ * Errors: NNC_E_INVAL, NNC_E_NOMEM. */
+int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg);
+void nnc_batch_destroy(nnc_batch *b);
+
+/* Host arrays of scenes+1 entries each (the last entry is the total). */
+int nnc_batch_offsets(const nnc_batch *b, int64_t *point_off, int64_t *coord_off);
+
+/* Certificates of every point of every scene (device, concatenated positions;
+ * borrowed like nnc_init_certificates).  Asynchronous. */
+int nnc_batch_init(nnc_batch *b, const float *pos);
+
+/* One maintenance step of every scene: measure eps_t, advance the clock, update
+ * the cells, filter and compact, compute the features, choose the strategy by
+ * policy, rebuild or refresh grids where needed, run every scene's queries in
+ * one launch, and reduce the failure entropy.  pos_new is borrowed.
+ * Asynchronous; safe to capture in a HIP graph (no allocation, no memset, no
+ * synchronisation). */
+int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau);
+
+/* Load the selector's parameters (device float32 [NNC_SELECTOR_PARAMS]); copied. */
+int nnc_batch_selector_load(nnc_batch *b, const float *params);
+
+/* Per-scene results of the last step (host array [scenes]).  Synchronises. */
+int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out);
+
+/* Device views of the concatenated state arrays (n = total points, d = 0,
+ * grid_g = 0).  Does not synchronise. */
+int nnc_batch_get_state(nnc_batch *b, nnc_state *v);
+
+/* ---- selector network: training and inference kernels ----------------------- */
+/* A 6-64-64-2 ReLU network in FP32 (layout as NNC_SELECTOR_PARAMS above).  All
+ * pointers are device pointers; all calls are asynchronous on stream. */
+
+/* Bytes of workspace nnc_mlp_grad needs for a batch of B samples. */
+size_t nnc_mlp_workspace_bytes(int B);
+
+/* Loss L = (1/B) sum_b w_b * CE(softmax(z_b), y_b) of a batch (X [B][6] float32,
+ * y [B] int32 in {0,1}, w [B] float32) and its gradient grad [NNC_SELECTOR_PARAMS]
+ * (overwritten), loss [1]. */
+int nnc_mlp_grad(const float *params, const float *X, const int32_t *y, const float *w, int B, void *workspace,
+                 float *grad, float *loss, void *stream);
+
+/* One Adam step (step = 1, 2, ...) on params with moments m, v. */
+int nnc_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
+                 float beta2, float eps, void *stream);
+
+/* Logits [B][2] of a batch of feature rows X [B][6]. */
+int nnc_mlp_forward(const float *params, const float *X, int B, float *logits, void *stream);
 
 /* Human-readable text of an error code. */
 const char *nnc_strerror(int code);

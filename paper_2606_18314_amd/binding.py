@@ -37,7 +37,14 @@ EXPORTS = (
     "nnc_create", "nnc_destroy", "nnc_init_certificates", "nnc_step", "nnc_repair", "nnc_rebuild",
     "nnc_oracle_verify", "nnc_frontier_entropy", "nnc_get_state", "nnc_snapshot", "nnc_restore",
     "nnc_snap_free", "nnc_allpairs_top2", "nnc_strerror", "nnc_profile_enable", "nnc_profile_read",
+    "nnc_batch_create", "nnc_batch_destroy", "nnc_batch_offsets", "nnc_batch_init", "nnc_batch_step",
+    "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
+    "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
 )
+
+POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
+NFEATURES = 6
+SELECTOR_PARAMS = 4738
 
 K_INGEST, K_FILTER, K_GRID, K_QUERY, K_ENTROPY = range(5)
 KERNEL_CLASSES = ("ingest", "filter", "grid", "query", "entropy")
@@ -81,6 +88,19 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 5), ("count", ctypes.c_int64 * 5)]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("scenes", ctypes.c_int32), ("n", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("grid_g", ctypes.c_void_p), ("lanes", ctypes.c_int32), ("guard", ctypes.c_double),
+                ("refresh", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class SceneStats(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("S", ctypes.c_double), ("H_fail", ctypes.c_double),
+                ("H_cand", ctypes.c_double), ("n_cand", ctypes.c_int32), ("n_fail", ctypes.c_int32),
+                ("m_cand", ctypes.c_int32), ("C", ctypes.c_int32), ("strategy", ctypes.c_int32),
+                ("err", ctypes.c_int32), ("features", ctypes.c_float * 6)]
+
+
 _lib = None
 _hip = None
 
@@ -107,11 +127,28 @@ def load():
     lib.nnc_get_state.argtypes = [P, ctypes.POINTER(State)]
     lib.nnc_snapshot.argtypes = [P, ctypes.POINTER(P)]
     lib.nnc_restore.argtypes = [P, P]
+    lib.nnc_snapshot_update.argtypes = [P, P]
     lib.nnc_snap_free.argtypes = [P]
     lib.nnc_snap_free.restype = None
     lib.nnc_allpairs_top2.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P, P, P]
     lib.nnc_profile_enable.argtypes = [P, ctypes.c_int]
     lib.nnc_profile_read.argtypes = [P, ctypes.POINTER(Profile), ctypes.c_int]
+    lib.nnc_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(BatchConfig)]
+    lib.nnc_batch_destroy.argtypes = [P]
+    lib.nnc_batch_destroy.restype = None
+    lib.nnc_batch_offsets.argtypes = [P, P, P]
+    lib.nnc_batch_init.argtypes = [P, P]
+    lib.nnc_batch_step.argtypes = [P, P, ctypes.c_int, ctypes.c_float]
+    lib.nnc_batch_selector_load.argtypes = [P, P]
+    lib.nnc_batch_scene_stats.argtypes = [P, P]
+    lib.nnc_batch_get_state.argtypes = [P, ctypes.POINTER(State)]
+    lib.nnc_features.argtypes = [P, P]
+    lib.nnc_mlp_workspace_bytes.argtypes = [ctypes.c_int]
+    lib.nnc_mlp_workspace_bytes.restype = ctypes.c_size_t
+    lib.nnc_mlp_grad.argtypes = [P, P, P, P, ctypes.c_int, P, P, P, P]
+    lib.nnc_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, P]
+    lib.nnc_mlp_forward.argtypes = [P, P, ctypes.c_int, P, P]
     lib.nnc_strerror.argtypes = [ctypes.c_int]
     lib.nnc_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -267,6 +304,13 @@ class NNCert:
         torch.cuda.synchronize()
         return out
 
+    def features(self) -> torch.Tensor:
+        """The six selector features of the pending step (CUDA float32 tensor)."""
+        out = torch.empty(NFEATURES, dtype=torch.float32, device="cuda")
+        check(_lib.nnc_features(self.h, _ptr(out)), "nnc_features")
+        torch.cuda.synchronize()
+        return out
+
     def profile_enable(self, on: bool = True) -> None:
         check(_lib.nnc_profile_enable(self.h, 1 if on else 0), "nnc_profile_enable")
 
@@ -276,10 +320,112 @@ class NNCert:
         check(_lib.nnc_profile_read(self.h, ctypes.byref(p), 1 if reset else 0), "nnc_profile_read")
         return {name: (p.ms[k], p.count[k]) for k, name in enumerate(KERNEL_CLASSES)}
 
-    def snapshot(self) -> Snapshot:
+    def snapshot(self, into: Snapshot | None = None) -> Snapshot:
+        if into is not None:
+            check(_lib.nnc_snapshot_update(self.h, into.handle), "nnc_snapshot_update")
+            return into
         h = ctypes.c_void_p()
         check(_lib.nnc_snapshot(self.h, ctypes.byref(h)), "nnc_snapshot")
         return Snapshot(h.value)
 
     def restore(self, snap: Snapshot) -> None:
         check(_lib.nnc_restore(self.h, snap.handle), "nnc_restore")
+
+
+class NNCBatch:
+    """Many independent scenes advanced together (one launch per kernel for all scenes).
+
+    Positions are one concatenated float32 CUDA tensor: scene s occupies the
+    [d_s, n_s] block starting at ``coord_off[s]``."""
+
+    def __init__(self, ns, ds, grids=None, lanes: int = 0, guard: float = -1.0, refresh: float = 0.0,
+                 stream: int | None = None):
+        import numpy as np
+        lib = load()
+        self.S = len(ns)
+        self._n = np.ascontiguousarray(ns, dtype=np.int64)
+        self._d = np.ascontiguousarray(ds, dtype=np.int32)
+        self._g = None if grids is None else np.ascontiguousarray(grids, dtype=np.int32)
+        self.stream = _stream() if stream is None else stream
+        cfg = BatchConfig(scenes=self.S, n=self._n.ctypes.data, d=self._d.ctypes.data,
+                          grid_g=0 if self._g is None else self._g.ctypes.data, lanes=int(lanes),
+                          guard=float(guard), refresh=float(refresh), stream=self.stream)
+        h = ctypes.c_void_p()
+        check(lib.nnc_batch_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_batch_create")
+        self.h = h.value
+        self.point_off = np.zeros(self.S + 1, np.int64)
+        self.coord_off = np.zeros(self.S + 1, np.int64)
+        check(lib.nnc_batch_offsets(self.h, self.point_off.ctypes.data, self.coord_off.ctypes.data),
+              "nnc_batch_offsets")
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.nnc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def init(self, pos: torch.Tensor) -> None:
+        self._keep = [pos]
+        check(_lib.nnc_batch_init(self.h, _ptr(pos)), "nnc_batch_init")
+
+    def step(self, pos: torch.Tensor, policy: int = POLICY_REPAIR, tau: float = 0.5) -> None:
+        self._keep = (self._keep + [pos])[-2:]
+        check(_lib.nnc_batch_step(self.h, _ptr(pos), int(policy), float(tau)), "nnc_batch_step")
+
+    def selector_load(self, params: torch.Tensor) -> None:
+        if params.numel() != SELECTOR_PARAMS or params.dtype != torch.float32:
+            raise ValueError("selector parameters: float32 tensor of 4738 values")
+        check(_lib.nnc_batch_selector_load(self.h, _ptr(params)), "nnc_batch_selector_load")
+
+    def stats(self) -> list:
+        arr = (SceneStats * self.S)()
+        check(_lib.nnc_batch_scene_stats(self.h, arr), "nnc_batch_scene_stats")
+        out = []
+        for st in arr:
+            d = {k: getattr(st, k) for k, _ in SceneStats._fields_ if k != "features"}
+            d["features"] = list(st.features)
+            out.append(d)
+        return out
+
+    def state(self) -> dict:
+        st = State()
+        check(_lib.nnc_batch_get_state(self.h, ctypes.byref(st)), "nnc_batch_get_state")
+        n = int(st.n)
+        spec = [("nn", torch.int32, 4), ("d1", torch.float32, 4), ("d2", torch.float32, 4),
+                ("e", torch.float64, 8), ("cell", torch.int32, 4), ("fail", torch.uint8, 1)]
+        out = {}
+        for name, dt, sz in spec:
+            t = torch.empty(n, dtype=dt, device="cuda")
+            out[name] = copy_from_device(t, getattr(st, name), n * sz, self.stream)
+        torch.cuda.synchronize()
+        return out
+
+
+# ---- selector network kernels ---------------------------------------------------------
+
+def mlp_grad(params: torch.Tensor, X: torch.Tensor, y: torch.Tensor, w: torch.Tensor,
+             workspace: torch.Tensor | None = None):
+    """(loss, grad) of the weighted cross-entropy on a batch, by the HIP kernels."""
+    B = X.shape[0]
+    nbytes = load().nnc_mlp_workspace_bytes(B)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(1, nbytes // 4), dtype=torch.float32, device=X.device)
+    g = torch.empty(SELECTOR_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    check(_lib.nnc_mlp_grad(_ptr(params), _ptr(X), _ptr(y), _ptr(w), B, _ptr(workspace), _ptr(g), _ptr(loss),
+                            _stream()), "nnc_mlp_grad")
+    return loss, g
+
+
+def mlp_adam(params, m, v, grad, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+    check(_lib.nnc_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr), float(beta1),
+                            float(beta2), float(eps), _stream()), "nnc_mlp_adam")
+
+
+def mlp_forward(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    logits = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+    check(load().nnc_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(logits), _stream()), "nnc_mlp_forward")
+    return logits

@@ -343,6 +343,16 @@ int nnc_frontier_entropy(nnc_ctx *c, int which, nnc_entropy *out)
     return take_error(c, h);
 }
 
+int nnc_features(nnc_ctx *c, float *out)
+{
+    if (!c || !out) return NNC_E_INVAL;
+    if (!c->inited || !c->pending) return NNC_E_STATE;
+    int rc = nnc::launch_cand_hist(c);
+    if (rc == NNC_OK) rc = nnc::launch_entropy(c, 1);
+    if (rc == NNC_OK) rc = nnc::launch_features(c, out);
+    return rc;
+}
+
 int nnc_get_state(nnc_ctx *c, nnc_state *v)
 {
     if (!c || !v) return NNC_E_INVAL;
@@ -382,6 +392,21 @@ int nnc_snapshot(nnc_ctx *c, nnc_snap **out)
     s->pos_cur = c->pos_cur;
     s->pos_prev = c->pos_prev;
     *out = s;
+    return NNC_OK;
+}
+
+int nnc_snapshot_update(nnc_ctx *c, nnc_snap *s)
+{
+    if (!c || !s || s->bytes != c->state_bytes) return NNC_E_INVAL;
+    if (hipMemcpyAsync(s->dev, c->arena, s->bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return NNC_E_HIP;
+    s->t = c->t;
+    s->pending = c->pending;
+    s->grid_fresh = c->grid_fresh;
+    s->drift_host = c->drift_host;
+    s->steps_since_grid = c->steps_since_grid;
+    s->pos_cur = c->pos_cur;
+    s->pos_prev = c->pos_prev;
     return NNC_OK;
 }
 

@@ -1,0 +1,738 @@
+// Batched maintenance step: many independent scenes of uneven size and
+// dimension advanced together, for gfx950.
+//
+// Every kernel spans all scenes:
+//   k_b_ingest   one workgroup per 256-point tile of a scene: displacement,
+//                per-scene maximum (one atomic per wave), cells, occupancy,
+//                current coordinates into the grid slots;
+//   k_b_filter   one 1024-thread workgroup per scene: clock, safety filter,
+//                ordered compaction, candidate-cell histogram and entropy, the
+//                six selector features, and the strategy decision (threshold
+//                rule or the selector network, evaluated by one wave);
+//   k_b_grid     one workgroup per scene that needs a fresh grid (rebuild, or
+//                repair after the motion budget of the loose grid is spent):
+//                cell-start scan and counting-sort scatter; one extra workgroup
+//                turns the per-scene query counts into offsets;
+//   k_b_query    one persistent grid-stride launch over the queries of all
+//                scenes (candidates of repaired scenes, every point of rebuilt
+//                ones), L lanes per query, the same exact search as one scene;
+//   k_b_entropy  one workgroup per scene: failure entropy (Definition 2).
+// No workgroup waits for another: all cross-scene coordination is by kernel
+// order, so the step is safe to capture in a graph.
+#include <math.h>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+#include "kernels_common.hpp"
+
+namespace nnc {
+
+namespace {
+
+using namespace kc;
+
+constexpr int kB = 256;       // point-parallel workgroup
+constexpr int kFB = 1024;     // per-scene workgroup
+constexpr int kFRows = NNC_BATCH_MAX_N / kFB;
+constexpr int kH = 64;        // selector hidden width
+
+}  // namespace
+
+struct SceneDesc {
+    int n, d, G, ncell;
+    long long poff, coff, goff, soff;  // point, coordinate, cell and cell-start offsets
+    double refresh_w;
+};
+
+struct BatchArgs {
+    const SceneDesc *desc;
+    int scenes, parity, t, policy;
+    float tau;
+    int have_params;
+    double guard, K;
+    DevScalars *sc;
+    const float *pos_prev, *pos_cur;
+    float *sorted;
+    int *cell, *counts, *rank, *perm, *cell_start, *cursor;
+    int *nn, *stamp, *frontier, *hist_fail, *touched_fail, *hist_cand, *touched_cand;
+    float *d1, *d2;
+    double *e;
+    uint8_t *fail;
+    const int *tile_scene, *tile_start;
+    int *strategy, *need_grid, *qcount, *qpre;
+    float *features;
+    const float *params;
+};
+
+namespace {
+
+__global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
+{
+    const int s = a.tile_scene[blockIdx.x];
+    const SceneDesc sd = a.desc[s];
+    const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x;
+    int dC = 0;
+    if (i < sd.n) {
+        const float *p = a.pos_cur + sd.coff;
+        const size_t n1 = (size_t)sd.n;
+        const float x = p[i], y = p[n1 + i], z = sd.d == 3 ? p[2 * n1 + i] : 0.f;
+        int c = 0;
+        const bool ok = sd.d == 3 ? all_finite<3>(x, y, z) : all_finite<2>(x, y, z);
+        if (ok)
+            c = sd.d == 3 ? cell_id<3>(x, y, z, sd.G) : cell_id<2>(x, y, z, sd.G);
+        else
+            atomicOr(&a.sc[s].err, kErrNonFinite);
+        a.cell[sd.poff + i] = c;
+        dC = atomicAdd(&a.counts[sd.goff + c], 1) == 0;
+    }
+    add_C(&a.sc[s], dC);
+}
+
+__global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
+{
+    const int s = a.tile_scene[blockIdx.x];
+    const SceneDesc sd = a.desc[s];
+    const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x;
+    float sq = 0.0f;
+    int dC = 0;
+    if (i < sd.n) {
+        const float *po = a.pos_prev + sd.coff, *pn = a.pos_cur + sd.coff;
+        const size_t n1 = (size_t)sd.n, n2 = 2 * (size_t)sd.n;
+        const bool d3 = sd.d == 3;
+        const float x0 = po[i], y0 = po[n1 + i], z0 = d3 ? po[n2 + i] : 0.f;
+        const float x1 = pn[i], y1 = pn[n1 + i], z1 = d3 ? pn[n2 + i] : 0.f;
+        const int k = a.rank[sd.poff + i];
+        float *so = a.sorted + sd.coff;
+        so[k] = x1;
+        so[n1 + k] = y1;
+        if (d3) so[n2 + k] = z1;
+        const bool ok = d3 ? all_finite<3>(x1, y1, z1) && all_finite<3>(x0, y0, z0)
+                           : all_finite<2>(x1, y1, z1) && all_finite<2>(x0, y0, z0);
+        if (ok) {
+            sq = d3 ? sqdist<3>(x0, y0, z0, x1, y1, z1) : sqdist<2>(x0, y0, z0, x1, y1, z1);
+            const int c = d3 ? cell_id<3>(x1, y1, z1, sd.G) : cell_id<2>(x1, y1, z1, sd.G);
+            const int old = a.cell[sd.poff + i];
+            if (c != old) {
+                a.cell[sd.poff + i] = c;
+                dC -= atomicSub(&a.counts[sd.goff + old], 1) == 1;
+                dC += atomicAdd(&a.counts[sd.goff + c], 1) == 0;
+            }
+        } else {
+            atomicOr(&a.sc[s].err, kErrNonFinite);
+        }
+    }
+    add_C(&a.sc[s], dC);
+    sq = wave_max(sq);
+    if (lane_id() == 0 && sq > 0.0f) atomicMax(&a.sc[s].dmax[a.parity], __float_as_uint(sq));
+}
+
+// The selector network on one wave: lane j is hidden unit j of both layers.
+// Returns (to every lane) 1 for rebuild, 0 for repair.
+__device__ int mlp_decide(const float *__restrict__ p, const float *x, float *s_h)
+{
+    const int j = (int)lane_id();
+    const float *W1 = p, *b1 = p + kH * NNC_FEATURES, *W2 = b1 + kH, *b2 = W2 + kH * kH, *W3 = b2 + kH,
+                *b3 = W3 + 2 * kH;
+    float h = b1[j];
+#pragma unroll
+    for (int k = 0; k < NNC_FEATURES; ++k) h += W1[j * NNC_FEATURES + k] * x[k];
+    h = fmaxf(h, 0.0f);
+    s_h[j] = h;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float h2 = b2[j];
+    for (int k = 0; k < kH; ++k) h2 += W2[j * kH + k] * s_h[k];
+    h2 = fmaxf(h2, 0.0f);
+    float o0 = W3[j] * h2, o1 = W3[kH + j] * h2;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        o0 += __shfl_xor(o0, off, 64);
+        o1 += __shfl_xor(o1, off, 64);
+    }
+    o0 += b3[0];
+    o1 += b3[1];
+    return o1 > o0 ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
+{
+    constexpr int NW = kFB / 64;
+    constexpr int NC = kFRows * NW;
+    constexpr int PER = (NC + kFB - 1) / kFB;
+    __shared__ int s_cnt[NC];
+    __shared__ int s_w[NW];
+    __shared__ int s_vh[kVBins];
+    __shared__ int s_m;
+    __shared__ double s_acc[NW];
+    __shared__ float s_x[NNC_FEATURES];
+    __shared__ float s_h[kH];
+    __shared__ int s_dec;
+    const int s = blockIdx.x;
+    const SceneDesc sd = a.desc[s];
+    DevScalars *sc = &a.sc[s];
+    const int n = sd.n;
+    if (threadIdx.x < kVBins) s_vh[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_m = 0;
+    const double Sprev = sc->S[a.parity ^ 1];
+    const float eps = sqrtf(__uint_as_float(sc->dmax[a.parity]));
+    const double St = advance_clock(sc, a.parity, -1.0f, threadIdx.x == 0);
+    double ev[kFRows];
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        const int i = k * kFB + (int)threadIdx.x;
+        ev[k] = i < n ? a.e[sd.poff + i] : __builtin_inf();
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const unsigned lane = lane_id();
+    unsigned long long masks[kFRows];
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        const int i = k * kFB + (int)threadIdx.x;
+        if (i < n) {
+            a.fail[sd.poff + i] = 0;
+            const double r = ev[k] - Sprev;  // remaining motion budget of the certificate
+            if (r > 0.0 && r < __builtin_inf()) atomicAdd(&s_vh[validity_bin(r)], 1);
+        }
+        masks[k] = __ballot(St >= ev[k]);
+        if (lane == 0) s_cnt[k * NW + w] = __popcll(masks[k]);
+    }
+    __syncthreads();
+    int v[PER];
+    int loc = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = (int)threadIdx.x * PER + u;
+        v[u] = idx < NC ? s_cnt[idx] : 0;
+        loc += v[u];
+    }
+    int tot;
+    int ex = block_excl_scan<kFB>(loc, s_w, tot);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = (int)threadIdx.x * PER + u;
+        if (idx < NC) s_cnt[idx] = ex;
+        ex += v[u];
+    }
+    __syncthreads();
+    int *front = a.frontier + sd.poff;
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        if ((masks[k] >> lane) & 1ull) {
+            const int at = s_cnt[k * NW + w] + rank_below(masks[k]);
+            const int i = k * kFB + (int)threadIdx.x;
+            if (at < n) front[at] = i;
+        }
+    }
+    // candidate cells: histogram, touched list, entropy (all within this workgroup)
+    const int *cell = a.cell + sd.poff;
+    int *hist = a.hist_cand + sd.goff;
+    int *touched = a.touched_cand + sd.poff;
+    for (int q = (int)threadIdx.x; q < tot; q += kFB) {
+        const int c = cell[front[q]];
+        if (atomicAdd(&hist[c], 1) == 0) touched[atomicAdd(&s_m, 1)] = c;
+    }
+    __syncthreads();
+    const int m = s_m;
+    double acc = 0.0;
+    for (int k = (int)threadIdx.x; k < m; k += kFB) {
+        const int nk = atomicExch(&hist[touched[k]], 0);
+        acc += (double)nk * log((double)nk);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) s_acc[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < NW; ++k) sum += s_acc[k];
+        const int C = sc->C;
+        double Hc = 0.0;
+        if (tot > 0 && C > 1) Hc = (log((double)tot) - sum / (double)tot) / log((double)C);
+        float f[NNC_FEATURES];
+        scene_features(f, n, sd.d, sd.ncell, tot, Hc, m, eps, validity_median(s_vh));
+        for (int k = 0; k < NNC_FEATURES; ++k) {
+            s_x[k] = f[k];
+            a.features[s * NNC_FEATURES + k] = f[k];
+        }
+        sc->nfront = tot;
+        sc->H[1] = Hc;
+        sc->m[1] = m;
+        sc->F[1] = tot;
+        sc->Cres[1] = C;
+        int dec = 0;
+        if (a.policy == NNC_POLICY_REBUILD) dec = 1;
+        else if (a.policy != NNC_POLICY_REPAIR) dec = f[0] >= a.tau ? 1 : 0;
+        s_dec = dec;
+    }
+    __syncthreads();
+    if (a.policy == NNC_POLICY_LEARNED && a.have_params && threadIdx.x < 64) {
+        bool finite = true;
+        for (int k = 0; k < NNC_FEATURES; ++k) finite = finite && __builtin_isfinite(s_x[k]);
+        if (finite) {
+            const int dec = mlp_decide(a.params, s_x, s_h);
+            if (threadIdx.x == 0) s_dec = dec;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int dec = s_dec;
+        a.strategy[s] = dec;
+        a.need_grid[s] = dec == 1 || (St - sc->S_grid > sd.refresh_w);
+        a.qcount[s] = dec == 1 ? n : tot;
+    }
+}
+
+// Per-scene grid builds (workgroups 0..scenes-1) and the query offsets (last workgroup).
+__global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
+{
+    __shared__ int s_w[kFB / 64];
+    if ((int)blockIdx.x == a.scenes) {
+        int run = 0;
+        for (int base = 0; base < a.scenes; base += kFB) {
+            const int s = base + (int)threadIdx.x;
+            const int v = s < a.scenes ? a.qcount[s] : 0;
+            int tot;
+            const int ex = block_excl_scan<kFB>(v, s_w, tot);
+            if (s < a.scenes) a.qpre[s] = run + ex;
+            run += tot;
+        }
+        if (threadIdx.x == 0) a.qpre[a.scenes] = run;
+        return;
+    }
+    const int s = blockIdx.x;
+    if (!a.need_grid[s]) return;
+    const SceneDesc sd = a.desc[s];
+    int run = 0;
+    for (int base = 0; base < sd.ncell; base += kFB) {
+        const int c = base + (int)threadIdx.x;
+        const int v = c < sd.ncell ? a.counts[sd.goff + c] : 0;
+        int tot;
+        const int ex = block_excl_scan<kFB>(v, s_w, tot);
+        if (c < sd.ncell) {
+            a.cell_start[sd.soff + c] = run + ex;
+            a.cursor[sd.goff + c] = run + ex;
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        a.cell_start[sd.soff + sd.ncell] = run;
+        a.sc[s].S_grid = a.sc[s].S[a.parity];
+    }
+    __syncthreads();
+    const size_t n1 = (size_t)sd.n;
+    const float *p = a.pos_cur + sd.coff;
+    float *so = a.sorted + sd.coff;
+    for (int i = (int)threadIdx.x; i < sd.n; i += kFB) {
+        const int k = atomicAdd(&a.cursor[sd.goff + a.cell[sd.poff + i]], 1);
+        if (k >= sd.n) {
+            atomicOr(&a.sc[s].err, kErrOverflow);
+            continue;
+        }
+        a.perm[sd.poff + k] = i;
+        a.rank[sd.poff + i] = k;
+        so[k] = p[i];
+        so[n1 + k] = p[n1 + i];
+        if (sd.d == 3) so[2 * n1 + k] = p[2 * n1 + i];
+    }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
+{
+    constexpr int GPB = kB / L;
+    const int total = a.qpre[a.scenes];
+    const int lane = threadIdx.x & (L - 1);
+    for (int g = blockIdx.x * GPB + (int)(threadIdx.x / L); g < total; g += gridDim.x * GPB) {
+        // scene of query g: the last s with qpre[s] <= g
+        int lo = 0, hi = a.scenes;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.qpre[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const int s = lo;
+        const SceneDesc sd = a.desc[s];
+        QueryArgs q;
+        q.pos = a.pos_cur + sd.coff;
+        q.sorted = a.sorted + sd.coff;
+        q.cell_start = a.cell_start + sd.soff;
+        q.perm = a.perm + sd.poff;
+        q.cell = a.cell + sd.poff;
+        q.list = a.frontier + sd.poff;
+        q.count_dev = nullptr;
+        q.n = sd.n;
+        q.G = sd.G;
+        q.all = a.strategy[s];
+        q.init = init;
+        q.t = a.t;
+        q.parity = a.parity;
+        q.nn = a.nn + sd.poff;
+        q.stamp = a.stamp + sd.poff;
+        q.hist = a.hist_fail + sd.goff;
+        q.touched = a.touched_fail + sd.poff;
+        q.d1 = a.d1 + sd.poff;
+        q.d2 = a.d2 + sd.poff;
+        q.e = a.e + sd.poff;
+        q.fail = a.fail + sd.poff;
+        q.sc = &a.sc[s];
+        q.guard = a.guard;
+        q.K = a.K;
+        const double St = a.sc[s].S[a.parity];
+        const double margin = query_margin(St, a.sc[s].S_grid);
+        if (sd.d == 3)
+            query_one<3, L>(q, g - a.qpre[s], St, margin, lane);
+        else
+            query_one<2, L>(q, g - a.qpre[s], St, margin, lane);
+    }
+}
+
+__global__ void __launch_bounds__(kB) k_b_entropy(BatchArgs a)
+{
+    const int s = blockIdx.x;
+    const SceneDesc sd = a.desc[s];
+    entropy_block<kB>(0, a.hist_fail + sd.goff, a.touched_fail + sd.poff, &a.sc[s]);
+}
+
+// Init: every scene rebuilds, every grid is built, queries are all points.
+__global__ void k_b_init_flags(BatchArgs a)
+{
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < a.scenes; s += gridDim.x * blockDim.x) {
+        a.strategy[s] = 1;
+        a.need_grid[s] = 1;
+        a.qcount[s] = a.desc[s].n;
+    }
+}
+
+inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP; }
+
+}  // namespace
+
+}  // namespace nnc
+
+// ---- host side -----------------------------------------------------------------------
+
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+struct nnc_batch {
+    int S, lanes;
+    double guard, K;
+    hipStream_t stream;
+    std::vector<nnc::SceneDesc> desc;
+    std::vector<int> tile_scene, tile_start;
+    std::vector<long long> point_off, coord_off;
+    long long P, Q, NC, NS;
+    int ntiles;
+    void *arena;
+    nnc::BatchArgs a;       // device pointers, refreshed per call
+    int64_t t;
+    int inited, have_params;
+    const float *pos_cur, *pos_prev;
+};
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int default_grid_b(int64_t n, int d)
+{
+    if (n <= 0) return 1;
+    const double w = d == 2 ? 2.0 / sqrt((double)n) : cbrt(4.0 / (double)n);
+    const double g = floor(1.0 / w);
+    return g < 1.0 ? 1 : (int)g;
+}
+
+int launch_query_b(nnc_batch *b, int init)
+{
+    const int blocks = 2048;
+    switch (b->lanes) {
+    case 64: hipLaunchKernelGGL(nnc::k_b_query<64>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
+    case 32: hipLaunchKernelGGL(nnc::k_b_query<32>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
+    default: hipLaunchKernelGGL(nnc::k_b_query<16>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
+    }
+    return nnc::check();
+}
+
+}  // namespace
+
+extern "C" {
+
+int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
+{
+    if (!out || !cfg || cfg->scenes <= 0 || !cfg->n || !cfg->d) return NNC_E_INVAL;
+    *out = nullptr;
+    nnc_batch *b = new (std::nothrow) nnc_batch();
+    if (!b) return NNC_E_NOMEM;
+    b->S = cfg->scenes;
+    b->lanes = cfg->lanes == 32 || cfg->lanes == 64 ? cfg->lanes : 16;
+    b->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
+    b->K = 1.0 / (4.0 + 4.0 * b->guard);
+    b->stream = (hipStream_t)cfg->stream;
+    const double refresh = cfg->refresh > 0.0 ? cfg->refresh : 0.25;
+    long long P = 0, Q = 0, NC = 0, NS = 0;
+    b->desc.resize(b->S);
+    b->point_off.resize(b->S + 1);
+    b->coord_off.resize(b->S + 1);
+    for (int s = 0; s < b->S; ++s) {
+        const int64_t n = cfg->n[s];
+        const int d = cfg->d[s];
+        if ((d != 2 && d != 3) || n < 0 || n > NNC_BATCH_MAX_N) {
+            delete b;
+            return NNC_E_INVAL;
+        }
+        const int G = cfg->grid_g && cfg->grid_g[s] > 0 ? cfg->grid_g[s] : default_grid_b(n, d);
+        const double cells = pow((double)G, (double)d);
+        if (cells > (double)(1 << 22)) {
+            delete b;
+            return NNC_E_INVAL;
+        }
+        nnc::SceneDesc &sd = b->desc[s];
+        sd.n = (int)n;
+        sd.d = d;
+        sd.G = G;
+        sd.ncell = (int)cells;
+        sd.poff = P;
+        sd.coff = Q;
+        sd.goff = NC;
+        sd.soff = NS;
+        sd.refresh_w = refresh / (double)G;
+        b->point_off[s] = P;
+        b->coord_off[s] = Q;
+        P += n;
+        Q += n * d;
+        NC += sd.ncell;
+        NS += sd.ncell + 1;
+        for (int64_t i0 = 0; i0 < n; i0 += nnc::kB) {
+            b->tile_scene.push_back(s);
+            b->tile_start.push_back((int)i0);
+        }
+    }
+    if (P >= (1ll << 31) || Q >= (1ll << 31) || NS >= (1ll << 31)) {
+        delete b;
+        return NNC_E_INVAL;
+    }
+    b->point_off[b->S] = P;
+    b->coord_off[b->S] = Q;
+    b->P = P;
+    b->Q = Q;
+    b->NC = NC;
+    b->NS = NS;
+    b->ntiles = (int)b->tile_scene.size();
+    const size_t S = (size_t)b->S, Pp = (size_t)(P > 0 ? P : 1), Qq = (size_t)(Q > 0 ? Q : 1);
+    const size_t T = (size_t)(b->ntiles > 0 ? b->ntiles : 1);
+    size_t bytes = 0;
+    bytes += al(S * sizeof(nnc::SceneDesc)) + al(S * sizeof(nnc::DevScalars));
+    bytes += al(Qq * 4);                                       // sorted
+    bytes += 4 * al(Pp * 4);                                   // cell, rank, perm, nn
+    bytes += 2 * al(Pp * 4) + al(Pp * 8) + al(Pp);             // d1, d2, e, fail
+    bytes += 4 * al(Pp * 4);                                   // stamp, frontier, touched x2
+    bytes += 4 * al((size_t)NC * 4) + al((size_t)NS * 4);      // counts, cursor, hist x2, cell_start
+    bytes += 2 * al(T * 4) + 3 * al(S * 4) + al((S + 1) * 4);  // tiles, strategy/need/qcount, qpre
+    bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4);
+    if (hipMalloc(&b->arena, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return NNC_E_NOMEM;
+    }
+    if (hipMemsetAsync(b->arena, 0, bytes, b->stream) != hipSuccess) {
+        (void)hipFree(b->arena);
+        delete b;
+        return NNC_E_HIP;
+    }
+    char *p = (char *)b->arena;
+    auto take = [&](size_t n) {
+        char *r = p;
+        p += al(n);
+        return r;
+    };
+    nnc::BatchArgs &a = b->a;
+    memset(&a, 0, sizeof(a));
+    a.desc = (const nnc::SceneDesc *)take(S * sizeof(nnc::SceneDesc));
+    a.sc = (nnc::DevScalars *)take(S * sizeof(nnc::DevScalars));
+    a.sorted = (float *)take(Qq * 4);
+    a.cell = (int *)take(Pp * 4);
+    a.rank = (int *)take(Pp * 4);
+    a.perm = (int *)take(Pp * 4);
+    a.nn = (int *)take(Pp * 4);
+    a.d1 = (float *)take(Pp * 4);
+    a.d2 = (float *)take(Pp * 4);
+    a.e = (double *)take(Pp * 8);
+    a.fail = (uint8_t *)take(Pp);
+    a.stamp = (int *)take(Pp * 4);
+    a.frontier = (int *)take(Pp * 4);
+    a.touched_fail = (int *)take(Pp * 4);
+    a.touched_cand = (int *)take(Pp * 4);
+    a.counts = (int *)take((size_t)NC * 4);
+    a.cursor = (int *)take((size_t)NC * 4);
+    a.hist_fail = (int *)take((size_t)NC * 4);
+    a.hist_cand = (int *)take((size_t)NC * 4);
+    a.cell_start = (int *)take((size_t)NS * 4);
+    a.tile_scene = (const int *)take(T * 4);
+    a.tile_start = (const int *)take(T * 4);
+    a.strategy = (int *)take(S * 4);
+    a.need_grid = (int *)take(S * 4);
+    a.qcount = (int *)take(S * 4);
+    a.qpre = (int *)take((S + 1) * 4);
+    a.features = (float *)take(S * NNC_FEATURES * 4);
+    a.params = (const float *)take(NNC_SELECTOR_PARAMS * 4);
+    a.scenes = b->S;
+    a.guard = b->guard;
+    a.K = b->K;
+    int rc = NNC_OK;
+    if (hipMemcpyAsync((void *)a.desc, b->desc.data(), S * sizeof(nnc::SceneDesc), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        (b->ntiles > 0 &&
+         (hipMemcpyAsync((void *)a.tile_scene, b->tile_scene.data(), b->ntiles * 4, hipMemcpyHostToDevice,
+                         b->stream) != hipSuccess ||
+          hipMemcpyAsync((void *)a.tile_start, b->tile_start.data(), b->ntiles * 4, hipMemcpyHostToDevice,
+                         b->stream) != hipSuccess)))
+        rc = NNC_E_HIP;
+    if (rc == NNC_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = NNC_E_HIP;
+    if (rc != NNC_OK) {
+        (void)hipFree(b->arena);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return NNC_OK;
+}
+
+void nnc_batch_destroy(nnc_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(b->arena);
+    delete b;
+}
+
+int nnc_batch_offsets(const nnc_batch *b, int64_t *point_off, int64_t *coord_off)
+{
+    if (!b) return NNC_E_INVAL;
+    for (int s = 0; s <= b->S; ++s) {
+        if (point_off) point_off[s] = b->point_off[s];
+        if (coord_off) coord_off[s] = b->coord_off[s];
+    }
+    return NNC_OK;
+}
+
+int nnc_batch_init(nnc_batch *b, const float *pos)
+{
+    if (!b || (!pos && b->P > 0)) return NNC_E_INVAL;
+    nnc::BatchArgs &a = b->a;
+    // clear the per-scene scalars and the occupancy and histogram arrays
+    if (hipMemsetAsync(a.sc, 0, b->S * sizeof(nnc::DevScalars), b->stream) != hipSuccess ||
+        hipMemsetAsync(a.counts, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
+        hipMemsetAsync(a.hist_fail, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
+        hipMemsetAsync(a.hist_cand, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
+        hipMemsetAsync(a.nn, 0xff, (size_t)(b->P > 0 ? b->P : 1) * 4, b->stream) != hipSuccess)
+        return NNC_E_HIP;
+    b->t = 0;
+    b->pos_cur = pos;
+    b->pos_prev = nullptr;
+    a.pos_cur = pos;
+    a.pos_prev = nullptr;
+    a.parity = 0;
+    a.t = 0;
+    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_cells_init, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_init_flags, dim3((b->S + 255) / 256), dim3(256), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
+    int rc = nnc::check();
+    if (rc == NNC_OK) rc = launch_query_b(b, 1);
+    b->inited = rc == NNC_OK;
+    return rc;
+}
+
+int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
+{
+    if (!b || (!pos_new && b->P > 0)) return NNC_E_INVAL;
+    if (!b->inited) return NNC_E_STATE;
+    if (policy < NNC_POLICY_REPAIR || policy > NNC_POLICY_LEARNED) return NNC_E_INVAL;
+    b->t += 1;
+    b->pos_prev = b->pos_cur;
+    b->pos_cur = pos_new;
+    nnc::BatchArgs &a = b->a;
+    a.pos_prev = b->pos_prev;
+    a.pos_cur = b->pos_cur;
+    a.parity = (int)(b->t & 1);
+    a.t = (int)b->t;
+    a.policy = policy;
+    a.tau = tau;
+    a.have_params = b->have_params;
+    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_ingest, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
+    int rc = nnc::check();
+    if (rc == NNC_OK) rc = launch_query_b(b, 0);
+    if (rc == NNC_OK) {
+        hipLaunchKernelGGL(nnc::k_b_entropy, dim3(b->S), dim3(nnc::kB), 0, b->stream, a);
+        rc = nnc::check();
+    }
+    return rc;
+}
+
+int nnc_batch_selector_load(nnc_batch *b, const float *params)
+{
+    if (!b || !params) return NNC_E_INVAL;
+    if (hipMemcpyAsync((void *)b->a.params, params, NNC_SELECTOR_PARAMS * 4, hipMemcpyDeviceToDevice, b->stream) !=
+        hipSuccess)
+        return NNC_E_HIP;
+    b->have_params = 1;
+    return NNC_OK;
+}
+
+int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)
+{
+    if (!b || !out) return NNC_E_INVAL;
+    std::vector<nnc::DevScalars> sc(b->S);
+    std::vector<int> strat(b->S);
+    std::vector<float> feat((size_t)b->S * NNC_FEATURES);
+    if (hipMemcpyAsync(sc.data(), b->a.sc, b->S * sizeof(nnc::DevScalars), hipMemcpyDeviceToHost, b->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(strat.data(), b->a.strategy, b->S * 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipMemcpyAsync(feat.data(), b->a.features, feat.size() * 4, hipMemcpyDeviceToHost, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return NNC_E_HIP;
+    int rc = NNC_OK;
+    for (int s = 0; s < b->S; ++s) {
+        const nnc::DevScalars &h = sc[s];
+        nnc_scene_stats &o = out[s];
+        o.eps = h.eps;
+        o.S = h.S[b->t & 1];
+        o.H_fail = h.H[0];
+        o.H_cand = h.H[1];
+        o.n_cand = h.F[1];
+        o.n_fail = h.F[0];
+        o.m_cand = h.m[1];
+        o.C = h.C;
+        o.strategy = strat[s];
+        o.err = h.err == 0u ? NNC_OK
+                : (h.err & nnc::kErrNonFinite) ? NNC_E_NONFINITE
+                : (h.err & nnc::kErrEps)       ? NNC_E_EPS
+                                               : NNC_E_DEVICE;
+        if (o.err != NNC_OK && rc == NNC_OK) rc = o.err;
+        for (int k = 0; k < NNC_FEATURES; ++k) o.features[k] = feat[(size_t)s * NNC_FEATURES + k];
+    }
+    return rc;
+}
+
+int nnc_batch_get_state(nnc_batch *b, nnc_state *v)
+{
+    if (!b || !v) return NNC_E_INVAL;
+    v->nn = b->a.nn;
+    v->d1 = b->a.d1;
+    v->d2 = b->a.d2;
+    v->e = b->a.e;
+    v->cell = b->a.cell;
+    v->fail = b->a.fail;
+    v->n = b->P;
+    v->d = 0;
+    v->grid_g = 0;
+    return NNC_OK;
+}
+
+}  // extern "C"

@@ -24,10 +24,13 @@
 
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "kernels_common.hpp"
 
 namespace nnc {
 
 namespace {
+
+using namespace kc;
 
 constexpr int kB = 256;            // threads per point-parallel workgroup
 constexpr int kRows = 8;           // items per thread in the tile scans
@@ -36,8 +39,6 @@ constexpr int kSmallB = 1024;      // one-workgroup filter: threads
 constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
-constexpr double kFuzz = 0x1p-20;  // cell-boundary rounding allowance (coordinates)
-constexpr double kRel = 0x1p-20;   // relative allowance on drift and distances
 
 __device__ __forceinline__ unsigned long long pack_status(unsigned epoch, int flag, unsigned v)
 {
@@ -96,42 +97,10 @@ __device__ __forceinline__ void retire_ticket(DevSync *sy, unsigned epoch)
     __hip_atomic_store(&sy->epoch, epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive scan of one value per thread over a workgroup of NT threads.
-template <int NT>
-__device__ __forceinline__ int block_excl_scan(int v, int *s_w, int &total)
-{
-    const int lane = (int)lane_id(), w = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) s_w[w] = x;
-    __syncthreads();
-    int wbase = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < NT / 64; ++k) {
-        const int t = s_w[k];
-        wbase += (k < w) ? t : 0;
-        tot += t;
-    }
-    __syncthreads();
-    total = tot;
-    return wbase + x - v;
-}
-
 __global__ void k_fill(int *p, int value, size_t count)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = value;
-}
-
-// Add a per-lane change of the occupied-cell count with one atomic per wave.
-__device__ __forceinline__ void add_C(DevScalars *sc, int delta)
-{
-    const int w = wave_sum(delta);
-    if (lane_id() == 0 && w != 0) atomicAdd(&sc->C, w);
 }
 
 template <int D>
@@ -187,22 +156,6 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
     add_C(sc, dC);
     s = wave_max(s);
     if (lane_id() == 0 && s > 0.0f) atomicMax(&sc->dmax[parity], __float_as_uint(s));
-}
-
-// Clock advance shared by both filter variants: every workgroup derives S_t
-// from the same two words; one leader publishes it.
-__device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, float eps_decl, bool leader)
-{
-    const float eps = sqrtf(__uint_as_float(sc->dmax[parity]));
-    const double St = sc->S[parity ^ 1] + (double)eps;
-    if (leader) {
-        sc->S[parity] = St;
-        sc->eps = (double)eps;
-        sc->dmax[parity ^ 1] = 0u;
-        if (eps_decl >= 0.0f && (double)eps > (double)eps_decl * (1.0 + 0x1p-16) + 0x1p-20)
-            atomicOr(&sc->err, kErrEps);
-    }
-    return St;
 }
 
 __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int n, DevScalars *sc, DevSync *sy,
@@ -387,306 +340,16 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
     if constexpr (D == 3) sorted[2 * (size_t)n + k] = pos[2 * (size_t)n + i];
 }
 
-// Normalised entropy (Definition 2) of the failures (which = 0) or candidates
-// (which = 1) over the touched cells, computed by one workgroup of NT threads;
-// clears the histogram entries and counters it consumed.
-template <int NT>
-__device__ void entropy_block(int which, int *__restrict__ hist, const int *__restrict__ touched, DevScalars *sc)
-{
-    __shared__ double s_acc[NT / 64];
-    const int m = which == 0 ? sc->ntouched : sc->ncand_touched;
-    const int F = which == 0 ? sc->nfail : sc->nfront;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < m; k += NT) {
-        const int c = touched[k];
-        const int nk = hist[c];
-        hist[c] = 0;
-        acc += (double)nk * log((double)nk);
-    }
-    acc = wave_sum(acc);
-    if (lane_id() == 0) s_acc[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < NT / 64; ++k) tot += s_acc[k];
-        const int C = sc->C;
-        double H = 0.0;
-        if (F > 0 && C > 1) H = (log((double)F) - tot / (double)F) / log((double)C);
-        sc->H[which] = H;
-        sc->m[which] = m;
-        sc->F[which] = F;
-        sc->Cres[which] = C;
-        if (which == 0) {
-            sc->nfail = 0;
-            sc->ntouched = 0;
-        } else {
-            sc->ncand_touched = 0;
-        }
-    }
-}
-
-struct QueryArgs {
-    const float *pos;          // current coordinates, point order
-    const float *sorted;       // current coordinates, slot order
-    const int *cell_start, *perm, *cell;
-    const int *list, *count_dev;
-    int n, G, all, init, t, parity;
-    int *nn, *stamp, *hist, *touched;
-    float *d1, *d2;
-    double *e;
-    uint8_t *fail;
-    DevScalars *sc;
-    double guard, K;
-};
-
-// Lower bound on the distance from (x,y,z) to any point whose build-time cell
-// lies outside the box of cells [g-r, g+r]^d; sides at the grid edge are open
-// (no cell lies beyond them).  +inf when the box covers the whole grid.
-template <int D>
-__device__ __forceinline__ double outside_bound(float x, float y, float z, int gx, int gy, int gz, int r, int G)
-{
-    double B = __builtin_inf();
-    const double invG = 1.0 / (double)G;
-    const float pc[3] = {x, y, z};
-    const int gc[3] = {gx, gy, gz};
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        if (gc[k] - r > 0) B = fmin(B, (double)pc[k] - (double)(gc[k] - r) * invG);
-        if (gc[k] + r < G - 1) B = fmin(B, (double)(gc[k] + r + 1) * invG - (double)pc[k]);
-    }
-    return B;
-}
-
-template <int L>
-__device__ __forceinline__ void group_reduce(Top2 &t)
-{
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) {
-        const float o1 = __shfl_xor(t.s1, off, L);
-        const float o2 = __shfl_xor(t.s2, off, L);
-        const int on = __shfl_xor(t.nn, off, L);
-        t.merge(o1, o2, on);
-    }
-}
-
-template <int D>
-__device__ __forceinline__ void visit_slot(const QueryArgs &a, int k, float x, float y, float z, int i, Top2 &t)
-{
-    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
-    const float xj = a.sorted[k];
-    const float yj = a.sorted[n1 + k];
-    const float zj = D == 3 ? a.sorted[n2 + k] : 0.0f;
-    const int j = a.perm[k];
-    const float s = sqdist<D>(x, y, z, xj, yj, zj);
-    if (j != i) t.push(s, j);
-}
-
-// Cells of the 3^d block around (gx,gy,gz), clipped to the grid: 3^(d-1) rows,
-// each a contiguous run of slots.  Lanes first fetch one row's bounds each,
-// then walk the concatenated slots with stride L.
-template <int D, int L>
-__device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
-                                           int gz, int lane, Top2 &t)
-{
-    constexpr int R = D == 3 ? 9 : 3;
-    static_assert(L >= R, "a group needs one lane per row");
-    const int G = a.G;
-    int rs = 0, rl = 0;
-    if (lane < R) {
-        const int cy = gy + lane % 3 - 1;
-        const int cz = D == 3 ? gz + lane / 3 - 1 : 0;
-        if (cy >= 0 && cy < G && cz >= 0 && cz < (D == 3 ? G : 1)) {
-            const int row = (cz * G + cy) * G;
-            const int xlo = max(gx - 1, 0), xhi = min(gx + 1, G - 1);
-            rs = a.cell_start[row + xlo];
-            rl = a.cell_start[row + xhi + 1] - rs;
-        }
-    }
-    int incl = rl;
-#pragma unroll
-    for (int off = 1; off < R; off <<= 1) {
-        const int v = __shfl_up(incl, off, L);
-        if (lane >= off) incl += v;
-    }
-    const int total = __shfl(incl, R - 1, L);
-    int rstart[R], rpre[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        rstart[r] = __shfl(rs, r, L);
-        rpre[r] = __shfl(incl - rl, r, L);
-    }
-#pragma unroll 4
-    for (int k = lane; k < total; k += L) {
-        int sr = rstart[0], pr = rpre[0];
-#pragma unroll
-        for (int u = 1; u < R; ++u) {
-            const bool in = k >= rpre[u];
-            sr = in ? rstart[u] : sr;
-            pr = in ? rpre[u] : pr;
-        }
-        visit_slot<D>(a, sr + (k - pr), x, y, z, i, t);
-    }
-}
-
-// One x-contiguous run of the ring of cells at Chebyshev distance exactly r
-// (r >= 2) from (gx,gy,gz): returns false when the run lies outside the grid.
-// With m = 2r+1, in d = 3 the runs are the 2m full rows of the two z faces,
-// the 2(m-2) full rows of the two y faces between them, and the 2(m-2)^2
-// single cells of the two x faces; in d = 2 the two full y rows and the
-// 2(m-2) single cells of the x sides.
-template <int D>
-__device__ __forceinline__ bool ring_run(int u, int r, int gx, int gy, int gz, int G, int &row, int &xlo, int &xhi)
-{
-    const int m = 2 * r + 1, m2 = m - 2;
-    int dy, dz = 0, x0, x1;
-    if constexpr (D == 3) {
-        if (u < 2 * m) {
-            dz = u < m ? -r : r;
-            dy = u % m - r;
-            x0 = -r;
-            x1 = r;
-        } else if (u < 2 * m + 2 * m2) {
-            const int v = u - 2 * m;
-            dy = v < m2 ? -r : r;
-            dz = v % m2 - (r - 1);
-            x0 = -r;
-            x1 = r;
-        } else {
-            const int v = u - 2 * m - 2 * m2;
-            const int f = v / (m2 * m2), rem = v % (m2 * m2);
-            dz = rem / m2 - (r - 1);
-            dy = rem % m2 - (r - 1);
-            x0 = x1 = f ? r : -r;
-        }
-    } else {
-        if (u < 2) {
-            dy = u ? r : -r;
-            x0 = -r;
-            x1 = r;
-        } else {
-            const int v = u - 2;
-            dy = v % m2 - (r - 1);
-            x0 = x1 = v < m2 ? -r : r;
-        }
-    }
-    const int cy = gy + dy, cz = gz + dz;
-    if (cy < 0 || cy >= G || (D == 3 && (cz < 0 || cz >= G))) return false;
-    xlo = max(gx + x0, 0);
-    xhi = min(gx + x1, G - 1);
-    if (xlo > xhi) return false;
-    row = (cz * G + cy) * G;
-    return true;
-}
-
-// Visit every slot of the ring r >= 2.  Runs are taken L at a time: each lane
-// fetches one run's slot range, a group scan concatenates them, and the lanes
-// walk the concatenation with stride L, finding each slot's run by a binary
-// search over the group (all loops are uniform over the group, so every
-// shuffle reads an active lane).
-template <int D, int L>
-__device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
-                                          int gz, int r, int lane, Top2 &t)
-{
-    const int G = a.G;
-    const int m2 = 2 * r - 1;
-    const int nruns = D == 3 ? 2 * (2 * r + 1) + 2 * m2 + 2 * m2 * m2 : 2 + 2 * m2;
-    for (int c0 = 0; c0 < nruns; c0 += L) {
-        const int u = c0 + lane;
-        int rs = 0, rl = 0;
-        int row, xlo, xhi;
-        if (u < nruns && ring_run<D>(u, r, gx, gy, gz, G, row, xlo, xhi)) {
-            rs = a.cell_start[row + xlo];
-            rl = a.cell_start[row + xhi + 1] - rs;
-        }
-        int incl = rl;
-#pragma unroll
-        for (int off = 1; off < L; off <<= 1) {
-            const int v = __shfl_up(incl, off, L);
-            if (lane >= off) incl += v;
-        }
-        const int total = __shfl(incl, L - 1, L);
-        const int pre = incl - rl;
-        for (int b = 0; b < total; b += L) {
-            const int k = b + lane;
-            const int kk = min(k, total - 1);
-            int lo = 0;
-#pragma unroll
-            for (int step = L / 2; step > 0; step >>= 1) {
-                const int p = __shfl(pre, lo + step, L);
-                if (p <= kk) lo += step;
-            }
-            const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
-            if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
-        }
-    }
-}
-
-template <int D, int L>
-__device__ void group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, int lane,
-                             Top2 &t)
-{
-    const int G = a.G;
-    const int gx = cell_axis(x, G), gy = cell_axis(y, G), gz = D == 3 ? cell_axis(z, G) : 0;
-    scan_block<D, L>(a, x, y, z, i, gx, gy, gz, lane, t);
-    group_reduce<L>(t);
-    for (int r = 1;; ++r) {
-        const double B = outside_bound<D>(x, y, z, gx, gy, gz, r, G);
-        if (__builtin_isinf(B)) break;  // the whole grid has been visited
-        const double Be = B - margin;
-        if (Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel)) break;
-        // every lane holds the merged result: keep it in lane 0 only, so that the
-        // next merge combines disjoint sets
-        if (lane != 0) t.init();
-        scan_ring<D, L>(a, x, y, z, i, gx, gy, gz, r + 1, lane, t);
-        group_reduce<L>(t);
-    }
-}
-
 template <int D, int L>
 __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 {
     const int count = a.all ? a.n : min(*a.count_dev, a.n);
     const double St = a.sc->S[a.parity];
-    const double drift = St - a.sc->S_grid;
-    const double margin = kFuzz + drift * (1.0 + kRel);
-    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
+    const double margin = query_margin(St, a.sc->S_grid);
     const int lane = threadIdx.x & (L - 1);
     constexpr int GPB = kB / L;
-    for (int q = blockIdx.x * GPB + (int)(threadIdx.x / L); q < count; q += gridDim.x * GPB) {
-        int i;
-        float x, y, z = 0.f;
-        if (a.all) {
-            i = a.perm[q];
-            x = a.sorted[q];
-            y = a.sorted[n1 + q];
-            if constexpr (D == 3) z = a.sorted[n2 + q];
-        } else {
-            i = a.list[q];
-            if (i < 0 || i >= a.n) continue;  // caller-supplied lists are checked
-            x = a.pos[i];
-            y = a.pos[n1 + i];
-            if constexpr (D == 3) z = a.pos[n2 + i];
-        }
-        const int old = lane == 0 ? a.nn[i] : 0;  // fetched early, used at the end
-        Top2 t;
-        t.init();
-        group_search<D, L>(a, x, y, z, i, margin, lane, t);
-        if (lane == 0) {
-            const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
-            a.nn[i] = t.nn;
-            a.d1[i] = d1;
-            a.d2[i] = d2;
-            a.e[i] = expiry(St, d1, d2, a.guard, a.K);
-            a.stamp[i] = a.t;
-            const bool f = !a.init && t.nn != old;
-            a.fail[i] = f ? 1 : 0;
-            if (f) {
-                atomicAdd(&a.sc->nfail, 1);
-                const int c = a.cell[i];
-                if (atomicAdd(&a.hist[c], 1) == 0) a.touched[atomicAdd(&a.sc->ntouched, 1)] = c;
-            }
-        }
-    }
+    for (int q = blockIdx.x * GPB + (int)(threadIdx.x / L); q < count; q += gridDim.x * GPB)
+        query_one<D, L>(a, q, St, margin, lane);
 }
 
 __global__ void __launch_bounds__(1024) k_entropy(int which, int *__restrict__ hist, const int *__restrict__ touched,
@@ -702,6 +365,27 @@ __global__ void __launch_bounds__(kB) k_cand_hist(const int *__restrict__ fronti
     for (int q = blockIdx.x * kB + threadIdx.x; q < count; q += gridDim.x * kB) {
         const int c = cell[frontier[q]];
         if (atomicAdd(&hist[c], 1) == 0) touched[atomicAdd(&sc->ncand_touched, 1)] = c;
+    }
+}
+
+// Selector features of the pending step (after the candidate entropy kernel).
+__global__ void __launch_bounds__(1024) k_features(const double *__restrict__ e, int n, int d, int ncell,
+                                                   DevScalars *sc, int parity, float *__restrict__ out)
+{
+    __shared__ int s_vh[kVBins];
+    if (threadIdx.x < kVBins) s_vh[threadIdx.x] = 0;
+    __syncthreads();
+    const double Sprev = sc->S[parity ^ 1];
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double r = e[i] - Sprev;
+        if (r > 0.0 && r < __builtin_inf()) atomicAdd(&s_vh[validity_bin(r)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float eps = (float)sc->eps;
+        float f[NNC_FEATURES];
+        scene_features(f, n, d, ncell, sc->nfront, sc->H[1], sc->m[1], eps, validity_median(s_vh));
+        for (int k = 0; k < NNC_FEATURES; ++k) out[k] = f[k];
     }
 }
 
@@ -891,6 +575,13 @@ int launch_cand_hist(nnc_ctx *c)
     const int blocks = c->n > 0 ? (blocks_for(c->n, kB) < 4096 ? blocks_for(c->n, kB) : 4096) : 1;
     hipLaunchKernelGGL(k_cand_hist, dim3(blocks), dim3(kB), 0, c->stream, c->frontier, c->cell, c->hist_cand,
                        c->touched_cand, c->sc);
+    return check();
+}
+
+int launch_features(nnc_ctx *c, float *out)
+{
+    hipLaunchKernelGGL(k_features, dim3(1), dim3(1024), 0, c->stream, c->e, (int)c->n, c->d, c->ncell, c->sc,
+                       (int)(c->t & 1), out);
     return check();
 }
 

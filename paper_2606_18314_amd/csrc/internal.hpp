@@ -132,6 +132,7 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
 int launch_entropy(nnc_ctx *c, int which);
 int launch_cand_hist(nnc_ctx *c);
 int launch_audit(nnc_ctx *c);
+int launch_features(nnc_ctx *c, float *out);
 int launch_fill(void *p, int value, size_t count, hipStream_t s);
 
 // allpairs.hip

@@ -1,0 +1,121 @@
+"""The selector's HIP kernels against the binary64 CPU oracle of the network,
+and the single-scene features against values recomputed from the oracle's state."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp, model
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nnc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_18314_amd as p
+    from paper_2606_18314_amd import binding
+    p.load()
+    return binding
+
+
+def _batch(g, B):
+    X = g.standard_normal((B, 6)).astype(np.float32)
+    y = g.integers(0, 2, B).astype(np.int32)
+    w = (g.random(B) + 0.1).astype(np.float32)
+    return X, y, w
+
+
+def test_forward_matches_oracle(nnc):
+    g = np.random.default_rng(1)
+    p = (mlp.init_params(g) + 0.1 * g.standard_normal(mlp.NPARAMS)).astype(np.float32)
+    X, _, _ = _batch(g, 777)
+    got = nnc.mlp_forward(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda()).cpu().numpy()
+    want, _ = mlp.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.allclose(got, want, rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("B", [1, 100, 1024])
+def test_gradient_and_loss_match_oracle(nnc, B):
+    g = np.random.default_rng(B)
+    p = (mlp.init_params(g) + 0.05 * g.standard_normal(mlp.NPARAMS)).astype(np.float32)
+    X, y, w = _batch(g, B)
+    loss, gr = nnc.mlp_grad(torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(),
+                            torch.from_numpy(w).cuda())
+    want_g = mlp.grad(p.astype(np.float64), X.astype(np.float64), y, w.astype(np.float64))
+    want_l = mlp.loss(p.astype(np.float64), X.astype(np.float64), y, w.astype(np.float64))
+    assert abs(float(loss.item()) - want_l) <= 1e-5 * max(1.0, abs(want_l))
+    got = gr.cpu().numpy()
+    scale = np.max(np.abs(want_g))
+    assert np.max(np.abs(got - want_g)) <= 2e-5 * scale + 1e-7
+
+
+def test_adam_matches_oracle(nnc):
+    g = np.random.default_rng(7)
+    p = g.standard_normal(mlp.NPARAMS).astype(np.float32)
+    m = (0.01 * g.standard_normal(mlp.NPARAMS)).astype(np.float32)
+    v = (0.01 * g.random(mlp.NPARAMS)).astype(np.float32)
+    gr = g.standard_normal(mlp.NPARAMS).astype(np.float32)
+    pd, md, vd = (torch.from_numpy(a.copy()).cuda() for a in (p, m, v))
+    nnc.mlp_adam(pd, md, vd, torch.from_numpy(gr).cuda(), 3, lr=1e-2)
+    wp, wm, wv = mlp.adam(p.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                          gr.astype(np.float64), 3, lr=1e-2)
+    assert np.allclose(pd.cpu().numpy(), wp, rtol=1e-5, atol=1e-6)
+    assert np.allclose(md.cpu().numpy(), wm, rtol=1e-5, atol=1e-7)
+    assert np.allclose(vd.cpu().numpy(), wv, rtol=1e-5, atol=1e-7)
+
+
+def test_training_learns_a_separable_rule(nnc):
+    from paper_2606_18314_amd import selector
+    g = np.random.default_rng(3)
+    X = g.random((8192, 6)).astype(np.float32)
+    t_rep = 1.0 + 2.0 * X[:, 0]
+    t_reb = np.full(8192, 2.0)
+    y, w = selector.labels(t_rep, t_reb)
+    params = selector.train(X, y, w, epochs=25, seed=1)
+    ch = selector.decide(params, X)
+    assert np.mean(ch == y) > 0.95
+    assert selector.regret(ch, t_rep, t_reb) < 0.02
+
+
+def _host_features(sc, res, S_prev):
+    """The six features from the oracle's state (same power-of-two median rule)."""
+    n = sc.n
+    H, m, C, F = sc.frontier_entropy(model.CANDIDATES, res.candidates)
+    r = sc.e - S_prev
+    r = r[(r > 0) & np.isfinite(r)]
+    h = np.zeros(64, int)
+    if r.size:
+        ex = np.frexp(r)[1] - 1          # ilogb
+        np.add.at(h, np.clip(ex + 48, 0, 63), 1)
+    V = h.sum()
+    radius = 0.0
+    if V:
+        b = int(np.searchsorted(np.cumsum(h) * 2 >= V, True))
+        radius = 1.5 * 2.0 ** (b - 48)
+    return np.array([F / n, H, math.log(n), sc.d, m / sc.G ** sc.d,
+                     float(res.eps) / radius if radius > 0 else 0.0])
+
+
+def test_single_scene_features(nnc):
+    import paper_2606_18314_amd as p
+    tr = synth.make_trajectory("clustered_drift", 5000, 3, 5, 5e-4, 9)
+    ctx = p.NNCert(5000, 3, grid_g=12)
+    sc = model.OracleScene(d=3, n=5000, G=12)
+    ctx.init_certificates(torch.from_numpy(tr.frames[0]).cuda())
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, 6):
+        S_prev = sc.S
+        e_prev = sc.e.copy()
+        ctx.step(torch.from_numpy(tr.frames[t]).cuda(), tr.eps)
+        res = sc.step(tr.frames[t])
+        f = ctx.features().cpu().numpy()
+        sc.e = e_prev                      # features use the keys of the pending step
+        want = _host_features(sc, res, S_prev)
+        assert np.allclose(f, want, rtol=1e-5, atol=1e-7), (t, f, want)
+        ctx.repair()
+        sc.repair()
+    ctx.close()
