@@ -50,8 +50,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="repair,rebuild,allpairs")
+    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched")
+    ap.add_argument("--scenes", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--regret-scenes", type=int, default=40)
+    ap.add_argument("--regret-steps", type=int, default=25)
     ap.add_argument("--grid", default="auto", help="'auto' (tuned per family) or an integer G for all")
+    ap.add_argument("--grid-json", default="", help='fixed {"family": [G, lanes], ...} instead of tuning')
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-certify", action="store_true")
@@ -87,6 +92,111 @@ def read_traffic(kernel_tag, current_hash):
         return None
 
 
+def batched_leg(args, nnc, synth, autotune, torch):
+    """Config 4: 512 scenes advanced together per launch, under each strategy policy,
+    against the same scenes advanced one by one (one context per scene)."""
+    from paper_2606_18314_amd import selector
+    t0 = time.time()
+    spec = synth.batch_spec(args.scenes, seed=4000)
+    steps = args.batch_steps
+    trajs = synth.batch_trajectories(spec, steps + 1, eps=5e-4, seed=4000)
+    ns = [int(v) for v in spec.n]
+    ds = [int(v) for v in spec.d]
+    frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 2)]
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    s = torch.cuda.Stream()
+    grids, lanes, table = autotune.tune_batch(frames, ns, ds, stream=s)
+    params, meta = selector.load_params()
+    tau = float(meta.get("tau", 0.5)) if meta else 0.5
+    total = sum(ns)
+    res = {"scenes": len(ns), "points": total, "steps": steps, "lanes": lanes, "tuning_ms": table,
+           "generator_seconds": round(gen_s, 1), "tau": tau}
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    policies = [("repair", 0), ("rebuild", 1), ("threshold", 2)]
+    if params is not None:
+        policies.append(("learned", 3))
+    pdev = torch.from_numpy(params).cuda() if params is not None else None
+    for name, pol in policies:
+        with torch.cuda.stream(s):
+            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream)
+            if pdev is not None:
+                b.selector_load(pdev)
+            b.init(frames[0])
+            b.step(frames[1], pol, tau)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for t in range(2, steps + 2):
+                b.step(frames[t], pol, tau)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(s)
+        with torch.cuda.stream(s):
+            g.replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = b.stats()
+        rebuilt = sum(x["strategy"] for x in st) / len(st)
+        res[name] = {"value": total * steps / (ms / 1e3), "ms_per_step": ms / steps,
+                     "last_step_rebuild_fraction": rebuilt,
+                     "errors": sum(1 for x in st if x["err"] != 0)}
+        del g
+        b.close()
+    # the same scenes, one context per scene, advanced one after another (graph-captured)
+    per = min(steps, 10)
+    tr_frames = [[torch.from_numpy(tr.frames[t]).cuda() for t in range(per + 2)] for tr in trajs]
+    ctxs = []
+    with torch.cuda.stream(s):
+        for k, tr in enumerate(trajs):
+            c = nnc.NNCert(ns[k], ds[k], grid_g=grids[k], stream=s.cuda_stream, lanes=lanes)
+            c.init_certificates(tr_frames[k][0])
+            c.step(tr_frames[k][1], 5e-4)
+            c.repair()
+            ctxs.append(c)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for t in range(2, per + 2):
+            for k, c in enumerate(ctxs):
+                c.step(tr_frames[k][t], 5e-4)
+                c.repair()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(s)
+    with torch.cuda.stream(s):
+        g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res["per_scene_loop"] = {"value": total * per / (ms / 1e3), "ms_per_step": ms / per, "steps": per}
+    del g
+    for c in ctxs:
+        c.close()
+    res["speedup_batched_repair_over_loop"] = res["repair"]["value"] / res["per_scene_loop"]["value"]
+    if "learned" in res:
+        res["speedup_learned_over_loop"] = res["learned"]["value"] / res["per_scene_loop"]["value"]
+    # selector error on freshly generated held-out transitions (seeds unseen in training)
+    if params is not None and args.regret_scenes > 0:
+        specs = selector.scene_specs(args.regret_scenes, seed=9000)
+        data = selector.collect(specs, args.regret_steps, reps=2)
+        X, tr_, tb_ = data["X"], data["t_repair"], data["t_rebuild"]
+        ch = selector.decide(params, X)
+        res["selector"] = {
+            "transitions": int(len(X)),
+            "regret_learned": selector.regret(ch, tr_, tb_),
+            "regret_threshold": selector.regret((X[:, 0] >= tau).astype(np.int32), tr_, tb_),
+            "regret_always_repair": selector.regret(np.zeros(len(X), np.int32), tr_, tb_),
+            "regret_always_rebuild": selector.regret(np.ones(len(X), np.int32), tr_, tb_),
+            "training": meta,
+        }
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -115,7 +225,11 @@ def main():
 
     tuning = {}
     lanes = {}
-    if args.grid == "auto":
+    if args.grid_json:
+        fixed = json.loads(args.grid_json)
+        grids = {f: int(fixed[f][0]) for f in fams}
+        lanes = {f: int(fixed[f][1]) for f in fams}
+    elif args.grid == "auto":
         grids = {}
         for f in fams:   # tuned on the first warm-up frames, outside every timed region
             (grids[f], lanes[f]), tuning[f] = autotune.tune_grid(
@@ -307,6 +421,10 @@ def main():
                                          "frac": ops / (launch_us * 1e-6) / 1e12 / VALU_PEAK_TOPS,
                                          "traffic": None}}
 
+    # ---- batched scenes (512 scenes, log-uniform N, mixed d and families) ------------------
+    if "batched" in legs_req:
+        legs["batched"] = batched_leg(args, nnc, synth, autotune, torch)
+
     # ---- headline ------------------------------------------------------------------------
     head = legs.get("repair")
     if head is not None:
@@ -362,26 +480,28 @@ def main():
         from oracle import model
         done = 0
         spent = 0.0
-        fam_i = 0
         per_fam_steps = {}
-        while spent < args.cpu_seconds and fam_i < len(fams):
-            f = fams[fam_i]
+        scenes = {}
+        for f in fams:
             sc = model.OracleScene(d=D, n=N, G=grids[f])
             sc.init_certificates(trajs[f].frames[0])
-            t = 1
-            while spent < args.cpu_seconds and t <= min(T, 8):
+            scenes[f] = sc
+            per_fam_steps[f] = 0
+        t = 1
+        while spent < args.cpu_seconds and t <= T:
+            for f in fams:     # the same step of every family, round robin
                 t0 = time.perf_counter()
-                sc.step(trajs[f].frames[t])
-                sc.repair()
+                scenes[f].step(trajs[f].frames[t])
+                scenes[f].repair()
                 spent += time.perf_counter() - t0
                 done += 1
-                t += 1
-            per_fam_steps[f] = t - 1
-            fam_i += 1
+                per_fam_steps[f] = t
+            t += 1
         out["cpu_baseline"] = {"value": done * N / spent, "unit": "point-steps/s", "cores": model.threads(),
                                "kind": "oracle",
-                               "sample": f"oracle step + repair (brute-force certificates of the candidates), "
-                                         f"first steps of each family: {per_fam_steps}, {spent:.1f} s"}
+                               "sample": f"oracle step + repair (brute-force certificates of the candidates) of the "
+                                         f"first {min(per_fam_steps.values())} steps of each of the five "
+                                         f"config-2 scenes, {spent:.1f} s of CPU time"}
     print(json.dumps(out), flush=True)
 
 

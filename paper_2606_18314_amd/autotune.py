@@ -89,3 +89,55 @@ def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(16,
         ctx.close()
     best = min(times, key=times.get)
     return best, {f"{g}/{l}": round(v, 5) for (g, l), v in times.items()}
+
+
+def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 16, factor: float = 1.0):
+    """Per-scene cells per axis for a batch: start from the occupancy rule, read each
+    scene's occupied-cell count C from the library, and refine G so that the occupied
+    cells hold about ``target`` points (capped at 8x the rule and 2^22 cells)."""
+    b = binding.NNCBatch(ns, ds, lanes=lanes)
+    b.init(frame0)
+    b.step(frame0, 0)            # a zero-motion step fills the per-scene statistics
+    st = b.stats()
+    b.close()
+    grids = []
+    for s, (n, d) in enumerate(zip(ns, ds)):
+        g0 = default_grid(int(n), int(d))
+        C = max(1, st[s]["C"])
+        occ = n / C
+        scale = min(8.0, max(1.0, (occ / target) ** (1.0 / d)))
+        g = max(1, int(round(g0 * scale * factor)))
+        while g ** d > MAX_CELLS:
+            g -= 1
+        grids.append(g)
+    return grids
+
+
+def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(0.75, 1.0, 1.5), lanes=(16, 32), policy: int = 0,
+               stream=None):
+    """Fastest (grid factor, lanes) for a batch over a few steps; returns (grids, lanes, table)."""
+    s = stream or torch.cuda.Stream()
+    table = {}
+    best = None
+    for L in lanes:
+        for f in factors:
+            grids = batch_grids(frames[0], ns, ds, lanes=L, factor=f)
+            with torch.cuda.stream(s):
+                b = binding.NNCBatch(ns, ds, grids=grids, lanes=L, stream=s.cuda_stream)
+                b.init(frames[0])
+                b.step(frames[1], policy)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            with torch.cuda.stream(s):
+                for t in range(2, eps_steps + 2):
+                    b.step(frames[t], policy)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / eps_steps
+            b.close()
+            table[f"{f}/{L}"] = round(ms, 4)
+            if best is None or ms < best[0]:
+                best = (ms, grids, L)
+    return best[1], best[2], table
