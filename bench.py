@@ -448,7 +448,7 @@ def main():
             achieved = per_launch / (q_us * 1e-6) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": read_traffic("query_repair_config2", src_hash("grid.hip", "device_common.hpp")),
+                    "traffic": read_traffic("query_repair_config2", src_hash("grid.hip", "device_common.hpp", "kernels_common.hpp")),
                     "kernel": "k_query (repair of the candidates)", "avg_launch_us": q_us,
                     "bytes_per_launch": per_launch}
         out["roofline"] = roof
