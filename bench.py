@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched")
+    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep")
+    ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--regret-scenes", type=int, default=40)
@@ -195,6 +196,143 @@ def batched_leg(args, nnc, synth, autotune, torch):
             "training": meta,
         }
     return res
+
+
+def sweep_leg(args, nnc, synth, torch):
+    """Config 3: N = 2^20 uniform points in the plane; for each target candidate fraction
+    f, one transition with eps = c_(ceil(fN))/4 applied to a disc (localized) or to
+    the same number of random points (diffuse); both strategies timed on the same
+    pending step from the same state, and forced frontiers of equal size (nearest the
+    disc centre vs uniform) repaired to isolate the entropy axis."""
+    n, d, G = 1 << 20, 2, 512
+    p0 = synth.sweep_start(n)
+    s = torch.cuda.Stream()
+    P0 = torch.from_numpy(p0).cuda()
+    reps = args.sweep_reps
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # lanes per query: the faster of 1 and 16 on repair + rebuild of a 5% diffuse transition
+    lanes_table = {}
+    c = None
+    for L in (1, 16):
+        with torch.cuda.stream(s):
+            ctx = nnc.NNCert(n, d, grid_g=G, stream=s.cuda_stream, lanes=L)
+            ctx.init_certificates(P0)
+        torch.cuda.synchronize()
+        if c is None:
+            st = ctx.state()
+            c = np.sort((st["d2"] - st["d1"]).cpu().numpy())
+        P1 = torch.from_numpy(synth.sweep_motion(p0, float(c[int(0.05 * n)]) / 4.0, "diffuse")).cuda()
+        with torch.cuda.stream(s):
+            ctx.step(P1, -1.0)
+        sn = ctx.snapshot()
+        best = math.inf
+        for _ in range(max(reps, 2)):
+            e0, e1 = ev(), ev()
+            with torch.cuda.stream(s):
+                ctx.restore(sn)
+                e0.record(s)
+                ctx.repair()
+                ctx.restore(sn)
+                ctx.rebuild()
+                e1.record(s)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        lanes_table[L] = best
+        del sn
+        ctx.close()
+    lanes = min(lanes_table, key=lanes_table.get)
+    with torch.cuda.stream(s):
+        ctx = nnc.NNCert(n, d, grid_g=G, stream=s.cuda_stream, lanes=lanes)
+        ctx.init_certificates(P0)
+    torch.cuda.synchronize()
+    fresh = ctx.snapshot()
+
+    def timed(fn):
+        best = math.inf
+        for _ in range(reps):
+            with torch.cuda.stream(s):
+                ctx.restore(snap)
+            e0, e1 = ev(), ev()
+            e0.record(s)
+            with torch.cuda.stream(s):
+                fn()
+            e1.record(s)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    rows = []
+    # kernel-level timing of the queries at this size (HBM roofline)
+    kern = {}
+    for f in (0.001, 0.01, 0.05, 0.2, 0.5):
+        k = max(1, int(math.ceil(f * n)))
+        eps = float(c[k - 1]) / 4.0
+        for mode in ("localized", "diffuse"):
+            P1 = torch.from_numpy(synth.sweep_motion(p0, eps, mode)).cuda()
+            with torch.cuda.stream(s):
+                ctx.restore(fresh)
+                ctx.profile_enable(True)
+                ctx.step(P1, -1.0)
+            prof_step = ctx.profile_read()
+            ctx.profile_enable(False)
+            snap = ctx.snapshot()
+            hc = ctx.frontier_entropy(nnc.NNC_CANDIDATES)
+            t_rep = timed(lambda: ctx.repair())
+            t_reb = timed(lambda: ctx.rebuild())
+            with torch.cuda.stream(s):
+                ctx.restore(snap)
+                ctx.profile_enable(True)
+                ctx.repair()
+            prof_rep = ctx.profile_read()
+            with torch.cuda.stream(s):
+                ctx.restore(snap)
+                ctx.rebuild()
+            prof_reb = ctx.profile_read()
+            ctx.profile_enable(False)
+            hf = ctx.frontier_entropy(nnc.NNC_FAILED)
+            rows.append({"target_fraction": f, "mode": mode, "eps": eps, "candidates": hc["count"],
+                         "candidate_fraction": hc["count"] / n, "H_candidates": hc["H"], "m_candidates": hc["m"],
+                         "failures": hf["count"], "H_fail": hf["H"], "m_fail": hf["m"], "C": hf["C"],
+                         "repair_ms": t_rep, "rebuild_ms": t_reb,
+                         "step_kernels_us": (prof_step["ingest"][0] + prof_step["filter"][0]) * 1e3,
+                         "repair_query_us": prof_rep["query"][0] * 1e3,
+                         "rebuild_query_us": prof_reb["query"][0] * 1e3,
+                         "rebuild_grid_us": prof_reb["grid"][0] * 1e3})
+            del snap
+        # forced frontiers of equal size: localized vs diffuse
+        local, diffuse = synth.sweep_lists(p0, k)
+        with torch.cuda.stream(s):
+            ctx.restore(fresh)
+            ctx.step(P0, -1.0)
+        snap = ctx.snapshot()
+        cnt = torch.tensor([k], dtype=torch.int32, device="cuda")
+        out = {}
+        for name, lst in (("localized", local), ("diffuse", diffuse)):
+            L = torch.from_numpy(lst).cuda()
+            out[name] = timed(lambda: ctx.repair(L, cnt))
+        rows.append({"target_fraction": f, "mode": "forced", "count": k, "forced_localized_ms": out["localized"],
+                     "forced_diffuse_ms": out["diffuse"]})
+        del snap
+    # HBM roofline of the rebuild's all-point query at this size
+    reb = [r for r in rows if r.get("mode") == "diffuse"]
+    q_us = sum(r["rebuild_query_us"] for r in reb) / len(reb)
+    qbytes = n * (8 * d + 29) + 4 * (G ** d + 1)
+    rep50 = [r for r in rows if r.get("mode") == "diffuse" and r["target_fraction"] == 0.5][0]
+    rbytes = rep50["candidates"] * (4 * d + 4 + 25) + n * (4 * d + 4) + 4 * (G ** d + 1)
+    ctx.close()
+    return {"n": n, "d": d, "G": G, "lanes": lanes, "lanes_table_ms": lanes_table, "rows": rows,
+            "roofline_rebuild_query": {"bound": "hbm", "achieved": qbytes / (q_us * 1e-6) / 1e9,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": qbytes / (q_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                       "avg_launch_us": q_us, "bytes_per_launch": qbytes},
+            "roofline_repair_query_f50": {"bound": "hbm",
+                                          "achieved": rbytes / (rep50["repair_query_us"] * 1e-6) / 1e9,
+                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": rbytes / (rep50["repair_query_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                          "avg_launch_us": rep50["repair_query_us"], "bytes_per_launch": rbytes}}
 
 
 def main():
@@ -420,6 +558,10 @@ def main():
                                          "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
                                          "frac": ops / (launch_us * 1e-6) / 1e12 / VALU_PEAK_TOPS,
                                          "traffic": None}}
+
+    # ---- frontier-fraction sweep at N = 2^20 -----------------------------------------------
+    if "sweep" in legs_req:
+        legs["sweep"] = sweep_leg(args, nnc, synth, torch)
 
     # ---- batched scenes (512 scenes, log-uniform N, mixed d and families) ------------------
     if "batched" in legs_req:

@@ -78,8 +78,8 @@ typedef struct {
                              index build exceeds refresh * cell width; <= 0 = 0.25 */
     void    *stream;      /* hipStream_t to order work on; NULL = the null stream */
     uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC */
-    int32_t  block;       /* lanes that share one 2-NN query: 16, 32 or 64; 0 = 32 for
-                             d = 3 and 16 for d = 2 */
+    int32_t  block;       /* lanes that share one 2-NN query: 1 (one thread per query,
+                             for large N), 16, 32 or 64; 0 = 32 for d = 3 and 16 for d = 2 */
 } nnc_config;
 
 /* Default grid_g: cell width w = 2/sqrt(N) (d = 2) or (4/N)^(1/3) (d = 3) and
@@ -241,11 +241,16 @@ typedef struct {
     const int64_t *n;        /* host [scenes]: points per scene, 0 <= n <= NNC_BATCH_MAX_N */
     const int32_t *d;        /* host [scenes]: 2 or 3 */
     const int32_t *grid_g;   /* host [scenes]: cells per axis; NULL or entries <= 0 = occupancy rule */
-    int32_t lanes;           /* lanes per query for all scenes: 16, 32 or 64; 0 = 16 */
+    int32_t lanes;           /* lanes per query for all scenes: 1, 16, 32 or 64; 0 = 16 */
     double guard;            /* as in nnc_config */
     double refresh;          /* as in nnc_config */
     void *stream;            /* hipStream_t */
+    uint32_t flags;          /* NNC_BATCH_FEATURES */
 } nnc_batch_config;
+
+/* Compute the candidate histogram, H of the candidates and the selector features
+ * at every step (otherwise only under NNC_POLICY_LEARNED). */
+#define NNC_BATCH_FEATURES 1u
 
 typedef struct {
     double  eps;             /* eps_t of the last step */
@@ -254,7 +259,7 @@ typedef struct {
     double  H_cand;          /* entropy of the candidates */
     int32_t n_cand;          /* |candidates| */
     int32_t n_fail;          /* |failures| */
-    int32_t m_cand;          /* cells met by the candidates */
+    int32_t m_cand;          /* cells met by the candidates (0 unless features are computed) */
     int32_t C;               /* occupied cells */
     int32_t strategy;        /* 0 repair, 1 rebuild */
     int32_t err;             /* NNC_OK or a negative code latched for this scene */

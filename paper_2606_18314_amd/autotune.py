@@ -61,7 +61,7 @@ def pick_grid(pos: torch.Tensor, d: int, target: float = 3.0) -> int:
     return best
 
 
-def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(16, 32, 64),
+def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(1, 16, 32, 64),
               stream=None) -> tuple[tuple[int, int], dict]:
     """Fastest (G, lanes per query) over a short run of step + repair on frames[0..steps];
     returns ((G, L), {"G/L": ms per step})."""
@@ -95,7 +95,7 @@ def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 
     """Per-scene cells per axis for a batch: start from the occupancy rule, read each
     scene's occupied-cell count C from the library, and refine G so that the occupied
     cells hold about ``target`` points (capped at 8x the rule and 2^22 cells)."""
-    b = binding.NNCBatch(ns, ds, lanes=lanes)
+    b = binding.NNCBatch(ns, ds, lanes=lanes, features=True)
     b.init(frame0)
     b.step(frame0, 0)            # a zero-motion step fills the per-scene statistics
     st = b.stats()
@@ -107,13 +107,14 @@ def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 
         occ = n / C
         scale = min(8.0, max(1.0, (occ / target) ** (1.0 / d)))
         g = max(1, int(round(g0 * scale * factor)))
-        while g ** d > MAX_CELLS:
+        # at most 8 cells per point: a scene's grid is built by one workgroup
+        while g > 1 and (g ** d > MAX_CELLS or g ** d > 8 * max(int(n), 1)):
             g -= 1
         grids.append(g)
     return grids
 
 
-def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(0.75, 1.0, 1.5), lanes=(16, 32), policy: int = 0,
+def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(0.75, 1.0, 1.5, 2.0), lanes=(1, 16, 32), policy: int = 0,
                stream=None):
     """Fastest (grid factor, lanes) for a batch over a few steps; returns (grids, lanes, table)."""
     s = stream or torch.cuda.Stream()

@@ -91,7 +91,7 @@ class Profile(ctypes.Structure):
 class BatchConfig(ctypes.Structure):
     _fields_ = [("scenes", ctypes.c_int32), ("n", ctypes.c_void_p), ("d", ctypes.c_void_p),
                 ("grid_g", ctypes.c_void_p), ("lanes", ctypes.c_int32), ("guard", ctypes.c_double),
-                ("refresh", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("refresh", ctypes.c_double), ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
 class SceneStats(ctypes.Structure):
@@ -339,7 +339,7 @@ class NNCBatch:
     [d_s, n_s] block starting at ``coord_off[s]``."""
 
     def __init__(self, ns, ds, grids=None, lanes: int = 0, guard: float = -1.0, refresh: float = 0.0,
-                 stream: int | None = None):
+                 stream: int | None = None, features: bool = False):
         import numpy as np
         lib = load()
         self.S = len(ns)
@@ -349,7 +349,8 @@ class NNCBatch:
         self.stream = _stream() if stream is None else stream
         cfg = BatchConfig(scenes=self.S, n=self._n.ctypes.data, d=self._d.ctypes.data,
                           grid_g=0 if self._g is None else self._g.ctypes.data, lanes=int(lanes),
-                          guard=float(guard), refresh=float(refresh), stream=self.stream)
+                          guard=float(guard), refresh=float(refresh), stream=self.stream,
+                          flags=1 if features else 0)
         h = ctypes.c_void_p()
         check(lib.nnc_batch_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_batch_create")
         self.h = h.value

@@ -48,7 +48,7 @@ struct BatchArgs {
     const SceneDesc *desc;
     int scenes, parity, t, policy;
     float tau;
-    int have_params;
+    int have_params, features_on;
     double guard, K;
     DevScalars *sc;
     const float *pos_prev, *pos_cur;
@@ -225,13 +225,17 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
             if (at < n) front[at] = i;
         }
     }
-    // candidate cells: histogram, touched list, entropy (all within this workgroup)
+    // candidate cells: histogram, touched list, entropy (all within this workgroup);
+    // only when a feature is wanted (the learned policy, or statistics requested)
+    const bool want = a.features_on || a.policy == NNC_POLICY_LEARNED;
     const int *cell = a.cell + sd.poff;
     int *hist = a.hist_cand + sd.goff;
     int *touched = a.touched_cand + sd.poff;
-    for (int q = (int)threadIdx.x; q < tot; q += kFB) {
-        const int c = cell[front[q]];
-        if (atomicAdd(&hist[c], 1) == 0) touched[atomicAdd(&s_m, 1)] = c;
+    if (want) {
+        for (int q = (int)threadIdx.x; q < tot; q += kFB) {
+            const int c = cell[front[q]];
+            if (atomicAdd(&hist[c], 1) == 0) touched[atomicAdd(&s_m, 1)] = c;
+        }
     }
     __syncthreads();
     const int m = s_m;
@@ -337,53 +341,78 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
     }
 }
 
+// Per-scene view of the concatenated arrays for the shared query routine.
+__device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneDesc &sd, int s, int init)
+{
+    QueryArgs q;
+    q.pos = a.pos_cur + sd.coff;
+    q.sorted = a.sorted + sd.coff;
+    q.cell_start = a.cell_start + sd.soff;
+    q.perm = a.perm + sd.poff;
+    q.cell = a.cell + sd.poff;
+    q.list = a.frontier + sd.poff;
+    q.count_dev = nullptr;
+    q.n = sd.n;
+    q.G = sd.G;
+    q.all = a.strategy[s];
+    q.init = init;
+    q.t = a.t;
+    q.parity = a.parity;
+    q.nn = a.nn + sd.poff;
+    q.stamp = a.stamp + sd.poff;
+    q.hist = a.hist_fail + sd.goff;
+    q.touched = a.touched_fail + sd.poff;
+    q.d1 = a.d1 + sd.poff;
+    q.d2 = a.d2 + sd.poff;
+    q.e = a.e + sd.poff;
+    q.fail = a.fail + sd.poff;
+    q.sc = &a.sc[s];
+    q.guard = a.guard;
+    q.K = a.K;
+    return q;
+}
+
+// Every workgroup takes one contiguous chunk of the concatenated query list (all
+// scenes' queries, scene by scene); its lane groups stride through the chunk, so
+// neighbouring groups take neighbouring queries.  A group finds the scene of its
+// first query once and steps to the next scene when it crosses a boundary.
 template <int L>
 __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
 {
     constexpr int GPB = kB / L;
     const int total = a.qpre[a.scenes];
     const int lane = threadIdx.x & (L - 1);
-    for (int g = blockIdx.x * GPB + (int)(threadIdx.x / L); g < total; g += gridDim.x * GPB) {
-        // scene of query g: the last s with qpre[s] <= g
-        int lo = 0, hi = a.scenes;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.qpre[mid] <= g) lo = mid;
-            else hi = mid;
+    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int chunk = (per + GPB - 1) / GPB * GPB;
+    const int q0 = (int)blockIdx.x * chunk + (int)(threadIdx.x / L);
+    const int q1 = min((int)blockIdx.x * chunk + chunk, total);
+    if (q0 >= q1) return;
+    int lo = 0, hi = a.scenes;  // the last s with qpre[s] <= q0
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.qpre[mid] <= q0) lo = mid;
+        else hi = mid;
+    }
+    int s = lo;
+    int next = a.qpre[s + 1];
+    SceneDesc sd = a.desc[s];
+    QueryArgs q = scene_view(a, sd, s, init);
+    double St = a.sc[s].S[a.parity];
+    double margin = query_margin(St, a.sc[s].S_grid);
+    for (int g = q0; g < q1; g += GPB) {
+        while (g >= next) {  // uniform within the lane group
+            ++s;
+            next = a.qpre[s + 1];
+            sd = a.desc[s];
+            q = scene_view(a, sd, s, init);
+            St = a.sc[s].S[a.parity];
+            margin = query_margin(St, a.sc[s].S_grid);
         }
-        const int s = lo;
-        const SceneDesc sd = a.desc[s];
-        QueryArgs q;
-        q.pos = a.pos_cur + sd.coff;
-        q.sorted = a.sorted + sd.coff;
-        q.cell_start = a.cell_start + sd.soff;
-        q.perm = a.perm + sd.poff;
-        q.cell = a.cell + sd.poff;
-        q.list = a.frontier + sd.poff;
-        q.count_dev = nullptr;
-        q.n = sd.n;
-        q.G = sd.G;
-        q.all = a.strategy[s];
-        q.init = init;
-        q.t = a.t;
-        q.parity = a.parity;
-        q.nn = a.nn + sd.poff;
-        q.stamp = a.stamp + sd.poff;
-        q.hist = a.hist_fail + sd.goff;
-        q.touched = a.touched_fail + sd.poff;
-        q.d1 = a.d1 + sd.poff;
-        q.d2 = a.d2 + sd.poff;
-        q.e = a.e + sd.poff;
-        q.fail = a.fail + sd.poff;
-        q.sc = &a.sc[s];
-        q.guard = a.guard;
-        q.K = a.K;
-        const double St = a.sc[s].S[a.parity];
-        const double margin = query_margin(St, a.sc[s].S_grid);
+        const int local = g - a.qpre[s];
         if (sd.d == 3)
-            query_one<3, L>(q, g - a.qpre[s], St, margin, lane);
+            query_one<3, L>(q, local, St, margin, lane);
         else
-            query_one<2, L>(q, g - a.qpre[s], St, margin, lane);
+            query_one<2, L>(q, local, St, margin, lane);
     }
 }
 
@@ -430,7 +459,7 @@ struct nnc_batch {
     void *arena;
     nnc::BatchArgs a;       // device pointers, refreshed per call
     int64_t t;
-    int inited, have_params;
+    int inited, have_params, features_on;
     const float *pos_cur, *pos_prev;
 };
 
@@ -450,6 +479,7 @@ int launch_query_b(nnc_batch *b, int init)
 {
     const int blocks = 2048;
     switch (b->lanes) {
+    case 1: hipLaunchKernelGGL(nnc::k_b_query<1>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
     case 64: hipLaunchKernelGGL(nnc::k_b_query<64>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
     case 32: hipLaunchKernelGGL(nnc::k_b_query<32>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
     default: hipLaunchKernelGGL(nnc::k_b_query<16>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
@@ -468,7 +498,8 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     nnc_batch *b = new (std::nothrow) nnc_batch();
     if (!b) return NNC_E_NOMEM;
     b->S = cfg->scenes;
-    b->lanes = cfg->lanes == 32 || cfg->lanes == 64 ? cfg->lanes : 16;
+    b->lanes = cfg->lanes == 1 || cfg->lanes == 32 || cfg->lanes == 64 ? cfg->lanes : 16;
+    b->features_on = (cfg->flags & NNC_BATCH_FEATURES) != 0;
     b->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
     b->K = 1.0 / (4.0 + 4.0 * b->guard);
     b->stream = (hipStream_t)cfg->stream;
@@ -662,6 +693,7 @@ int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
     a.policy = policy;
     a.tau = tau;
     a.have_params = b->have_params;
+    a.features_on = b->features_on;
     if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_ingest, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);

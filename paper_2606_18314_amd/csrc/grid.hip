@@ -45,37 +45,50 @@ __device__ __forceinline__ unsigned long long pack_status(unsigned epoch, int fl
     return ((unsigned long long)(epoch & 0x3fffffffu) << 34) | ((unsigned long long)flag << 32) | v;
 }
 
-// Decoupled look-back (single thread): publish this tile's aggregate, walk
-// predecessors until an inclusive prefix is found, publish the inclusive prefix
-// and return the exclusive one.  Tickets are taken in launch order, so every
-// predecessor is running or done; the wait is bounded all the same.
+// Decoupled look-back, run by all 64 lanes of wave 0: publish this tile's
+// aggregate, then inspect the 64 nearest predecessors at once; if a
+// predecessor nearer than the nearest inclusive prefix is not ready yet, wait
+// and re-read, else add the aggregates up to (and including) that prefix and
+// stop, or move 64 tiles further back.  Tickets are taken in launch order, so
+// every predecessor is running or done; the wait is bounded all the same.
 __device__ unsigned lookback(unsigned long long *status, int tile, unsigned agg, unsigned epoch, unsigned *err)
 {
+    const int lane = (int)lane_id();
+    const unsigned ep = epoch & 0x3fffffffu;
     if (tile == 0) {
-        st_agent(&status[0], pack_status(epoch, kFlagP, agg));
+        if (lane == 0) st_agent(&status[0], pack_status(epoch, kFlagP, agg));
         return 0u;
     }
-    st_agent(&status[tile], pack_status(epoch, kFlagA, agg));
+    if (lane == 0) st_agent(&status[tile], pack_status(epoch, kFlagA, agg));
     unsigned excl = 0;
-    int p = tile - 1;
+    int base = tile - 1;
     unsigned spins = 0;
-    const unsigned ep = epoch & 0x3fffffffu;
-    while (p >= 0) {
-        const unsigned long long v = ld_agent(&status[p]);
-        const int flag = (int)((v >> 32) & 3u);
-        if ((unsigned)(v >> 34) != ep || flag == 0) {
+    for (;;) {
+        const int p = base - lane;
+        unsigned long long v = 0;
+        int flag = kFlagP;  // before tile 0: an empty inclusive prefix
+        if (p >= 0) {
+            v = ld_agent(&status[p]);
+            flag = (unsigned)(v >> 34) == ep ? (int)((v >> 32) & 3u) : 0;
+        }
+        const unsigned long long pm = __ballot(flag == kFlagP);
+        const unsigned long long xm = __ballot(flag == 0);
+        const int firstP = pm ? __ffsll((long long)pm) - 1 : 64;
+        const int firstX = xm ? __ffsll((long long)xm) - 1 : 64;
+        if (firstX < firstP) {
             if (++spins > kSpinLimit) {
-                atomicOr(err, kErrSpin);
+                if (lane == 0) atomicOr(err, kErrSpin);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += (unsigned)v;
-        if (flag == kFlagP) break;
-        --p;
+        const unsigned mine = (lane <= firstP && p >= 0) ? (unsigned)v : 0u;
+        excl += (unsigned)wave_sum((int)mine);
+        if (firstP < 64) break;
+        base -= 64;
     }
-    st_agent(&status[tile], pack_status(epoch, kFlagP, excl + agg));
+    if (lane == 0) st_agent(&status[tile], pack_status(epoch, kFlagP, excl + agg));
     return excl;
 }
 
@@ -185,6 +198,7 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
         if (lane == 0) s_cnt[k][w] = __popcll(masks[k]);
     }
     __syncthreads();
+    __shared__ int s_run;
     if (threadIdx.x == 0) {
         int run = 0;
         for (int k = 0; k < kRows; ++k)
@@ -193,11 +207,18 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
                 s_cnt[k][v] = run;
                 run += c;
             }
+        s_run = run;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int run = s_run;
         const unsigned excl = lookback(status, tile, (unsigned)run, s_epoch, &sc->err);
-        s_base = excl;
-        if (tile == (int)gridDim.x - 1) {
-            sc->nfront = (int)(excl + (unsigned)run);
-            retire_ticket(sy, s_epoch);
+        if (threadIdx.x == 0) {
+            s_base = excl;
+            if (tile == (int)gridDim.x - 1) {
+                sc->nfront = (int)(excl + (unsigned)run);
+                retire_ticket(sy, s_epoch);
+            }
         }
     }
     __syncthreads();
@@ -299,14 +320,16 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
         pref[k] = run + ex;
         run += tot;
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
         const unsigned excl = lookback(status, tile, (unsigned)run, s_epoch, &sc->err);
-        s_base = excl;
-        if (tile == (int)gridDim.x - 1) {
-            cell_start[ncell] = (int)(excl + (unsigned)run);
-            retire_ticket(sy, s_epoch);
+        if (threadIdx.x == 0) {
+            s_base = excl;
+            if (tile == (int)gridDim.x - 1) {
+                cell_start[ncell] = (int)(excl + (unsigned)run);
+                retire_ticket(sy, s_epoch);
+            }
+            if (tile == 0) sc->S_grid = sc->S[parity];
         }
-        if (tile == 0) sc->S_grid = sc->S[parity];
     }
     __syncthreads();
     const int b = (int)s_base;
@@ -552,10 +575,12 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
     if (c->d == 2) {
         if (c->lanes == 64) launch_query_t<2, 64>(a, maxq, c->stream);
         else if (c->lanes == 32) launch_query_t<2, 32>(a, maxq, c->stream);
+        else if (c->lanes == 1) launch_query_t<2, 1>(a, maxq, c->stream);
         else launch_query_t<2, 16>(a, maxq, c->stream);
     } else {
         if (c->lanes == 64) launch_query_t<3, 64>(a, maxq, c->stream);
         else if (c->lanes == 32) launch_query_t<3, 32>(a, maxq, c->stream);
+        else if (c->lanes == 1) launch_query_t<3, 1>(a, maxq, c->stream);
         else launch_query_t<3, 16>(a, maxq, c->stream);
     }
     return check();

@@ -163,8 +163,22 @@ __device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y,
                                            int gz, int lane, Top2 &t)
 {
     constexpr int R = D == 3 ? 9 : 3;
-    static_assert(L >= R, "a group needs one lane per row");
     const int G = a.G;
+    if constexpr (L == 1) {
+        // one thread per query: walk the block's rows one after another
+        const int xlo = max(gx - 1, 0), xhi = min(gx + 1, G - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int cy = gy + r % 3 - 1;
+            const int cz = D == 3 ? gz + r / 3 - 1 : 0;
+            if (cy < 0 || cy >= G || cz < 0 || cz >= (D == 3 ? G : 1)) continue;
+            const int row = (cz * G + cy) * G;
+            const int k1 = a.cell_start[row + xhi + 1];
+            for (int k = a.cell_start[row + xlo]; k < k1; ++k) visit_slot<D>(a, k, x, y, z, i, t);
+        }
+        return;
+    }
+    static_assert(L == 1 || L >= R, "a group needs one lane per row");
     int rs = 0, rl = 0;
     if (lane < R) {
         const int cy = gy + lane % 3 - 1;

@@ -195,3 +195,44 @@ def batch_trajectories(spec: BatchSpec, steps: int, eps: float = 5e-4, seed: int
 def concat_frame(trajs, t: int) -> np.ndarray:
     """Concatenate frame t of every scene: scene s's block is [d_s][N_s] SoA."""
     return np.concatenate([tr.frames[t].reshape(-1) for tr in trajs]).astype(np.float32)
+
+
+# --- the frontier-fraction sweep (one large scene, one transition per point) ---------
+
+def sweep_start(n: int = 1 << 20, seed: int = 3000) -> np.ndarray:
+    """N points uniform in the unit square, float32 [2, N]."""
+    return _f32(rng(seed).random((2, n)))
+
+
+def sweep_centre(seed: int = 3000) -> np.ndarray:
+    """Centre of the moving disc, uniform in [0.1, 0.9]^2."""
+    return 0.1 + 0.8 * rng(seed, 1).random(2)
+
+
+def sweep_motion(p0: np.ndarray, eps: float, mode: str, seed: int = 3000, radius: float = 0.05) -> np.ndarray:
+    """One transition of the sweep: Brownian steps clipped to eps for the points inside
+    a disc of the given radius ("localized"), or for the same number of points drawn
+    uniformly at random ("diffuse"); every other point stays put."""
+    g = rng(seed, 2)
+    p = p0.astype(np.float64)
+    c = sweep_centre(seed)
+    inside = np.flatnonzero((p[0] - c[0]) ** 2 + (p[1] - c[1]) ** 2 <= radius * radius)
+    if mode == "localized":
+        movers = inside
+    elif mode == "diffuse":
+        movers = np.sort(g.choice(p.shape[1], inside.size, replace=False))
+    else:
+        raise ValueError(mode)
+    p[:, movers] += _brownian(g, 2, movers.size, eps)
+    return _f32(p)
+
+
+def sweep_lists(p0: np.ndarray, count: int, seed: int = 3000):
+    """Forced frontiers of equal size: the ``count`` points nearest the disc centre
+    (localized) and ``count`` points drawn uniformly (diffuse), ascending int32."""
+    g = rng(seed, 3)
+    c = sweep_centre(seed)
+    r2 = (p0[0].astype(np.float64) - c[0]) ** 2 + (p0[1].astype(np.float64) - c[1]) ** 2
+    local = np.sort(np.argpartition(r2, count - 1)[:count]).astype(np.int32)
+    diffuse = np.sort(g.choice(p0.shape[1], count, replace=False)).astype(np.int32)
+    return local, diffuse

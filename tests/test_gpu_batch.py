@@ -50,7 +50,7 @@ def make_scenes(seed, count, nmax=6000, steps=10):
 def run_batch(nnc, trajs, grids, policy, tau=0.5, params=None, lanes=16):
     ns = [t.n for t in trajs]
     ds = [t.d for t in trajs]
-    b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes)
+    b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, features=True)
     oracles = [model.OracleScene(d=t.d, n=t.n, G=G) for t, G in zip(trajs, grids)]
     steps = trajs[0].steps
     frames = [dev(synth.concat_frame(trajs, t)) for t in range(steps + 1)]
@@ -108,7 +108,7 @@ def test_batch_policies_match_per_scene_oracles(nnc, policy):
         assert set(chosen) == {1}
 
 
-@pytest.mark.parametrize("lanes", [32, 64])
+@pytest.mark.parametrize("lanes", [1, 32, 64])
 def test_batch_lane_widths(nnc, lanes):
     trajs, grids = make_scenes(21, 6, nmax=4000, steps=6)
     run_batch(nnc, trajs, grids, 2, tau=0.5, lanes=lanes)

@@ -154,7 +154,7 @@ def test_config2_families_reduced(nnc, family):
     run_parity(nnc, tr, G=9, strategy="alternate")
 
 
-@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("lanes", [1, 16, 32, 64])
 @pytest.mark.parametrize("d", [2, 3])
 def test_lanes_per_query_and_fine_grids(nnc, lanes, d):
     """Every lane-group width, on grids fine enough that most queries widen."""
@@ -197,7 +197,7 @@ def test_isolated_point_forces_widening(nnc):
         frames.append(q)
     tr = synth.Trajectory("custom", 2, n, -1.0, np.array(frames, dtype=np.float32))
     run_parity(nnc, tr, G=40)
-    for lanes in (16, 64):
+    for lanes in (1, 16, 64):
         run_parity(nnc, tr, G=40, lanes=lanes)
     p3 = np.concatenate([np.array(frames), 0.1 + 0.02 * g.random((6, 1, n))], axis=1)
     p3[:, 2, -1] = 0.97
