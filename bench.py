@@ -94,7 +94,7 @@ def read_traffic(kernel_tag, current_hash):
 
 
 def batched_leg(args, nnc, synth, autotune, torch):
-    """Config 4: 512 scenes advanced together per launch, under each strategy policy,
+    """Batched workload: 512 scenes advanced together per launch, under each strategy policy,
     against the same scenes advanced one by one (one context per scene)."""
     from paper_2606_18314_amd import selector
     t0 = time.time()
@@ -199,7 +199,7 @@ def batched_leg(args, nnc, synth, autotune, torch):
 
 
 def sweep_leg(args, nnc, synth, torch):
-    """Config 3: N = 2^20 uniform points in the plane; for each target candidate fraction
+    """Frontier sweep: N = 2^20 uniform points in the plane; for each target candidate fraction
     f, one transition with eps = c_(ceil(fN))/4 applied to a disc (localized) or to
     the same number of random points (diffuse); both strategies timed on the same
     pending step from the same state, and forced frontiers of equal size (nearest the
@@ -354,7 +354,7 @@ def main():
     dev = torch.device("cuda:0")
     fams = list(synth.FAMILIES)
     t_gen = time.time()
-    trajs = {f: synth.config2(f, n=N, steps=T) for f in fams}
+    trajs = {f: synth.cube_16k(f, n=N, steps=T) for f in fams}
     frames = {f: torch.from_numpy(trajs[f].frames).to(dev) for f in fams}   # resident in HBM
     torch.cuda.synchronize()
     gen_s = time.time() - t_gen
@@ -590,11 +590,11 @@ def main():
             achieved = per_launch / (q_us * 1e-6) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": read_traffic("query_repair_config2", src_hash("grid.hip", "device_common.hpp", "kernels_common.hpp")),
+                    "traffic": read_traffic("query_repair_cube_16k", src_hash("grid.hip", "device_common.hpp", "kernels_common.hpp")),
                     "kernel": "k_query (repair of the candidates)", "avg_launch_us": q_us,
                     "bytes_per_launch": per_launch}
         out["roofline"] = roof
-    out["config"] = {"workload": "config2: N=16000 points, d=3, five motion families, eps=5e-4, "
+    out["config"] = {"workload": "cube_16k: N=16000 points, d=3, five motion families, eps=5e-4, "
                                  f"{K} timed steps after {W} warm-up steps; the five independent scenes "
                                  "advance on their own streams as branches of one HIP graph",
                      "families": fams, "grid_g": grids, "lanes_per_query": lanes, "grid_tuning_ms": tuning, "strategy": "repair",
@@ -643,7 +643,7 @@ def main():
                                "kind": "oracle",
                                "sample": f"oracle step + repair (brute-force certificates of the candidates) of the "
                                          f"first {min(per_fam_steps.values())} steps of each of the five "
-                                         f"config-2 scenes, {spent:.1f} s of CPU time"}
+                                         f"N=16000 five-family scenes, {spent:.1f} s of CPU time"}
     print(json.dumps(out), flush=True)
 
 

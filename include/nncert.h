@@ -61,6 +61,10 @@ extern "C" {
 /* ---- configuration flags ------------------------------------------------ */
 #define NNC_COPY_POSITIONS 1u  /* keep a private copy of each position frame */
 #define NNC_SYNC           2u  /* nnc_step synchronises and fills count_host */
+/* All-point queries (initialisation, rebuild) run tiled by grid cells with the
+ * neighbourhood staged in LDS from N = 65536 on, pointwise below; these force one. */
+#define NNC_QUERY_TILED     4u
+#define NNC_QUERY_POINTWISE 8u
 
 /* nnc_frontier_entropy: which set */
 #define NNC_FAILED     0      /* certificates whose nearest neighbour changed (Definition 2) */
@@ -77,7 +81,7 @@ typedef struct {
     double   refresh;     /* loose-grid refresh when accumulated motion since the last
                              index build exceeds refresh * cell width; <= 0 = 0.25 */
     void    *stream;      /* hipStream_t to order work on; NULL = the null stream */
-    uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC */
+    uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC | NNC_QUERY_TILED | NNC_QUERY_POINTWISE */
     int32_t  block;       /* lanes that share one 2-NN query: 1 (one thread per query,
                              for large N), 16, 32 or 64; 0 = 32 for d = 3 and 16 for d = 2 */
 } nnc_config;

@@ -29,6 +29,8 @@ NNC_E_DEVICE = -7
 
 NNC_COPY_POSITIONS = 1
 NNC_SYNC = 2
+NNC_QUERY_TILED = 4
+NNC_QUERY_POINTWISE = 8
 
 NNC_FAILED = 0
 NNC_CANDIDATES = 1
@@ -223,13 +225,20 @@ class NNCert:
     """One moving point set and its certificates, on the current CUDA stream."""
 
     def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
-                 copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0):
+                 copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0,
+                 all_query: str = "auto"):
+        """all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
+        query every point (tiled by cells from N = 65536 on under "auto")."""
+        if all_query not in ("auto", "tiled", "pointwise"):
+            raise ValueError("all_query: 'auto', 'tiled' or 'pointwise'")
         lib = load()
         self.n, self.d = int(n), int(d)
         self.stream = _stream() if stream is None else stream
         cfg = Config(d=self.d, grid_g=int(grid_g), n=self.n, guard=float(guard), refresh=float(refresh),
                      stream=self.stream,
-                     flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0),
+                     flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0)
+                     | (NNC_QUERY_TILED if all_query == "tiled" else 0)
+                     | (NNC_QUERY_POINTWISE if all_query == "pointwise" else 0),
                      block=int(lanes))
         h = ctypes.c_void_p()
         check(lib.nnc_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_create")

@@ -52,17 +52,19 @@ size_t carve(nnc_ctx *c, char *base)
     c->grid.perm = k.take<int>(n);
     c->grid.rank = k.take<int>(n);
     c->grid.sorted = k.take<float>(n * (size_t)c->d);
-    c->hist_fail = k.take<int32_t>(nc);
-    c->hist_cand = k.take<int32_t>(nc);
+    // histograms padded to whole int4 groups (the entropy scans them four cells at a time)
+    c->hist_fail = k.take<int32_t>((nc + 3) / 4 * 4);
+    c->hist_cand = k.take<int32_t>((nc + 3) / 4 * 4);
     c->state_bytes = k.off;
     c->sync = k.take<nnc::DevSync>(1);
     c->grid.cursor = k.take<int>(nc);
-    c->touched_fail = k.take<int32_t>(n);
-    c->touched_cand = k.take<int32_t>(n);
     // one descriptor per look-back tile (2048 items of the filter or of the cell scan)
     const size_t tiles = ((n > nc ? n : nc) + 2047) / 2048 + 1;
     c->nstatus = (int)tiles;
     c->status = k.take<unsigned long long>(tiles);
+    c->wide = k.take<int32_t>(n);
+    c->rec = k.take<int4>(n);
+    c->ent_part = k.take<double>(3 * nnc::kEntropyParts);
     c->a_nn = k.take<int32_t>(n);
     c->a_d1 = k.take<float>(n);
     c->a_d2 = k.take<float>(n);
@@ -234,7 +236,7 @@ int nnc_init_certificates(nnc_ctx *c, const float *pos)
     if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
     int rc = nnc::launch_cells_init(c, c->pos_cur);
     if (rc == NNC_OK) rc = build_grid(c);
-    if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query(c, nullptr, nullptr, 1, 1); });
+    if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query_all(c, 1); });
     c->inited = rc == NNC_OK;
     return rc;
 }
@@ -294,7 +296,7 @@ int nnc_rebuild(nnc_ctx *c)
     if (!c) return NNC_E_INVAL;
     if (!c->pending) return NNC_E_STATE;
     int rc = build_grid(c);
-    if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query(c, nullptr, nullptr, 1, 0); });
+    if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query_all(c, 0); });
     if (rc == NNC_OK) rc = timed(c, NNC_K_ENTROPY, [&] { return nnc::launch_entropy(c, 0); });
     c->pending = 0;
     return rc;

@@ -121,9 +121,7 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
             atomicOr(&a.sc[s].err, kErrNonFinite);
         }
     }
-    add_C(&a.sc[s], dC);
-    sq = wave_max(sq);
-    if (lane_id() == 0 && sq > 0.0f) atomicMax(&a.sc[s].dmax[a.parity], __float_as_uint(sq));
+    publish_ingest<kB>(&a.sc[s], a.parity, sq, dC);
 }
 
 // The selector network on one wave: lane j is hidden unit j of both layers.

@@ -19,7 +19,8 @@
 //                  ring until the second neighbour is provably enclosed
 //                  (Corollary 1); then the new certificate, expiry key,
 //                  failure flag and failure histogram.
-//   k_entropy      normalised entropy (Definition 2) over the touched cells.
+//   k_entropy*     normalised entropy (Definition 2) from a scan of the cell
+//                  histogram (one workgroup, or partial sums for large grids).
 #include <math.h>
 
 #include "device_common.hpp"
@@ -39,6 +40,9 @@ constexpr int kSmallB = 1024;      // one-workgroup filter: threads
 constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
+constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
+constexpr int kEntropyOneGroup4 = 1 << 15;
+constexpr int kIngestBlocks = 256;  // same-address atomics cost ~10 ns each across the XCDs  // histograms up to 2^17 cells: one-workgroup entropy
 
 __device__ __forceinline__ unsigned long long pack_status(unsigned epoch, int flag, unsigned v)
 {
@@ -142,11 +146,12 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
                                                const int *__restrict__ rank, float *__restrict__ sorted,
                                                DevScalars *sc, int parity)
 {
-    const int i = blockIdx.x * kB + threadIdx.x;
+    // grid-stride, so that the launch has at most kIngestBlocks workgroups and as
+    // many pairs of atomics on the shared words
     float s = 0.0f;
     int dC = 0;
-    if (i < n) {
-        const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
+    const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
+    for (int i = blockIdx.x * kB + (int)threadIdx.x; i < n; i += gridDim.x * kB) {
         const float x0 = pold[i], y0 = pold[n1 + i], z0 = D == 3 ? pold[n2 + i] : 0.f;
         const float x1 = pnew[i], y1 = pnew[n1 + i], z1 = D == 3 ? pnew[n2 + i] : 0.f;
         const int k = rank[i];
@@ -154,7 +159,7 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
         sorted[n1 + k] = y1;
         if constexpr (D == 3) sorted[n2 + k] = z1;
         if (all_finite<D>(x1, y1, z1) && all_finite<D>(x0, y0, z0)) {
-            s = sqdist<D>(x0, y0, z0, x1, y1, z1);
+            s = fmaxf(s, sqdist<D>(x0, y0, z0, x1, y1, z1));
             const int c = cell_id<D>(x1, y1, z1, G);
             const int old = cell[i];
             if (c != old) {
@@ -166,9 +171,7 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
             atomicOr(&sc->err, kErrNonFinite);
         }
     }
-    add_C(sc, dC);
-    s = wave_max(s);
-    if (lane_id() == 0 && s > 0.0f) atomicMax(&sc->dmax[parity], __float_as_uint(s));
+    publish_ingest<kB>(sc, parity, s, dC);
 }
 
 __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int n, DevScalars *sc, DevSync *sy,
@@ -328,7 +331,10 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
                 cell_start[ncell] = (int)(excl + (unsigned)run);
                 retire_ticket(sy, s_epoch);
             }
-            if (tile == 0) sc->S_grid = sc->S[parity];
+            if (tile == 0) {
+                sc->S_grid = sc->S[parity];
+                sc->nwide = 0;
+            }
         }
     }
     __syncthreads();
@@ -375,20 +381,192 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
         query_one<D, L>(a, q, St, margin, lane);
 }
 
-__global__ void __launch_bounds__(1024) k_entropy(int which, int *__restrict__ hist, const int *__restrict__ touched,
-                                                  DevScalars *sc)
+// All-point query (rebuild and initialisation, right after a grid build), tiled
+// by cells: a tile is a run of TX cells of one grid row (fixed y, z); its 3^(d-1)
+// neighbouring row segments are contiguous slot ranges, staged once in LDS, and
+// every point of the tile's cells scans its 3^d block from LDS, one thread per
+// point.  A point whose second neighbour is not enclosed by the first block is
+// appended to the widening list and finished by the pointwise query; a tile
+// whose neighbourhood exceeds the LDS capacity runs the pointwise search for
+// its points.  Results go to a slot-ordered record per point (coalesced), and
+// k_finish_all moves them to point order with one random 16-byte read per point
+// instead of six scattered stores.  Tiles are dealt to XCDs in contiguous ranges
+// (workgroups go to the eight XCDs round-robin), so neighbouring tiles share an L2.
+constexpr int kTB = 256;       // threads per tile
+constexpr int kNbMax = 3072;   // neighbourhood points staged in LDS
+constexpr int kTXMax = 256;    // cells per tile
+
+__device__ __forceinline__ int xcd_tile(int b, int nt)
 {
-    entropy_block<1024>(which, hist, touched, sc);
+    const int x = b & 7, k = b >> 3;
+    const int full = nt >> 3, rem = nt & 7;
+    return x * full + min(x, rem) + k;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int nseg, int *__restrict__ wide,
+                                                     int4 *__restrict__ rec)
+{
+    constexpr int R = D == 3 ? 9 : 3;  // neighbourhood rows, (dy, dz) with dy fastest
+    constexpr int MID = R / 2;         // dy = dz = 0
+    __shared__ float s_x[kNbMax], s_y[kNbMax], s_z[D == 3 ? kNbMax : 1];
+    __shared__ int s_j[kNbMax];
+    __shared__ int s_cs[R][kTXMax + 3];
+    __shared__ int s_lo[R], s_off[R + 1];
+    const int G = a.G;
+    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int row = tile / nseg, seg = tile - row * nseg;
+    const int gy = D == 3 ? row % G : row, gz = D == 3 ? row / G : 0;
+    const int gx0 = seg * TX, gx1 = min(gx0 + TX, G);      // the tile's cells [gx0, gx1)
+    const int gl = max(gx0 - 1, 0), gh = min(gx1, G - 1);  // neighbourhood cells [gl, gh]
+    const int w = gh - gl + 1;
+    for (int idx = (int)threadIdx.x; idx < R * (w + 1); idx += kTB) {
+        const int k = idx / (w + 1), u = idx - k * (w + 1);
+        const int y = gy + (D == 3 ? k % 3 : k) - 1, z = D == 3 ? gz + k / 3 - 1 : 0;
+        const bool in = y >= 0 && y < G && z >= 0 && z < G;
+        s_cs[k][u] = in ? a.cell_start[gl + u + G * (y + G * z)] : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int k = 0; k < R; ++k) {
+            s_lo[k] = s_cs[k][0];
+            s_off[k] = off;
+            off += s_cs[k][w] - s_cs[k][0];
+        }
+        s_off[R] = off;
+    }
+    __syncthreads();
+    const int total = s_off[R];
+    const bool staged = total <= kNbMax;
+    // slot of LDS entry m of row k: s_lo[k] + (m - s_off[k]); cell starts become LDS positions
+    for (int idx = (int)threadIdx.x; idx < R * (w + 1); idx += kTB) {
+        const int k = idx / (w + 1), u = idx - k * (w + 1);
+        s_cs[k][u] += s_off[k] - s_lo[k];
+    }
+    if (staged) {
+        for (int m = (int)threadIdx.x; m < total; m += kTB) {
+            int k = 0;
+            while (k + 1 < R && s_off[k + 1] <= m) ++k;
+            const int slot = s_lo[k] + (m - s_off[k]);
+            s_x[m] = a.sorted[slot];
+            s_y[m] = a.sorted[n1 + slot];
+            if constexpr (D == 3) s_z[m] = a.sorted[n2 + slot];
+            s_j[m] = a.perm[slot];
+        }
+    }
+    __syncthreads();
+    const double St = a.sc->S[a.parity];
+    const double margin = query_margin(St, a.sc->S_grid);
+    const int q0 = s_cs[MID][gx0 - gl], q1 = s_cs[MID][gx1 - gl];
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += kTB) {
+        const int slot = s_lo[MID] + (q - s_off[MID]);
+        float x, y, z = 0.0f;
+        int i;
+        if (staged) {
+            x = s_x[q];
+            y = s_y[q];
+            if constexpr (D == 3) z = s_z[q];
+            i = s_j[q];
+        } else {
+            x = a.sorted[slot];
+            y = a.sorted[n1 + slot];
+            if constexpr (D == 3) z = a.sorted[n2 + slot];
+            i = a.perm[slot];
+        }
+        Top2 t;
+        t.init();
+        const int cx = cell_axis(x, G), cy = cell_axis(y, G), cz = D == 3 ? cell_axis(z, G) : 0;
+        if (staged && cx >= gx0 && cx < gx1 && cy == gy && cz == gz) {
+            const int ulo = max(cx - 1, 0) - gl, uhi = min(cx + 1, G - 1) - gl + 1;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int lo = s_cs[k][ulo], hi = s_cs[k][uhi];
+                for (int m = lo; m < hi; ++m) {
+                    const float s = sqdist<D>(x, y, z, s_x[m], s_y[m], D == 3 ? s_z[m] : 0.0f);
+                    const int j = s_j[m];
+                    if (j != i) t.push(s, j);
+                }
+            }
+            const double B = outside_bound<D>(x, y, z, cx, cy, cz, 1, G);
+            const double Be = B - margin;
+            if (!__builtin_isinf(B) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel))) {
+                const int at = atomicAdd(&a.sc->nwide, 1);
+                if (at < a.n)
+                    wide[at] = i;
+                else
+                    atomicOr(&a.sc->err, kErrOverflow);
+                rec[slot] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
+                continue;
+            }
+        } else {
+            group_search<D, 1>(a, x, y, z, i, margin, 0, t);
+        }
+        rec[slot] = make_int4(t.nn, __float_as_int(t.s1), __float_as_int(t.s2), 1);
+    }
+}
+
+// Point-order completion of the tiled pass: certificate of point i from the
+// record of its slot (skipped if the widening pass owns the point).
+__global__ void __launch_bounds__(kB) k_finish_all(QueryArgs a, const int *__restrict__ rank,
+                                                   const int4 *__restrict__ rec)
+{
+    const int i = blockIdx.x * kB + threadIdx.x;
+    if (i >= a.n) return;
+    const int4 r = rec[rank[i]];
+    if (r.w == 0) return;
+    Top2 t;
+    t.nn = r.x;
+    t.s1 = __int_as_float(r.y);
+    t.s2 = __int_as_float(r.z);
+    const double St = a.sc->S[a.parity];
+    write_certificate(a, i, t, St, a.nn[i]);
+}
+
+// Normalised entropy (Definition 2) of the failures (which = 0) or candidates
+// (which = 1): one workgroup scans the cell histogram.
+__global__ void __launch_bounds__(1024) k_entropy(int which, int *__restrict__ hist, int ncell4, DevScalars *sc)
+{
+    HistSums r{0.0, 0.0, 0.0};
+    hist_terms(hist, ncell4, (int)threadIdx.x, 1024, r);
+    const HistSums t = block_sums<1024>(r);
+    if (threadIdx.x == 0) entropy_publish(which, t, sc);
 }
 
 __global__ void __launch_bounds__(kB) k_cand_hist(const int *__restrict__ frontier, const int *__restrict__ cell,
-                                                  int *__restrict__ hist, int *__restrict__ touched, DevScalars *sc)
+                                                  int *__restrict__ hist, const DevScalars *sc)
 {
     const int count = sc->nfront;
-    for (int q = blockIdx.x * kB + threadIdx.x; q < count; q += gridDim.x * kB) {
-        const int c = cell[frontier[q]];
-        if (atomicAdd(&hist[c], 1) == 0) touched[atomicAdd(&sc->ncand_touched, 1)] = c;
+    for (int q = blockIdx.x * kB + (int)threadIdx.x; q < count; q += gridDim.x * kB)
+        atomicAdd(&hist[cell[frontier[q]]], 1);
+}
+
+// The same over a large histogram: per-workgroup partial sums, then one
+// workgroup adds them up and publishes.
+__global__ void __launch_bounds__(kB) k_entropy_part(int *__restrict__ hist, int ncell4, double *__restrict__ part)
+{
+    HistSums r{0.0, 0.0, 0.0};
+    hist_terms(hist, ncell4, blockIdx.x * kB + (int)threadIdx.x, (int)gridDim.x * kB, r);
+    const HistSums t = block_sums<kB>(r);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = t.F;
+        part[3 * blockIdx.x + 1] = t.m;
+        part[3 * blockIdx.x + 2] = t.s;
     }
+}
+
+__global__ void __launch_bounds__(kB) k_entropy_final(int which, int nparts, const double *__restrict__ part,
+                                                      DevScalars *sc)
+{
+    HistSums r{0.0, 0.0, 0.0};
+    for (int k = (int)threadIdx.x; k < nparts; k += kB) {
+        r.F += part[3 * k];
+        r.m += part[3 * k + 1];
+        r.s += part[3 * k + 2];
+    }
+    const HistSums t = block_sums<kB>(r);
+    if (threadIdx.x == 0) entropy_publish(which, t, sc);
 }
 
 // Selector features of the pending step (after the candidate entropy kernel).
@@ -465,10 +643,13 @@ inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP
 template <int D, int L>
 void launch_query_t(const QueryArgs &a, long long maxq, hipStream_t s)
 {
+    // at most 2048 workgroups (eight per CU) striding over the queries: enough
+    // waves to fill the chip, and few idle ones when the count on the device is
+    // far below the bound maxq
     constexpr int GPB = kB / L;
     long long blocks = (maxq + GPB - 1) / GPB;
     if (blocks < 1) blocks = 1;
-    if (blocks > 16384) blocks = 16384;
+    if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL((k_query<D, L>), dim3((unsigned)blocks), dim3(kB), 0, s, a);
 }
 
@@ -499,7 +680,7 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
 {
     if (c->n == 0) return NNC_OK;
     const int parity = (int)(c->t & 1);
-    const int blocks = blocks_for(c->n, kB);
+    const int blocks = blocks_for(c->n, kB) < kIngestBlocks ? blocks_for(c->n, kB) : kIngestBlocks;
     if (c->d == 2)
         hipLaunchKernelGGL(k_ingest<2>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->cell,
                            c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
@@ -543,9 +724,10 @@ int launch_grid_build(nnc_ctx *c, const float *pos)
     return check();
 }
 
-int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init)
+namespace {
+
+QueryArgs query_args(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init)
 {
-    if (c->n == 0) return NNC_OK;
     QueryArgs a;
     a.pos = c->pos_cur;
     a.sorted = c->grid.sorted;
@@ -563,7 +745,7 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
     a.nn = c->nn;
     a.stamp = c->stamp;
     a.hist = c->hist_fail;
-    a.touched = c->touched_fail;
+    a.touched = nullptr;  // the entropy scans the histogram
     a.d1 = c->d1;
     a.d2 = c->d2;
     a.e = c->e;
@@ -571,6 +753,11 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
     a.sc = c->sc;
     a.guard = c->guard;
     a.K = c->K;
+    return a;
+}
+
+void launch_pointwise(nnc_ctx *c, const QueryArgs &a)
+{
     const long long maxq = c->n;
     if (c->d == 2) {
         if (c->lanes == 64) launch_query_t<2, 64>(a, maxq, c->stream);
@@ -583,15 +770,59 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
         else if (c->lanes == 1) launch_query_t<3, 1>(a, maxq, c->stream);
         else launch_query_t<3, 16>(a, maxq, c->stream);
     }
+}
+
+}  // namespace
+
+int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init)
+{
+    if (c->n == 0) return NNC_OK;
+    launch_pointwise(c, query_args(c, list, count_dev, all, init));
+    return check();
+}
+
+// All points, right after a grid build: tiled (then the widening pass over the
+// points it left), or pointwise.
+int launch_query_all(nnc_ctx *c, int init)
+{
+    if (c->n == 0) return NNC_OK;
+    const bool tiled = (c->flags & NNC_QUERY_TILED) ||
+                       (!(c->flags & NNC_QUERY_POINTWISE) && c->n >= kTiledMinN);
+    if (!tiled) return launch_query(c, nullptr, nullptr, 1, init);
+    const int R = c->d == 3 ? 9 : 3;
+    const double occ = (double)c->n / (double)c->ncell;
+    int TX = (int)(0.6 * kNbMax / (R * (occ > 1.0 ? occ : 1.0))) - 2;
+    TX = TX < 4 ? 4 : TX;
+    TX = TX > kTXMax ? kTXMax : TX;
+    TX = TX > c->G ? c->G : TX;
+    const long long nseg = (c->G + TX - 1) / TX;
+    const long long rows = c->d == 3 ? (long long)c->G * c->G : c->G;
+    const long long tiles = rows * nseg;
+    if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
+    const QueryArgs a = query_args(c, nullptr, nullptr, 1, init);
+    if (c->d == 2)
+        hipLaunchKernelGGL(k_query_tiled<2>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, (int)nseg,
+                           c->wide, c->rec);
+    else
+        hipLaunchKernelGGL(k_query_tiled<3>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, (int)nseg,
+                           c->wide, c->rec);
+    hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, a, c->grid.rank,
+                       (const int4 *)c->rec);
+    launch_pointwise(c, query_args(c, c->wide, &c->sc->nwide, 0, init));
     return check();
 }
 
 int launch_entropy(nnc_ctx *c, int which)
 {
-    if (which == 0)
-        hipLaunchKernelGGL(k_entropy, dim3(1), dim3(1024), 0, c->stream, 0, c->hist_fail, c->touched_fail, c->sc);
-    else
-        hipLaunchKernelGGL(k_entropy, dim3(1), dim3(1024), 0, c->stream, 1, c->hist_cand, c->touched_cand, c->sc);
+    int *hist = which == 0 ? c->hist_fail : c->hist_cand;
+    const int ncell4 = (c->ncell + 3) / 4;
+    if (ncell4 > kEntropyOneGroup4) {
+        hipLaunchKernelGGL(k_entropy_part, dim3(kEntropyParts), dim3(kB), 0, c->stream, hist, ncell4, c->ent_part);
+        hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(kB), 0, c->stream, which, kEntropyParts,
+                           (const double *)c->ent_part, c->sc);
+    } else {
+        hipLaunchKernelGGL(k_entropy, dim3(1), dim3(1024), 0, c->stream, which, hist, ncell4, c->sc);
+    }
     return check();
 }
 
@@ -599,7 +830,7 @@ int launch_cand_hist(nnc_ctx *c)
 {
     const int blocks = c->n > 0 ? (blocks_for(c->n, kB) < 4096 ? blocks_for(c->n, kB) : 4096) : 1;
     hipLaunchKernelGGL(k_cand_hist, dim3(blocks), dim3(kB), 0, c->stream, c->frontier, c->cell, c->hist_cand,
-                       c->touched_cand, c->sc);
+                       c->sc);
     return check();
 }
 

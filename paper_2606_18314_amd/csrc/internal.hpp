@@ -11,6 +11,8 @@ namespace nnc {
 // Bits of the device error word.
 enum : unsigned { kErrNonFinite = 1u, kErrEps = 2u, kErrSpin = 4u, kErrOverflow = 8u };
 
+constexpr int kEntropyParts = 256;  // workgroups of the split entropy reduction
+
 // Scalars that live on the device so that a step never waits for the host.
 // The clock and the displacement maximum are double-buffered by step parity:
 // step t reads S[(t-1)&1], writes S[t&1]; its ingest accumulates into dmax[t&1].
@@ -25,7 +27,8 @@ struct DevScalars {
     int ntouched;            // cells met by those failures
     int ncand_touched;       // cells met by the candidates (on demand)
     unsigned err;            // kErr* bits
-    int pad0, pad1;
+    int nwide;               // all-point query: points left to the widening pass
+    int pad1;
     // results of the entropy kernel: [0] failures, [1] candidates
     double H[2];
     int m[2];
@@ -87,12 +90,16 @@ struct nnc_ctx {
     nnc::Grid grid;
     // frontier and histograms
     int32_t *frontier;
-    int32_t *hist_fail, *touched_fail;
-    int32_t *hist_cand, *touched_cand;
+    int32_t *hist_fail, *hist_cand;   // per-cell counts of failures / candidates
     unsigned long long *status;   // look-back tile descriptors
     int nstatus;
     nnc::DevScalars *sc;
     nnc::DevSync *sync;
+    // all-point query: points whose search must widen past the first block, and
+    // the tiled pass's results in slot order (nn, d1, d2 bits, done flag)
+    int32_t *wide;
+    int4 *rec;
+    double *ent_part;             // partial sums of the split entropy reduction
     // audit scratch
     int32_t *a_nn;
     float *a_d1, *a_d2;
@@ -129,6 +136,7 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew);
 int launch_filter(nnc_ctx *c, float eps_declared);
 int launch_grid_build(nnc_ctx *c, const float *pos);
 int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init);
+int launch_query_all(nnc_ctx *c, int init);
 int launch_entropy(nnc_ctx *c, int which);
 int launch_cand_hist(nnc_ctx *c);
 int launch_audit(nnc_ctx *c);

@@ -45,6 +45,37 @@ __device__ __forceinline__ void add_C(DevScalars *sc, int delta)
     if (lane_id() == 0 && w != 0) atomicAdd(&sc->C, w);
 }
 
+// Per-workgroup publication of the ingest results: the largest squared
+// displacement and the change of the occupied-cell count, reduced over the
+// workgroup first so that one atomic per quantity leaves each workgroup (the
+// words are shared by every workgroup of the launch).
+template <int NT>
+__device__ __forceinline__ void publish_ingest(DevScalars *sc, int parity, float sq, int dC)
+{
+    constexpr int NW = NT / 64;
+    __shared__ float s_sq[NW];
+    __shared__ int s_dc[NW];
+    sq = wave_max(sq);
+    dC = wave_sum(dC);
+    const int w = (int)(threadIdx.x >> 6);
+    if (lane_id() == 0) {
+        s_sq[w] = sq;
+        s_dc[w] = dC;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.0f;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            m = fmaxf(m, s_sq[k]);
+            c += s_dc[k];
+        }
+        if (c != 0) atomicAdd(&sc->C, c);
+        if (m > 0.0f) atomicMax(&sc->dmax[parity], __float_as_uint(m));
+    }
+}
+
 // Clock advance shared by both filter variants: every workgroup derives S_t
 // from the same two words; one leader publishes it.
 __device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, float eps_decl, bool leader)
@@ -64,39 +95,148 @@ __device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, floa
 // Normalised entropy (Definition 2) of the failures (which = 0) or candidates
 // (which = 1) over the touched cells, computed by one workgroup of NT threads;
 // clears the histogram entries and counters it consumed.
+// Sum of a double over a workgroup of NT threads; the result is valid in thread 0.
 template <int NT>
-__device__ void entropy_block(int which, int *__restrict__ hist, const int *__restrict__ touched, DevScalars *sc)
+__device__ __forceinline__ double block_sum(double v)
 {
     __shared__ double s_acc[NT / 64];
-    const int m = which == 0 ? sc->ntouched : sc->ncand_touched;
-    const int F = which == 0 ? sc->nfail : sc->nfront;
+    v = wave_sum(v);
+    if (lane_id() == 0) s_acc[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) tot += s_acc[k];
+    return tot;
+}
+
+// This thread's share (k = k0, k0 + stride, ...) of sum n_k ln n_k over the touched
+// cells; clears the histogram entries it reads.
+__device__ __forceinline__ double entropy_terms(int m, int *__restrict__ hist, const int *__restrict__ touched,
+                                                int k0, int stride)
+{
     double acc = 0.0;
-    for (int k = threadIdx.x; k < m; k += NT) {
+    for (int k = k0; k < m; k += stride) {
         const int c = touched[k];
         const int nk = hist[c];
         hist[c] = 0;
         acc += (double)nk * log((double)nk);
     }
-    acc = wave_sum(acc);
-    if (lane_id() == 0) s_acc[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < NT / 64; ++k) tot += s_acc[k];
-        const int C = sc->C;
-        double H = 0.0;
-        if (F > 0 && C > 1) H = (log((double)F) - tot / (double)F) / log((double)C);
-        sc->H[which] = H;
-        sc->m[which] = m;
-        sc->F[which] = F;
-        sc->Cres[which] = C;
-        if (which == 0) {
-            sc->nfail = 0;
-            sc->ntouched = 0;
-        } else {
-            sc->ncand_touched = 0;
+    return acc;
+}
+
+// H = (ln F - sum n ln n / F) / ln C (0 when F = 0 or C <= 1); publishes the
+// result and resets the counters of the histogram it consumed.  One thread.
+__device__ __forceinline__ void entropy_finish(int which, double tot, DevScalars *sc)
+{
+    const int m = which == 0 ? sc->ntouched : sc->ncand_touched;
+    const int F = which == 0 ? sc->nfail : sc->nfront;
+    const int C = sc->C;
+    double H = 0.0;
+    if (F > 0 && C > 1) H = (log((double)F) - tot / (double)F) / log((double)C);
+    sc->H[which] = H;
+    sc->m[which] = m;
+    sc->F[which] = F;
+    sc->Cres[which] = C;
+    if (which == 0) {
+        sc->nfail = 0;
+        sc->ntouched = 0;
+    } else {
+        sc->ncand_touched = 0;
+    }
+}
+
+// Normalised entropy (Definition 2) of the failures (which = 0) or candidates
+// (which = 1) over the touched cells, computed by one workgroup of NT threads.
+template <int NT>
+__device__ void entropy_block(int which, int *__restrict__ hist, const int *__restrict__ touched, DevScalars *sc)
+{
+    const int m = which == 0 ? sc->ntouched : sc->ncand_touched;
+    const double tot = block_sum<NT>(entropy_terms(m, hist, touched, (int)threadIdx.x, NT));
+    if (threadIdx.x == 0) entropy_finish(which, tot, sc);
+}
+
+// Histogram-scan form of the entropy reduction, for a histogram without a list of
+// touched cells: this thread's share of (F, m, sum n ln n) over the int4 groups
+// k0, k0 + stride, ... of hist (zero-padded to a multiple of four cells); clears
+// the nonzero groups it reads.  Four groups are loaded before any is cleared.
+struct HistSums {
+    double F, m, s;
+};
+
+__device__ __forceinline__ void hist_terms(int *__restrict__ hist, int ncell4, int k0, int stride, HistSums &r)
+{
+    int4 *h4 = reinterpret_cast<int4 *>(hist);
+    for (int k = k0; k < ncell4; k += 4 * stride) {
+        int4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = k + u * stride;
+            v[u] = idx < ncell4 ? h4[idx] : make_int4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if ((v[u].x | v[u].y | v[u].z | v[u].w) == 0) continue;
+            h4[k + u * stride] = make_int4(0, 0, 0, 0);
+            const int c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (c[e] > 0) {
+                    r.F += (double)c[e];
+                    r.m += 1.0;
+                    r.s += (double)c[e] * log((double)c[e]);
+                }
+            }
         }
     }
+}
+
+// Workgroup sum of HistSums; valid in thread 0.
+template <int NT>
+__device__ __forceinline__ HistSums block_sums(HistSums r)
+{
+    __shared__ double s_v[3][NT / 64];
+    r.F = wave_sum(r.F);
+    r.m = wave_sum(r.m);
+    r.s = wave_sum(r.s);
+    if (lane_id() == 0) {
+        s_v[0][threadIdx.x >> 6] = r.F;
+        s_v[1][threadIdx.x >> 6] = r.m;
+        s_v[2][threadIdx.x >> 6] = r.s;
+    }
+    __syncthreads();
+    HistSums t{0.0, 0.0, 0.0};
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) {
+            t.F += s_v[0][k];
+            t.m += s_v[1][k];
+            t.s += s_v[2][k];
+        }
+    return t;
+}
+
+// H from the sums (F = number of items, m = cells they meet); one thread.
+__device__ __forceinline__ void entropy_publish(int which, const HistSums &t, DevScalars *sc)
+{
+    const int F = (int)t.F, C = sc->C;
+    double H = 0.0;
+    if (F > 0 && C > 1) H = (log(t.F) - t.s / t.F) / log((double)C);
+    sc->H[which] = H;
+    sc->m[which] = (int)t.m;
+    sc->F[which] = F;
+    sc->Cres[which] = C;
+}
+
+// Slot of each lane with pred set in a list whose length is *counter: one atomic
+// per wave (lanes that are not active take no part).  -1 where pred is false.
+__device__ __forceinline__ int wave_append(int *counter, bool pred)
+{
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return -1;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(counter, (int)__popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + rank_below(m) : -1;
 }
 
 struct QueryArgs {
@@ -338,6 +478,38 @@ __device__ __forceinline__ double query_margin(double St, double S_grid)
     return kFuzz + drift * (1.0 + kRel);
 }
 
+// The new certificate of point i from its exact top-2 (old: its previous nearest
+// neighbour): distances, expiry key, stamp, failure flag, failure histogram.
+__device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old)
+{
+    const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
+    a.nn[i] = t.nn;
+    a.d1[i] = d1;
+    a.d2[i] = d2;
+    a.e[i] = expiry(St, d1, d2, a.guard, a.K);
+    a.stamp[i] = a.t;
+    const bool f = !a.init && t.nn != old;
+    a.fail[i] = f ? 1 : 0;
+    if (a.touched == nullptr) {
+        // histogram only (the entropy scans it): no shared counters
+        if (f) atomicAdd(&a.hist[a.cell[i]], 1);
+        return;
+    }
+    // failure count and first touch of each cell: one counter atomic per wave
+    const unsigned long long fm = __ballot(f);
+    if (fm != 0) {
+        if ((int)lane_id() == __ffsll((long long)fm) - 1) atomicAdd(&a.sc->nfail, (int)__popcll(fm));
+        int c = 0;
+        bool first = false;
+        if (f) {
+            c = a.cell[i];
+            first = atomicAdd(&a.hist[c], 1) == 0;
+        }
+        const int at = wave_append(&a.sc->ntouched, first);
+        if (first) a.touched[at] = c;
+    }
+}
+
 // Query q of a scene (the q-th candidate, or the q-th slot when recomputing all
 // points) by the L lanes of one group; lane 0 writes the new certificate, its
 // expiry key, stamp and failure flag, and counts a failure in the histogram.
@@ -363,21 +535,7 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     Top2 t;
     t.init();
     group_search<D, L>(a, x, y, z, i, margin, lane, t);
-    if (lane == 0) {
-        const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
-        a.nn[i] = t.nn;
-        a.d1[i] = d1;
-        a.d2[i] = d2;
-        a.e[i] = expiry(St, d1, d2, a.guard, a.K);
-        a.stamp[i] = a.t;
-        const bool f = !a.init && t.nn != old;
-        a.fail[i] = f ? 1 : 0;
-        if (f) {
-            atomicAdd(&a.sc->nfail, 1);
-            const int c = a.cell[i];
-            if (atomicAdd(&a.hist[c], 1) == 0) a.touched[atomicAdd(&a.sc->ntouched, 1)] = c;
-        }
-    }
+    if (lane == 0) write_certificate(a, i, t, St, old);
 }
 
 // Selector features of one scene-step (the same six numbers for a single scene

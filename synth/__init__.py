@@ -160,12 +160,12 @@ def make_trajectory(family: str, n: int, d: int, steps: int, eps: float, seed) -
 
 # --- the workload configurations -------------------------------------------------
 
-def config1(steps: int = 50) -> Trajectory:
+def plane_1k(steps: int = 50) -> Trajectory:
     """N = 1000 uniform points in the unit square, Brownian steps clipped to 1e-3."""
     return make_trajectory("uniform_brownian", 1000, 2, steps, 1e-3, 1)
 
 
-def config2(family: str, n: int = 16000, steps: int = 200) -> Trajectory:
+def cube_16k(family: str, n: int = 16000, steps: int = 200) -> Trajectory:
     """N = 16000 points in the unit cube, eps = 5e-4, one of the five families."""
     return make_trajectory(family, n, 3, steps, 5e-4, 2000 + FAMILIES.index(family))
 

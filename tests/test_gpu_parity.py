@@ -87,8 +87,8 @@ def test_allpairs_subset_mode(nnc):
     assert np.array_equal(bits(host(d2)), bits(od2))
 
 
-def test_allpairs_config2_size(nnc):
-    tr = synth.config2("clustered_drift", steps=1)
+def test_allpairs_cube_16k_size(nnc):
+    tr = synth.cube_16k("clustered_drift", steps=1)
     pos = tr.frames[1]
     nn, d1, d2 = nnc.allpairs_top2(dev(pos))
     onn, od1, od2 = model.top2(pos)
@@ -99,10 +99,10 @@ def test_allpairs_config2_size(nnc):
 
 # --- the state machine ---------------------------------------------------------------
 
-def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0):
+def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0, all_query="auto"):
     d, n = traj.d, traj.n
     frames = [dev(f) for f in traj.frames]
-    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes)
+    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query)
     assert ctx.grid_g == G
     sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard)
     ctx.init_certificates(frames[0])
@@ -140,16 +140,16 @@ def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_ev
     return audit
 
 
-def test_config1_every_step(nnc):
-    run_parity(nnc, synth.config1(), G=15)
+def test_plane_1k_every_step(nnc):
+    run_parity(nnc, synth.plane_1k(), G=15)
 
 
-def test_config1_rebuild_every_step(nnc):
-    run_parity(nnc, synth.config1(steps=20), G=15, strategy="rebuild")
+def test_plane_1k_rebuild_every_step(nnc):
+    run_parity(nnc, synth.plane_1k(steps=20), G=15, strategy="rebuild")
 
 
 @pytest.mark.parametrize("family", synth.FAMILIES)
-def test_config2_families_reduced(nnc, family):
+def test_cube_16k_families_reduced(nnc, family):
     tr = synth.make_trajectory(family, 4000, 3, 40, 5e-4, 2000 + synth.FAMILIES.index(family))
     run_parity(nnc, tr, G=9, strategy="alternate")
 
@@ -162,15 +162,38 @@ def test_lanes_per_query_and_fine_grids(nnc, lanes, d):
     run_parity(nnc, tr, G=64 if d == 3 else 200, lanes=lanes, strategy="alternate")
 
 
+@pytest.mark.parametrize("lanes", [1, 16])
+@pytest.mark.parametrize("G", [1, 2, 5, 33])
+@pytest.mark.parametrize("d", [2, 3])
+def test_tiled_all_point_query(nnc, d, G, lanes):
+    """The cell-tiled query of every point (initialisation and each rebuild): from one
+    cell (the neighbourhood exceeds the LDS stage, pointwise fallback) to grids fine
+    enough that many points go through the widening pass."""
+    tr = synth.make_trajectory("clustered_drift", 5000, d, 5, 5e-4, 300 + d)
+    run_parity(nnc, tr, G=G, strategy="rebuild", lanes=lanes, all_query="tiled")
+
+
+@pytest.mark.parametrize("family", ["uniform_brownian", "ring_rotation", "adversarial_crossing"])
+def test_tiled_all_point_query_families(nnc, family):
+    tr = synth.make_trajectory(family, 6000, 3, 8, 5e-4, 2000 + synth.FAMILIES.index(family))
+    run_parity(nnc, tr, G=20, strategy="alternate", all_query="tiled")
+
+
+def test_tiled_is_the_default_from_65536_points(nnc):
+    """N = 66000 in the plane: the automatic choice tiles; two rebuilds checked."""
+    tr = synth.make_trajectory("uniform_brownian", 66000, 2, 2, 5e-4, 4242)
+    run_parity(nnc, tr, G=128, strategy="rebuild")
+
+
 @pytest.mark.parametrize("family", synth.FAMILIES)
-def test_config2_families_full_size(nnc, family):
+def test_cube_16k_families_full_size(nnc, family):
     """N = 16000, d = 3 at the default grid (G = 15), first 6 steps, every array checked."""
-    tr = synth.config2(family, steps=6)
+    tr = synth.cube_16k(family, steps=6)
     run_parity(nnc, tr, G=15)
 
 
 def test_guard_zero_literal_key(nnc):
-    run_parity(nnc, synth.config1(steps=15), G=15, guard=0.0)
+    run_parity(nnc, synth.plane_1k(steps=15), G=15, guard=0.0)
 
 
 # --- edge cases ----------------------------------------------------------------------
@@ -230,7 +253,7 @@ def test_lattice_scene_with_ties(nnc):
 # --- API behaviour --------------------------------------------------------------------
 
 def test_error_paths(nnc):
-    tr = synth.config1(steps=2)
+    tr = synth.plane_1k(steps=2)
     ctx = nnc.NNCert(1000, 2, grid_g=15)
     with pytest.raises(nnc.NNCError) as ei:
         ctx.repair()
@@ -256,7 +279,7 @@ def test_error_paths(nnc):
 
 
 def test_snapshot_restore_and_determinism(nnc):
-    tr = synth.config2("uniform_brownian", n=4000, steps=6)
+    tr = synth.cube_16k("uniform_brownian", n=4000, steps=6)
     frames = [dev(f) for f in tr.frames]
     ctx = nnc.NNCert(4000, 3, grid_g=9)
     ctx.init_certificates(frames[0])
@@ -281,7 +304,7 @@ def test_snapshot_restore_and_determinism(nnc):
 
 
 def test_forced_frontier_list(nnc):
-    tr = synth.config1(steps=1)
+    tr = synth.plane_1k(steps=1)
     ctx = nnc.NNCert(1000, 2, grid_g=15)
     sc = model.OracleScene(d=2, n=1000, G=15)
     ctx.init_certificates(dev(tr.frames[0]))
@@ -304,7 +327,7 @@ def test_large_scene_uses_the_multi_tile_path(nnc):
 def test_graph_replays_match_eager(nnc):
     """A captured step sequence, replayed several times from the same restored state,
     gives the eager result every time (the look-back epochs never repeat)."""
-    tr = synth.config2("adversarial_crossing", n=6000, steps=12)
+    tr = synth.cube_16k("adversarial_crossing", n=6000, steps=12)
     frames = [dev(f) for f in tr.frames]
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -345,7 +368,7 @@ def test_audit_between_steps(nnc):
     """Every step audited (the all-pairs scratch rewritten) between steps, at a cell
     count so small that few look-back descriptors are allocated: regression test for
     descriptor sizing (a step kernel once indexed the descriptors per workgroup)."""
-    tr = synth.config2("uniform_brownian", n=16000, steps=8)
+    tr = synth.cube_16k("uniform_brownian", n=16000, steps=8)
     frames = [dev(f) for f in tr.frames]
     ctx = nnc.NNCert(16000, 3, grid_g=15)
     sc = model.OracleScene(d=3, n=16000, G=15)

@@ -248,7 +248,7 @@ def test_lattice_enumeration_no_missed_failure_and_superset():
 # --- special cases -----------------------------------------------------------------
 
 def test_zero_motion_breaks_nothing():
-    tr = synth.config1(steps=1)
+    tr = synth.plane_1k(steps=1)
     sc = model.OracleScene(d=2, n=1000, G=15)
     sc.init_certificates(tr.frames[0])
     res = sc.step(tr.frames[0])
@@ -289,8 +289,8 @@ def test_tiny_scenes():
 
 # --- the whole state machine on the workloads -------------------------------------
 
-def test_config1_every_step_no_miss_and_fail_set_is_the_true_change():
-    tr = synth.config1()
+def test_plane_1k_every_step_no_miss_and_fail_set_is_the_true_change():
+    tr = synth.plane_1k()
     sc = model.OracleScene(d=2, n=1000, G=15)
     sc.init_certificates(tr.frames[0])
     prev_nn = model.top2(tr.frames[0])[0]
@@ -305,7 +305,7 @@ def test_config1_every_step_no_miss_and_fail_set_is_the_true_change():
 
 
 @pytest.mark.parametrize("family", synth.FAMILIES)
-def test_config2_families_no_miss_reduced(family):
+def test_cube_16k_families_no_miss_reduced(family):
     tr = synth.make_trajectory(family, 3000, 3, 25, 5e-4, 2000 + synth.FAMILIES.index(family))
     sc = model.OracleScene(d=3, n=3000, G=9)
     sc.init_certificates(tr.frames[0])
@@ -321,7 +321,7 @@ def test_config2_families_no_miss_reduced(family):
 def test_literal_algorithm_with_stale_certificates_misses_failures():
     """Read step by step with the clearance of possibly stale certificates, the
     filter of Algorithm 1 does miss failures; the appendix's clock does not."""
-    tr = synth.config1()
+    tr = synth.plane_1k()
     literal = model.OracleScene(d=2, n=1000, G=15, rule="literal")
     clock = model.OracleScene(d=2, n=1000, G=15)
     literal.init_certificates(tr.frames[0])
@@ -338,7 +338,7 @@ def test_literal_algorithm_with_stale_certificates_misses_failures():
 
 
 def test_first_step_literal_equals_clock_without_guard():
-    tr = synth.config1(steps=1)
+    tr = synth.plane_1k(steps=1)
     a = model.OracleScene(d=2, n=1000, G=15, rule="literal", guard=0.0)
     b = model.OracleScene(d=2, n=1000, G=15, rule="clock", guard=0.0)
     a.init_certificates(tr.frames[0])
