@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--regret-scenes", type=int, default=40)
     ap.add_argument("--regret-steps", type=int, default=25)
-    ap.add_argument("--grid", default="auto", help="'auto' (tuned per family) or an integer G for all")
+    ap.add_argument("--grid", default="table",
+                    help="'table' (the committed tuning table, paper_2606_18314_amd/tuned_cube16k.json), "
+                         "'auto' (tuned per family now) or an integer G for all")
     ap.add_argument("--grid-json", default="", help='fixed {"family": [G, lanes], ...} instead of tuning')
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -64,6 +66,11 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line on stderr per finished piece of work (long runs stay visibly alive)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def src_hash(*names):
@@ -143,6 +150,7 @@ def batched_leg(args, nnc, synth, autotune, torch):
         ms = e0.elapsed_time(e1)
         st = b.stats()
         rebuilt = sum(x["strategy"] for x in st) / len(st)
+        progress(f"batched {name}: {ms / steps:.4f} ms/step")
         res[name] = {"value": total * steps / (ms / 1e3), "ms_per_step": ms / steps,
                      "last_step_rebuild_fraction": rebuilt,
                      "errors": sum(1 for x in st if x["err"] != 0)}
@@ -319,9 +327,10 @@ def sweep_leg(args, nnc, synth, torch):
     # HBM roofline of the rebuild's all-point query at this size
     reb = [r for r in rows if r.get("mode") == "diffuse"]
     q_us = sum(r["rebuild_query_us"] for r in reb) / len(reb)
-    qbytes = n * (8 * d + 29) + 4 * (G ** d + 1)
+    C_mean = sum(r["C"] for r in reb) / len(reb)
+    qbytes = n * (8 * d + 29) + 4 * (C_mean + 1)
     rep50 = [r for r in rows if r.get("mode") == "diffuse" and r["target_fraction"] == 0.5][0]
-    rbytes = rep50["candidates"] * (4 * d + 4 + 25) + n * (4 * d + 4) + 4 * (G ** d + 1)
+    rbytes = rep50["candidates"] * (4 * d + 4 + 25) + n * (4 * d + 4) + 4 * (rep50["C"] + 1)
     ctx.close()
     return {"n": n, "d": d, "G": G, "lanes": lanes, "lanes_table_ms": lanes_table, "rows": rows,
             "roofline_rebuild_query": {"bound": "hbm", "achieved": qbytes / (q_us * 1e-6) / 1e9,
@@ -338,8 +347,8 @@ def sweep_leg(args, nnc, synth, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the maintenance path of this "
-              f"build is single-GPU, see DESIGN.md for how it would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the certificate-maintenance "
+              f"path of this library runs on a single GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -363,6 +372,14 @@ def main():
 
     tuning = {}
     lanes = {}
+    table_path = os.path.join(ROOT, "paper_2606_18314_amd", "tuned_cube16k.json")
+    if not args.grid_json and args.grid == "table":
+        if os.path.exists(table_path):
+            tab = json.load(open(table_path))["scenes"]
+            args.grid_json = json.dumps({f: [tab[f]["G"], tab[f]["lanes"]] for f in fams})
+        else:
+            args.grid = "auto"
+    grid_source = "table" if args.grid == "table" else ("fixed" if args.grid_json else args.grid)
     if args.grid_json:
         fixed = json.loads(args.grid_json)
         grids = {f: int(fixed[f][0]) for f in fams}
@@ -469,6 +486,7 @@ def main():
                     g.replay()
             graph_ms = timed(replay)
             end_audit = {f: ctxs[f][0].oracle_verify() for f in fams}
+            progress(f"{strategy} {mode}: {graph_ms / K:.4f} ms/step")
             leg[mode] = {"value": pts_per_step * K / (graph_ms / 1e3), "ms_per_step": graph_ms / K,
                          "eager_value": pts_per_step * K / (eager_ms / 1e3), "eager_ms_per_step": eager_ms / K,
                          "end_state_missed": sum(a["n_missed"] for a in end_audit.values()),
@@ -500,7 +518,7 @@ def main():
                     for f in fams:
                         ctxs[f][0].restore(snaps[f])
                     tot = {"steps": 0, "n_missed": 0, "n_value_mismatch": 0, "n_detect": 0, "n_true_fail": 0,
-                           "H_fail_sum": 0.0, "H_cand_sum": 0.0}
+                           "H_fail_sum": 0.0, "H_cand_sum": 0.0, "C_sum": 0}
                     for t in range(W + 1, T + 1):
                         for f in fams:
                             c, st = ctxs[f]
@@ -518,12 +536,15 @@ def main():
                             tot["n_true_fail"] += a["n_true_fail"]
                             tot["H_fail_sum"] += hf["H"]
                             tot["H_cand_sum"] += hc["H"]
+                            tot["C_sum"] += hf["C"]
                     cert = {"scene_steps": tot["steps"], "n_missed": tot["n_missed"],
                             "n_value_mismatch": tot["n_value_mismatch"],
                             "candidate_fraction": tot["n_detect"] / (tot["steps"] * N),
                             "failure_fraction": tot["n_true_fail"] / (tot["steps"] * N),
                             "mean_H_fail": tot["H_fail_sum"] / tot["steps"],
-                            "mean_H_candidates": tot["H_cand_sum"] / tot["steps"]}
+                            "mean_H_candidates": tot["H_cand_sum"] / tot["steps"],
+                            "mean_occupied_cells": tot["C_sum"] / tot["steps"]}
+                progress(f"{strategy} certification done")
                 audits[strategy] = cert
                 leg["certification"] = cert
             for f in fams:
@@ -551,6 +572,7 @@ def main():
         ms = e0.elapsed_time(e1)
         launch_us = ms * 1e3 / (ksteps * len(fams))
         ops = (3 * D) * N * (N - 1)           # 3d-1 distance operations + 1 comparison per pair
+        progress(f"allpairs: {ms / ksteps:.4f} ms/step")
         legs["allpairs"] = {"value": pts_per_step * ksteps / (ms / 1e3), "ms_per_step": ms / ksteps,
                             "steps": ksteps, "pairs_per_s": N * (N - 1) * ksteps * len(fams) / (ms / 1e3),
                             "kernel_avg_us": launch_us,
@@ -562,10 +584,12 @@ def main():
     # ---- frontier-fraction sweep at N = 2^20 -----------------------------------------------
     if "sweep" in legs_req:
         legs["sweep"] = sweep_leg(args, nnc, synth, torch)
+        progress("sweep done")
 
     # ---- batched scenes (512 scenes, log-uniform N, mixed d and families) ------------------
     if "batched" in legs_req:
         legs["batched"] = batched_leg(args, nnc, synth, autotune, torch)
+        progress("batched done")
 
     # ---- headline ------------------------------------------------------------------------
     head = legs.get("repair")
@@ -575,14 +599,14 @@ def main():
         q_us, q_cnt = kernel_avg["repair"]["query"]
         q_us *= 1e3
         cand = audits["repair"]["candidate_fraction"] if audits.get("repair") else None
+        occ_cells = audits["repair"]["mean_occupied_cells"] if audits.get("repair") else 0.0
         G = grids
         # algorithmic bytes of one repair query launch (per scene): each candidate reads its
         # coordinates and list entry and writes its certificate (nn, d1, d2, stamp 4 B each,
         # expiry 8 B, fail flag 1 B); every point of the visited blocks is read once
-        # (coordinates + grid slot); the cell-start table is read once.
-        mean_cells = sum(g ** D for g in G.values()) / len(G)
+        # (coordinates + grid slot); one cell-start entry per occupied cell.
         if cand is not None:
-            per_launch = cand * N * (4 * D + 4 + 25) + N * (4 * D + 4) + 4 * (mean_cells + 1)
+            per_launch = cand * N * (4 * D + 4 + 25) + N * (4 * D + 4) + 4 * (occ_cells + 1)
         else:
             per_launch = None
         roof = None
@@ -597,7 +621,8 @@ def main():
     out["config"] = {"workload": "cube_16k: N=16000 points, d=3, five motion families, eps=5e-4, "
                                  f"{K} timed steps after {W} warm-up steps; the five independent scenes "
                                  "advance on their own streams as branches of one HIP graph",
-                     "families": fams, "grid_g": grids, "lanes_per_query": lanes, "grid_tuning_ms": tuning, "strategy": "repair",
+                     "families": fams, "grid_g": grids, "lanes_per_query": lanes, "grid_tuning_ms": tuning,
+                     "grid_source": grid_source, "strategy": "repair",
                      "generator_seconds": round(gen_s, 2)}
     out["strategies"] = legs
 
@@ -639,6 +664,7 @@ def main():
                 done += 1
                 per_fam_steps[f] = t
             t += 1
+        progress(f"cpu baseline: {done} scene-steps in {spent:.1f} s")
         out["cpu_baseline"] = {"value": done * N / spent, "unit": "point-steps/s", "cores": model.threads(),
                                "kind": "oracle",
                                "sample": f"oracle step + repair (brute-force certificates of the candidates) of the "

@@ -142,3 +142,47 @@ def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(0.75, 1.0, 1.5, 2.0)
             if best is None or ms < best[0]:
                 best = (ms, grids, L)
     return best[1], best[2], table
+
+
+def tune_table(frames_by_scene: dict, d: int, eps: float, steps: int = 30, rounds: int = 3) -> dict:
+    """(G, lanes) per scene: the smallest median step time over ``rounds`` runs of
+    ``tune_grid`` on the scene's first ``steps`` transitions."""
+    out = {}
+    for name, frames in frames_by_scene.items():
+        runs = [tune_grid(frames, d, eps, steps=steps)[1] for _ in range(rounds)]
+        med = {k: sorted(r[k] for r in runs)[len(runs) // 2] for k in runs[0]}
+        best = min(med, key=med.get)
+        g, lanes = (int(v) for v in best.split("/"))
+        out[name] = {"G": g, "lanes": lanes, "ms_per_step": med[best], "median_ms": med}
+    return out
+
+
+def main():
+    """Tune the five-family N = 16000, d = 3 scenes and write the table bench.py uses."""
+    import argparse
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import synth
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--rounds", type=int, default=3)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_cube16k.json"))
+    args = ap.parse_args()
+    binding.load()
+    frames = {}
+    for f in synth.FAMILIES:
+        tr = synth.cube_16k(f, steps=args.steps + 1)
+        fr = torch.from_numpy(tr.frames).cuda()
+        frames[f] = [fr[t] for t in range(args.steps + 1)]
+    table = tune_table(frames, 3, 5e-4, steps=args.steps, rounds=args.rounds)
+    meta = {"device": torch.cuda.get_device_name(0), "steps": args.steps, "rounds": args.rounds,
+            "workload": "cube_16k: N = 16000, d = 3, eps = 5e-4, the five families"}
+    with open(args.out, "w") as fh:
+        json.dump({"meta": meta, "scenes": table}, fh, indent=1)
+    print(json.dumps({k: (v["G"], v["lanes"], v["ms_per_step"]) for k, v in table.items()}))
+
+
+if __name__ == "__main__":
+    main()
