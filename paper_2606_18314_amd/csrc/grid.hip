@@ -38,6 +38,7 @@ constexpr int kRows = 8;           // items per thread in the tile scans
 constexpr int kTile = kB * kRows;  // items per look-back tile
 constexpr int kSmallB = 1024;      // one-workgroup filter: threads
 constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
+constexpr int kSmallMaxN = 2 * kTile;  // scenes up to this size use the one-workgroup filter
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
 constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
@@ -693,8 +694,11 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
 int launch_filter(nnc_ctx *c, float eps_declared)
 {
     const int parity = (int)(c->t & 1);
-    if (c->n > (int64_t)kSmallB * kSmallRows && blocks_for(c->n, kTile) > c->nstatus) return NNC_E_INVAL;
-    if (c->n <= (int64_t)kSmallB * kSmallRows) {
+    // one workgroup only for small scenes: above two tiles the look-back version,
+    // whose tiles count in parallel, is faster (measured at N = 16000)
+    const bool small = c->n <= (int64_t)kSmallMaxN;
+    if (!small && blocks_for(c->n, kTile) > c->nstatus) return NNC_E_INVAL;
+    if (small) {
         hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(kSmallB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
                            eps_declared, c->frontier, c->fail);
     } else {
