@@ -54,8 +54,8 @@ def parse():
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--regret-scenes", type=int, default=40)
-    ap.add_argument("--regret-steps", type=int, default=25)
+    ap.add_argument("--regret-scenes", type=int, default=24)
+    ap.add_argument("--regret-steps", type=int, default=110)
     ap.add_argument("--grid", default="table",
                     help="'table' (the committed tuning table, paper_2606_18314_amd/tuned_cube16k.json), "
                          "'auto' (tuned per family now) or an integer G for all")
