@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--regret-scenes", type=int, default=24)
+    ap.add_argument("--regret-scenes", type=int, default=100)
     ap.add_argument("--regret-steps", type=int, default=110)
     ap.add_argument("--grid", default="table",
                     help="'table' (the committed tuning table, paper_2606_18314_amd/tuned_cube16k.json), "
@@ -114,7 +114,7 @@ def batched_leg(args, nnc, synth, autotune, torch):
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     s = torch.cuda.Stream()
-    grids, lanes, table = autotune.tune_batch(frames, ns, ds, stream=s)
+    grids, lanes, table = autotune.tune_batch(frames, ns, ds, eps_steps=8, stream=s)
     params, meta = selector.load_params()
     tau = float(meta.get("tau", 0.5)) if meta else 0.5
     total = sum(ns)

@@ -91,7 +91,8 @@ def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(1, 
     return best, {f"{g}/{l}": round(v, 5) for (g, l), v in times.items()}
 
 
-def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 16, factor: float = 1.0):
+def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 16, factor: float = 1.0,
+                cells_per_point: int = 8):
     """Per-scene cells per axis for a batch: start from the occupancy rule, read each
     scene's occupied-cell count C from the library, and refine G so that the occupied
     cells hold about ``target`` points (capped at 8x the rule and 2^22 cells)."""
@@ -107,40 +108,42 @@ def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 
         occ = n / C
         scale = min(8.0, max(1.0, (occ / target) ** (1.0 / d)))
         g = max(1, int(round(g0 * scale * factor)))
-        # at most 8 cells per point: a scene's grid is built by one workgroup
-        while g > 1 and (g ** d > MAX_CELLS or g ** d > 8 * max(int(n), 1)):
+        # at most cells_per_point cells per point: a scene's grid is built by one workgroup
+        while g > 1 and (g ** d > MAX_CELLS or g ** d > cells_per_point * max(int(n), 1)):
             g -= 1
         grids.append(g)
     return grids
 
 
-def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(0.75, 1.0, 1.5, 2.0), lanes=(1, 16, 32), policy: int = 0,
-               stream=None):
-    """Fastest (grid factor, lanes) for a batch over a few steps; returns (grids, lanes, table)."""
+def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(1.5, 2.0, 3.0), caps=(8, 16, 32, 64), lanes=(16, 32),
+               policy: int = 0, stream=None):
+    """Fastest (grid factor, cells-per-point cap, lanes) for a batch over a few steps;
+    returns (grids, lanes, table)."""
     s = stream or torch.cuda.Stream()
     table = {}
     best = None
     for L in lanes:
-        for f in factors:
-            grids = batch_grids(frames[0], ns, ds, lanes=L, factor=f)
-            with torch.cuda.stream(s):
-                b = binding.NNCBatch(ns, ds, grids=grids, lanes=L, stream=s.cuda_stream)
-                b.init(frames[0])
-                b.step(frames[1], policy)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            with torch.cuda.stream(s):
-                for t in range(2, eps_steps + 2):
-                    b.step(frames[t], policy)
-            e1.record(s)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / eps_steps
-            b.close()
-            table[f"{f}/{L}"] = round(ms, 4)
-            if best is None or ms < best[0]:
-                best = (ms, grids, L)
+        for cap in caps:
+            for f in factors:
+                grids = batch_grids(frames[0], ns, ds, lanes=L, factor=f, cells_per_point=cap)
+                with torch.cuda.stream(s):
+                    b = binding.NNCBatch(ns, ds, grids=grids, lanes=L, stream=s.cuda_stream)
+                    b.init(frames[0])
+                    b.step(frames[1], policy)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                with torch.cuda.stream(s):
+                    for t in range(2, eps_steps + 2):
+                        b.step(frames[t], policy)
+                e1.record(s)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / eps_steps
+                b.close()
+                table[f"{f}/{cap}/{L}"] = round(ms, 4)
+                if best is None or ms < best[0]:
+                    best = (ms, grids, L)
     return best[1], best[2], table
 
 
