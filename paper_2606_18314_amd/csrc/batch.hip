@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
     if (threadIdx.x == 0) s_m = 0;
     const double Sprev = sc->S[a.parity ^ 1];
     const float eps = sqrtf(__uint_as_float(sc->dmax[a.parity]));
-    const double St = advance_clock(sc, a.parity, -1.0f, threadIdx.x == 0);
+    const double St = advance_clock(sc, a.parity, -1.0f, threadIdx.x < 64);
     double ev[kFRows];
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {

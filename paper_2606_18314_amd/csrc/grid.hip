@@ -43,7 +43,7 @@ constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
 constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
 constexpr int kEntropyOneGroup4 = 1 << 15;
-constexpr int kIngestBlocks = 256;  // same-address atomics cost ~10 ns each across the XCDs  // histograms up to 2^17 cells: one-workgroup entropy
+constexpr int kIngestBlocks = 4096;  // at most 64 workgroups per spread slot  // histograms up to 2^17 cells: one-workgroup entropy
 
 __device__ __forceinline__ unsigned long long pack_status(unsigned epoch, int flag, unsigned v)
 {
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos
         cell[i] = c;
         dC = atomicAdd(&counts[c], 1) == 0;
     }
-    add_C(sc, dC);
+    publish_ingest_spread<kB>(sc, 0, 0.0f, dC);  // C is folded by the first filter
 }
 
 template <int D>
@@ -147,8 +147,8 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
                                                const int *__restrict__ rank, float *__restrict__ sorted,
                                                DevScalars *sc, int parity)
 {
-    // grid-stride, so that the launch has at most kIngestBlocks workgroups and as
-    // many pairs of atomics on the shared words
+    // grid-stride over at most kIngestBlocks workgroups, each adding its maximum and
+    // cell-count change into one of the spread slots
     float s = 0.0f;
     int dC = 0;
     const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
             atomicOr(&sc->err, kErrNonFinite);
         }
     }
-    publish_ingest<kB>(sc, parity, s, dC);
+    publish_ingest_spread<kB>(sc, parity, s, dC);
 }
 
 __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int n, DevScalars *sc, DevSync *sy,
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
     __shared__ unsigned s_base;
     take_ticket(sy, &s_tile, &s_epoch);
     const int tile = s_tile;
-    const double St = advance_clock(sc, parity, eps_decl, tile == 0 && threadIdx.x == 0);
+    const double St = advance_clock(sc, parity, eps_decl, tile == 0 && threadIdx.x < 64);
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
     const long long base = (long long)tile * kTile;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restri
     constexpr int PER = (NC + kSmallB - 1) / kSmallB;   // counts scanned per thread
     __shared__ int s_cnt[NC];
     __shared__ int s_w[NW];
-    const double St = advance_clock(sc, parity, eps_decl, threadIdx.x == 0);
+    const double St = advance_clock(sc, parity, eps_decl, threadIdx.x < 64);
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
     // all loads first, so that they are in flight together

@@ -36,6 +36,11 @@ struct DevScalars {
     int Cres[2];
     // audit counters
     unsigned long long audit[6];
+    // ingest results spread over kSpread words (workgroup b adds into slot b % kSpread),
+    // folded by the filter's leading wave: displacement maxima per parity, and
+    // changes of the occupied-cell count
+    unsigned dmax_part[2][64];
+    int dC_part[64];
 };
 
 // Ticket counter and epoch of the look-back scans.  Kept outside the state that

@@ -76,20 +76,60 @@ __device__ __forceinline__ void publish_ingest(DevScalars *sc, int parity, float
     }
 }
 
-// Clock advance shared by both filter variants: every workgroup derives S_t
-// from the same two words; one leader publishes it.
-__device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, float eps_decl, bool leader)
+// Clock advance shared by the filter variants, called by every thread of a full
+// workgroup: each wave derives S_t from the displacement maximum (the shared
+// word and its kSpread slots, one per lane); the leading wave publishes S_t,
+// folds the occupied-cell changes into C and clears the other parity's words.
+__device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, float eps_decl, bool leader_wave)
 {
-    const float eps = sqrtf(__uint_as_float(sc->dmax[parity]));
+    const int lane = (int)lane_id();
+    const float m = fmaxf(wave_max(__uint_as_float(sc->dmax_part[parity][lane])), __uint_as_float(sc->dmax[parity]));
+    const float eps = sqrtf(m);
     const double St = sc->S[parity ^ 1] + (double)eps;
-    if (leader) {
-        sc->S[parity] = St;
-        sc->eps = (double)eps;
-        sc->dmax[parity ^ 1] = 0u;
-        if (eps_decl >= 0.0f && (double)eps > (double)eps_decl * (1.0 + 0x1p-16) + 0x1p-20)
-            atomicOr(&sc->err, kErrEps);
+    if (leader_wave) {
+        const int dc = wave_sum(sc->dC_part[lane]);
+        sc->dC_part[lane] = 0;
+        sc->dmax_part[parity ^ 1][lane] = 0u;
+        if (lane == 0) {
+            sc->C += dc;
+            sc->S[parity] = St;
+            sc->eps = (double)eps;
+            sc->dmax[parity ^ 1] = 0u;
+            if (eps_decl >= 0.0f && (double)eps > (double)eps_decl * (1.0 + 0x1p-16) + 0x1p-20)
+                atomicOr(&sc->err, kErrEps);
+        }
     }
     return St;
+}
+
+// Ingest results of a workgroup into slot blockIdx % kSpread of the spread words
+// (the launch may have thousands of workgroups; a slot sees few of them).
+template <int NT>
+__device__ __forceinline__ void publish_ingest_spread(DevScalars *sc, int parity, float sq, int dC)
+{
+    constexpr int NW = NT / 64;
+    __shared__ float s_sq[NW];
+    __shared__ int s_dc[NW];
+    sq = wave_max(sq);
+    dC = wave_sum(dC);
+    const int w = (int)(threadIdx.x >> 6);
+    if (lane_id() == 0) {
+        s_sq[w] = sq;
+        s_dc[w] = dC;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.0f;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            m = fmaxf(m, s_sq[k]);
+            c += s_dc[k];
+        }
+        const int slot = (int)(blockIdx.x & 63);
+        if (c != 0) atomicAdd(&sc->dC_part[slot], c);
+        if (m > 0.0f) atomicMax(&sc->dmax_part[parity][slot], __float_as_uint(m));
+    }
 }
 
 // Normalised entropy (Definition 2) of the failures (which = 0) or candidates
