@@ -383,19 +383,22 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 }
 
 // All-point query (rebuild and initialisation, right after a grid build), tiled
-// by cells: a tile is a run of TX cells of one grid row (fixed y, z); its 3^(d-1)
-// neighbouring row segments are contiguous slot ranges, staged once in LDS, and
-// every point of the tile's cells scans its 3^d block from LDS, one thread per
-// point.  A point whose second neighbour is not enclosed by the first block is
-// appended to the widening list and finished by the pointwise query; a tile
-// whose neighbourhood exceeds the LDS capacity runs the pointwise search for
-// its points.  Results go to a slot-ordered record per point (coalesced), and
-// k_finish_all moves them to point order with one random 16-byte read per point
-// instead of six scattered stores.  Tiles are dealt to XCDs in contiguous ranges
-// (workgroups go to the eight XCDs round-robin), so neighbouring tiles share an L2.
+// by cells: a tile is a patch of TX x TY cells of one grid plane (fixed z); the
+// (TY + 2) x 3^(d-2) neighbouring row segments are contiguous slot ranges, staged
+// once in LDS, and every point of the tile's cells scans its 3^d block from LDS,
+// one thread per point.  A point whose second neighbour is not enclosed by the
+// first block is appended to the widening list and finished by the pointwise
+// query; a tile whose neighbourhood exceeds the LDS capacity runs the pointwise
+// search for its points.  Results go to a slot-ordered record per point
+// (coalesced), and k_finish_all moves them to point order with one random 16-byte
+// read per point instead of six scattered stores.  Tiles are dealt to XCDs in
+// contiguous ranges (workgroups go to the eight XCDs round-robin), so
+// neighbouring tiles share an L2.
 constexpr int kTB = 256;       // threads per tile
 constexpr int kNbMax = 3072;   // neighbourhood points staged in LDS
-constexpr int kTXMax = 256;    // cells per tile
+constexpr int kTXMax = 256;    // cells per tile row
+constexpr int kTYMax = 8;      // rows per tile
+constexpr int kCsMax = 2304;   // cell-start entries of a tile's neighbourhood rows
 
 __device__ __forceinline__ int xcd_tile(int b, int nt)
 {
@@ -405,51 +408,58 @@ __device__ __forceinline__ int xcd_tile(int b, int nt)
 }
 
 template <int D>
-__global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int nseg, int *__restrict__ wide,
-                                                     int4 *__restrict__ rec)
+__global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY, int nsx, int nsy,
+                                                     int *__restrict__ wide, int4 *__restrict__ rec)
 {
-    constexpr int R = D == 3 ? 9 : 3;  // neighbourhood rows, (dy, dz) with dy fastest
-    constexpr int MID = R / 2;         // dy = dz = 0
+    constexpr int RMAX = D == 3 ? 3 * (kTYMax + 2) : kTYMax + 2;
     __shared__ float s_x[kNbMax], s_y[kNbMax], s_z[D == 3 ? kNbMax : 1];
     __shared__ int s_j[kNbMax];
-    __shared__ int s_cs[R][kTXMax + 3];
-    __shared__ int s_lo[R], s_off[R + 1];
+    __shared__ int s_cs[kCsMax];
+    __shared__ int s_lo[RMAX], s_off[RMAX + 1], s_qoff[kTYMax + 1];
     const int G = a.G;
     const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int row = tile / nseg, seg = tile - row * nseg;
-    const int gy = D == 3 ? row % G : row, gz = D == 3 ? row / G : 0;
-    const int gx0 = seg * TX, gx1 = min(gx0 + TX, G);      // the tile's cells [gx0, gx1)
-    const int gl = max(gx0 - 1, 0), gh = min(gx1, G - 1);  // neighbourhood cells [gl, gh]
-    const int w = gh - gl + 1;
-    for (int idx = (int)threadIdx.x; idx < R * (w + 1); idx += kTB) {
-        const int k = idx / (w + 1), u = idx - k * (w + 1);
-        const int y = gy + (D == 3 ? k % 3 : k) - 1, z = D == 3 ? gz + k / 3 - 1 : 0;
+    const int sx = tile % nsx, rest = tile / nsx;
+    const int sy = rest % nsy, gz = D == 3 ? rest / nsy : 0;
+    const int gx0 = sx * TX, gx1 = min(gx0 + TX, G);      // the tile's cells [gx0, gx1) x [gy0, gy1)
+    const int gy0 = sy * TY, gy1 = min(gy0 + TY, G);
+    const int ty = gy1 - gy0, ry = ty + 2;                // neighbourhood rows per plane
+    const int R = D == 3 ? 3 * ry : ry;                   // row k: y = gy0 - 1 + k % ry, z = gz - 1 + k / ry
+    const int gl = max(gx0 - 1, 0), gh = min(gx1, G - 1);  // neighbourhood cells [gl, gh] of each row
+    const int w1 = gh - gl + 2;                           // cell-start entries per row
+    const int kbase = D == 3 ? ry : 0;                    // first row of the middle plane
+    for (int idx = (int)threadIdx.x; idx < R * w1; idx += kTB) {
+        const int k = idx / w1, u = idx - k * w1;
+        const int y = gy0 - 1 + k % ry, z = D == 3 ? gz - 1 + k / ry : 0;
         const bool in = y >= 0 && y < G && z >= 0 && z < G;
-        s_cs[k][u] = in ? a.cell_start[gl + u + G * (y + G * z)] : 0;
+        s_cs[idx] = in ? a.cell_start[gl + u + G * (y + G * z)] : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int off = 0;
         for (int k = 0; k < R; ++k) {
-            s_lo[k] = s_cs[k][0];
+            s_lo[k] = s_cs[k * w1];
             s_off[k] = off;
-            off += s_cs[k][w] - s_cs[k][0];
+            off += s_cs[k * w1 + w1 - 1] - s_cs[k * w1];
         }
         s_off[R] = off;
+        int q = 0;
+        for (int j = 0; j < ty; ++j) {
+            const int k = kbase + 1 + j;
+            s_qoff[j] = q;
+            q += s_cs[k * w1 + gx1 - gl] - s_cs[k * w1 + gx0 - gl];
+        }
+        s_qoff[ty] = q;
     }
     __syncthreads();
     const int total = s_off[R];
     const bool staged = total <= kNbMax;
     // slot of LDS entry m of row k: s_lo[k] + (m - s_off[k]); cell starts become LDS positions
-    for (int idx = (int)threadIdx.x; idx < R * (w + 1); idx += kTB) {
-        const int k = idx / (w + 1), u = idx - k * (w + 1);
-        s_cs[k][u] += s_off[k] - s_lo[k];
-    }
+    for (int idx = (int)threadIdx.x; idx < R * w1; idx += kTB) s_cs[idx] += s_off[idx / w1] - s_lo[idx / w1];
     if (staged) {
+        int k = 0;
         for (int m = (int)threadIdx.x; m < total; m += kTB) {
-            int k = 0;
-            while (k + 1 < R && s_off[k + 1] <= m) ++k;
+            while (s_off[k + 1] <= m) ++k;  // m increases, so k only moves forward
             const int slot = s_lo[k] + (m - s_off[k]);
             s_x[m] = a.sorted[slot];
             s_y[m] = a.sorted[n1 + slot];
@@ -460,9 +470,13 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int ns
     __syncthreads();
     const double St = a.sc->S[a.parity];
     const double margin = query_margin(St, a.sc->S_grid);
-    const int q0 = s_cs[MID][gx0 - gl], q1 = s_cs[MID][gx1 - gl];
-    for (int q = q0 + (int)threadIdx.x; q < q1; q += kTB) {
-        const int slot = s_lo[MID] + (q - s_off[MID]);
+    const int qtotal = s_qoff[ty];
+    int j = 0;
+    for (int qq = (int)threadIdx.x; qq < qtotal; qq += kTB) {
+        while (s_qoff[j + 1] <= qq) ++j;
+        const int kq = kbase + 1 + j;
+        const int q = s_cs[kq * w1 + gx0 - gl] + (qq - s_qoff[j]);  // LDS position
+        const int slot = s_lo[kq] + (q - s_off[kq]);
         float x, y, z = 0.0f;
         int i;
         if (staged) {
@@ -479,32 +493,39 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int ns
         Top2 t;
         t.init();
         const int cx = cell_axis(x, G), cy = cell_axis(y, G), cz = D == 3 ? cell_axis(z, G) : 0;
-        if (staged && cx >= gx0 && cx < gx1 && cy == gy && cz == gz) {
+        bool widen = false;
+        if (staged && cx >= gx0 && cx < gx1 && cy >= gy0 && cy < gy1 && cz == gz) {
             const int ulo = max(cx - 1, 0) - gl, uhi = min(cx + 1, G - 1) - gl + 1;
+            const int k0 = cy - gy0;  // row of dy = -1 in each plane
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const int lo = s_cs[k][ulo], hi = s_cs[k][uhi];
-                for (int m = lo; m < hi; ++m) {
-                    const float s = sqdist<D>(x, y, z, s_x[m], s_y[m], D == 3 ? s_z[m] : 0.0f);
-                    const int j = s_j[m];
-                    if (j != i) t.push(s, j);
+            for (int pz = 0; pz < (D == 3 ? 3 : 1); ++pz) {
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int k = k0 + dy + pz * ry;
+                    const int lo = s_cs[k * w1 + ulo], hi = s_cs[k * w1 + uhi];
+                    for (int m = lo; m < hi; ++m) {
+                        const float s = sqdist<D>(x, y, z, s_x[m], s_y[m], D == 3 ? s_z[m] : 0.0f);
+                        const int jj = s_j[m];
+                        if (jj != i) t.push(s, jj);
+                    }
                 }
             }
             const double B = outside_bound<D>(x, y, z, cx, cy, cz, 1, G);
             const double Be = B - margin;
-            if (!__builtin_isinf(B) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel))) {
-                const int at = atomicAdd(&a.sc->nwide, 1);
-                if (at < a.n)
-                    wide[at] = i;
-                else
-                    atomicOr(&a.sc->err, kErrOverflow);
-                rec[slot] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
-                continue;
-            }
+            widen = !__builtin_isinf(B) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel));
         } else {
             group_search<D, 1>(a, x, y, z, i, margin, 0, t);
         }
-        rec[slot] = make_int4(t.nn, __float_as_int(t.s1), __float_as_int(t.s2), 1);
+        const int at = wave_append(&a.sc->nwide, widen);
+        if (widen) {
+            if (at < a.n)
+                wide[at] = i;
+            else
+                atomicOr(&a.sc->err, kErrOverflow);
+            rec[slot] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
+        } else {
+            rec[slot] = make_int4(t.nn, __float_as_int(t.s1), __float_as_int(t.s2), 1);
+        }
     }
 }
 
@@ -793,23 +814,35 @@ int launch_query_all(nnc_ctx *c, int init)
     const bool tiled = (c->flags & NNC_QUERY_TILED) ||
                        (!(c->flags & NNC_QUERY_POINTWISE) && c->n >= kTiledMinN);
     if (!tiled) return launch_query(c, nullptr, nullptr, 1, init);
-    const int R = c->d == 3 ? 9 : 3;
-    const double occ = (double)c->n / (double)c->ncell;
-    int TX = (int)(0.6 * kNbMax / (R * (occ > 1.0 ? occ : 1.0))) - 2;
-    TX = TX < 4 ? 4 : TX;
-    TX = TX > kTXMax ? kTXMax : TX;
-    TX = TX > c->G ? c->G : TX;
-    const long long nseg = (c->G + TX - 1) / TX;
-    const long long rows = c->d == 3 ? (long long)c->G * c->G : c->G;
-    const long long tiles = rows * nseg;
+    // tile shape: the most queries per staged neighbour at the mean occupancy,
+    // within the LDS stage and the cell-start table
+    const double occ = (double)c->n / (double)c->ncell > 1.0 ? (double)c->n / (double)c->ncell : 1.0;
+    int TX = 1, TY = 1;
+    double best = -1.0;
+    for (int ty = 1; ty <= kTYMax && ty <= c->G; ty *= 2) {
+        const int R = c->d == 3 ? 3 * (ty + 2) : ty + 2;
+        int tx = (int)(0.6 * kNbMax / (R * occ)) - 2;
+        tx = tx > kTXMax ? kTXMax : tx;
+        tx = tx > c->G ? c->G : tx;
+        tx = tx > kCsMax / R - 3 ? kCsMax / R - 3 : tx;
+        if (tx < 1) continue;
+        const double ratio = (double)tx * ty / ((double)R * (tx + 2));
+        if (ratio > best) {
+            best = ratio;
+            TX = tx;
+            TY = ty;
+        }
+    }
+    const long long nsx = (c->G + TX - 1) / TX, nsy = (c->G + TY - 1) / TY;
+    const long long tiles = nsx * nsy * (c->d == 3 ? c->G : 1);
     if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
     const QueryArgs a = query_args(c, nullptr, nullptr, 1, init);
     if (c->d == 2)
-        hipLaunchKernelGGL(k_query_tiled<2>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, (int)nseg,
-                           c->wide, c->rec);
+        hipLaunchKernelGGL(k_query_tiled<2>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, TY, (int)nsx,
+                           (int)nsy, c->wide, c->rec);
     else
-        hipLaunchKernelGGL(k_query_tiled<3>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, (int)nseg,
-                           c->wide, c->rec);
+        hipLaunchKernelGGL(k_query_tiled<3>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, TY, (int)nsx,
+                           (int)nsy, c->wide, c->rec);
     hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, a, c->grid.rank,
                        (const int4 *)c->rec);
     launch_pointwise(c, query_args(c, c->wide, &c->sc->nwide, 0, init));
