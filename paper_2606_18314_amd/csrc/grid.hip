@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 // read per point instead of six scattered stores.  Tiles are dealt to XCDs in
 // contiguous ranges (workgroups go to the eight XCDs round-robin), so
 // neighbouring tiles share an L2.
-constexpr int kTB = 256;       // threads per tile
+constexpr int kTB = 512;       // threads per tile
 constexpr int kNbMax = 3072;   // neighbourhood points staged in LDS
 constexpr int kTXMax = 256;    // cells per tile row
 constexpr int kTYMax = 8;      // rows per tile
@@ -412,8 +412,7 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                                                      int *__restrict__ wide, int4 *__restrict__ rec)
 {
     constexpr int RMAX = D == 3 ? 3 * (kTYMax + 2) : kTYMax + 2;
-    __shared__ float s_x[kNbMax], s_y[kNbMax], s_z[D == 3 ? kNbMax : 1];
-    __shared__ int s_j[kNbMax];
+    __shared__ float4 s_p[kNbMax];  // x, y, z (0 in the plane), point index bits
     __shared__ int s_cs[kCsMax];
     __shared__ int s_lo[RMAX], s_off[RMAX + 1], s_qoff[kTYMax + 1];
     const int G = a.G;
@@ -461,10 +460,8 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         for (int m = (int)threadIdx.x; m < total; m += kTB) {
             while (s_off[k + 1] <= m) ++k;  // m increases, so k only moves forward
             const int slot = s_lo[k] + (m - s_off[k]);
-            s_x[m] = a.sorted[slot];
-            s_y[m] = a.sorted[n1 + slot];
-            if constexpr (D == 3) s_z[m] = a.sorted[n2 + slot];
-            s_j[m] = a.perm[slot];
+            s_p[m] = make_float4(a.sorted[slot], a.sorted[n1 + slot], D == 3 ? a.sorted[n2 + slot] : 0.0f,
+                                 __int_as_float(a.perm[slot]));
         }
     }
     __syncthreads();
@@ -480,10 +477,11 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         float x, y, z = 0.0f;
         int i;
         if (staged) {
-            x = s_x[q];
-            y = s_y[q];
-            if constexpr (D == 3) z = s_z[q];
-            i = s_j[q];
+            const float4 v = s_p[q];
+            x = v.x;
+            y = v.y;
+            z = v.z;
+            i = __float_as_int(v.w);
         } else {
             x = a.sorted[slot];
             y = a.sorted[n1 + slot];
@@ -504,8 +502,9 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                     const int k = k0 + dy + pz * ry;
                     const int lo = s_cs[k * w1 + ulo], hi = s_cs[k * w1 + uhi];
                     for (int m = lo; m < hi; ++m) {
-                        const float s = sqdist<D>(x, y, z, s_x[m], s_y[m], D == 3 ? s_z[m] : 0.0f);
-                        const int jj = s_j[m];
+                        const float4 v = s_p[m];
+                        const float s = sqdist<D>(x, y, z, v.x, v.y, v.z);
+                        const int jj = __float_as_int(v.w);
                         if (jj != i) t.push(s, jj);
                     }
                 }
