@@ -50,8 +50,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep")
+    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling")
     ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--scaling-exps", default="16,18,20,22,24,26",
+                    help="log2 N of the scaling leg's scenes")
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--regret-scenes", type=int, default=100)
@@ -344,6 +346,78 @@ def sweep_leg(args, nnc, synth, torch):
                                           "avg_launch_us": rep50["repair_query_us"], "bytes_per_launch": rbytes}}
 
 
+def scaling_leg(args, nnc, synth, torch):
+    """The step, repair and rebuild kernels from N = 2^16 to 2^26 (d = 2, uniform,
+    Brownian steps, eps set so that about 5 % of the points are candidates): mean
+    kernel times from HIP events and achieved bandwidth against 8 TB/s with the
+    algorithmic bytes of each kernel; each size certified on 4096 sampled points by
+    the exact all-pairs kernel."""
+    rows = []
+    d = 2
+    for e in [int(v) for v in args.scaling_exps.split(",") if v]:
+        n = 1 << e
+        p0 = synth.device_uniform(n, d, seed=7000 + e)
+        ctx = nnc.NNCert(n, d, lanes=16)
+        G = ctx.grid_g
+        ctx.init_certificates(p0)
+        st = ctx.state()
+        c = (st["d2"] - st["d1"]).float()
+        k = max(1, int(0.05 * n))
+        eps = float(torch.kthvalue(c, k).values) / 4.0
+        del st, c
+        frames = [p0]
+        for t in range(1, 7):
+            frames.append(synth.device_brownian_step(frames[-1], eps, seed=7100 + 10 * e + t))
+        torch.cuda.synchronize()
+        prof = {}
+        nf = C = 0
+        for t in range(1, 7):
+            strategy = "repair" if t <= 4 else "rebuild"
+            if t == 2 or t == 5:
+                ctx.profile_enable(True)
+            ctx.step(frames[t], -1.0)
+            if t == 4:  # candidates and occupied cells of a profiled step
+                ctx.profile_enable(False)
+                F = ctx.frontier_entropy(nnc.NNC_CANDIDATES)
+                nf, C = F["count"], F["C"]
+                ctx.profile_enable(True)
+            ctx.repair() if strategy == "repair" else ctx.rebuild()
+            if t == 4 or t == 6:
+                for name, (ms, cnt) in ctx.profile_read().items():
+                    prof[(strategy, name)] = (ms / cnt * 1e3) if cnt else 0.0
+                ctx.profile_enable(False)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7200 + e)
+        qidx = torch.sort(torch.randperm(n, generator=g, device="cuda")[:4096]).values.to(torch.int32)
+        nn, d1, d2 = nnc.allpairs_top2(frames[6], qidx)
+        stt = ctx.state()
+        ql = qidx.long()
+        bad = int((stt["nn"][ql] != nn).sum()) + int((stt["d1"][ql].view(torch.int32) != d1.view(torch.int32)).sum())
+        ctx.close()
+        occ = n / G ** d
+        nbytes = {
+            "ingest": n * (12 * d + 8),
+            "filter": n * 9 + 4 * nf,
+            "repair_query": nf * (4 * d + 4 + 25) + min(n, 9 * occ * nf) * (4 * d + 4) + 4 * (C + 1),
+            "grid": 12 * G ** d + n * (8 * d + 12),
+            "rebuild_query": n * (8 * d + 29) + 4 * (C + 1),
+        }
+        times = {"ingest": prof[("repair", "ingest")], "filter": prof[("repair", "filter")],
+                 "repair_query": prof[("repair", "query")], "grid": prof[("rebuild", "grid")],
+                 "rebuild_query": prof[("rebuild", "query")]}
+        row = {"n": n, "G": G, "eps": eps, "candidates": nf, "sampled_mismatches": bad}
+        for kname, us in times.items():
+            gbs = nbytes[kname] / (us * 1e-6) / 1e9 if us > 0 else 0.0
+            row[kname] = {"us": round(us, 2), "bytes": int(nbytes[kname]), "GB_s": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        progress(f"scaling N=2^{e}: " + ", ".join(f"{k} {v['us']} us {v['frac']:.3f}" for k, v in row.items()
+                                                   if isinstance(v, dict)))
+        rows.append(row)
+        del frames
+        torch.cuda.empty_cache()
+    return {"d": d, "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -585,6 +659,8 @@ def main():
     if "sweep" in legs_req:
         legs["sweep"] = sweep_leg(args, nnc, synth, torch)
         progress("sweep done")
+    if "scaling" in legs_req:
+        legs["scaling"] = scaling_leg(args, nnc, synth, torch)
 
     # ---- batched scenes (512 scenes, log-uniform N, mixed d and families) ------------------
     if "batched" in legs_req:

@@ -64,6 +64,8 @@ size_t carve(nnc_ctx *c, char *base)
     c->status = k.take<unsigned long long>(tiles);
     c->wide = k.take<int32_t>(n);
     c->rec = k.take<int4>(n);
+    c->ntcount = (int)((n + 4095) / 4096 + 1);
+    c->tcount = k.take<int32_t>((size_t)c->ntcount);
     c->ent_part = k.take<double>(3 * nnc::kEntropyParts);
     c->a_nn = k.take<int32_t>(n);
     c->a_d1 = k.take<float>(n);

@@ -39,6 +39,7 @@ constexpr int kTile = kB * kRows;  // items per look-back tile
 constexpr int kSmallB = 1024;      // one-workgroup filter: threads
 constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
 constexpr int kSmallMaxN = 2 * kTile;  // scenes up to this size use the one-workgroup filter
+constexpr long long kReduceScanMinN = 1 << 21;  // above this, the reduce-then-scan filter
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
 constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
@@ -297,6 +298,94 @@ __global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restri
                 frontier[at] = i;
             else
                 atomicOr(&sc->err, kErrOverflow);
+        }
+    }
+}
+
+// Reduce-then-scan filter for large N (no chain between tiles): k_filter_count
+// advances the clock and counts each tile's candidates, k_filter_offsets scans
+// the counts in one workgroup, k_filter_write re-reads the keys and writes each
+// tile's candidates at its offset, in index order.
+constexpr int kFRows = 16;                // items per thread in the counting tiles
+constexpr int kFTile = kB * kFRows;       // 4096 items per tile
+
+__global__ void __launch_bounds__(kB) k_filter_count(const double *__restrict__ e, int n, DevScalars *sc, int parity,
+                                                     float eps_decl, uint8_t *__restrict__ fail,
+                                                     int *__restrict__ tcount)
+{
+    __shared__ int s_w[kB / 64];
+    const double St = advance_clock(sc, parity, eps_decl, blockIdx.x == 0 && threadIdx.x < 64);
+    const long long base = (long long)blockIdx.x * kFTile;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        const long long i = base + (long long)k * kB + threadIdx.x;
+        if (i < n) {
+            c += St >= e[i] ? 1 : 0;
+            fail[i] = 0;
+        }
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int v = 0; v < kB / 64; ++v) t += s_w[v];
+        tcount[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_filter_offsets(int *__restrict__ tcount, int tiles, DevScalars *sc)
+{
+    __shared__ int s_w[1024 / 64];
+    int run = 0;
+    for (int base = 0; base < tiles; base += 1024) {
+        const int t = base + (int)threadIdx.x;
+        const int v = t < tiles ? tcount[t] : 0;
+        int tot;
+        const int ex = block_excl_scan<1024>(v, s_w, tot);
+        if (t < tiles) tcount[t] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) sc->nfront = run;
+}
+
+__global__ void __launch_bounds__(kB) k_filter_write(const double *__restrict__ e, int n, const DevScalars *sc,
+                                                     int parity, const int *__restrict__ toff,
+                                                     int *__restrict__ frontier, unsigned *err)
+{
+    __shared__ int s_cnt[kFRows][kB / 64];
+    const double St = sc->S[parity];
+    const int w = threadIdx.x >> 6;
+    const unsigned lane = lane_id();
+    const long long base = (long long)blockIdx.x * kFTile;
+    unsigned long long masks[kFRows];
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        const long long i = base + (long long)k * kB + threadIdx.x;
+        masks[k] = __ballot(i < n && St >= e[i]);
+        if (lane == 0) s_cnt[k][w] = __popcll(masks[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = toff[blockIdx.x];
+        for (int k = 0; k < kFRows; ++k)
+            for (int v = 0; v < kB / 64; ++v) {
+                const int c = s_cnt[k][v];
+                s_cnt[k][v] = run;
+                run += c;
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        if ((masks[k] >> lane) & 1ull) {
+            const long long i = base + (long long)k * kB + threadIdx.x;
+            const unsigned at = (unsigned)s_cnt[k][w] + rank_below(masks[k]);
+            if (at < (unsigned)n)
+                frontier[at] = (int)i;
+            else
+                atomicOr(err, kErrOverflow);
         }
     }
 }
@@ -714,6 +803,16 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
 int launch_filter(nnc_ctx *c, float eps_declared)
 {
     const int parity = (int)(c->t & 1);
+    if (c->n > (int64_t)kReduceScanMinN) {
+        const int tiles = blocks_for(c->n, kFTile);
+        if (tiles + 1 > c->ntcount) return NNC_E_INVAL;
+        hipLaunchKernelGGL(k_filter_count, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
+                           eps_declared, c->fail, c->tcount);
+        hipLaunchKernelGGL(k_filter_offsets, dim3(1), dim3(1024), 0, c->stream, c->tcount, tiles, c->sc);
+        hipLaunchKernelGGL(k_filter_write, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n,
+                           (const DevScalars *)c->sc, parity, (const int *)c->tcount, c->frontier, &c->sc->err);
+        return check();
+    }
     // one workgroup only for small scenes: above two tiles the look-back version,
     // whose tiles count in parallel, is faster (measured at N = 16000)
     const bool small = c->n <= (int64_t)kSmallMaxN;

@@ -104,6 +104,9 @@ struct nnc_ctx {
     // the tiled pass's results in slot order (nn, d1, d2 bits, done flag)
     int32_t *wide;
     int4 *rec;
+    // reduce-then-scan filter: candidates per tile, then their offsets
+    int32_t *tcount;
+    int ntcount;
     double *ent_part;             // partial sums of the split entropy reduction
     // audit scratch
     int32_t *a_nn;

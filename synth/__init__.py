@@ -236,3 +236,28 @@ def sweep_lists(p0: np.ndarray, count: int, seed: int = 3000):
     local = np.sort(np.argpartition(r2, count - 1)[:count]).astype(np.int32)
     diffuse = np.sort(g.choice(p0.shape[1], count, replace=False)).astype(np.int32)
     return local, diffuse
+
+
+# --- large scenes generated on the device (scaling runs) ---------------------------
+
+def device_uniform(n: int, d: int, seed: int, device="cuda"):
+    """N points uniform in the unit box, float32 [d, N], drawn on the device by a
+    seeded torch generator (for sizes whose host generation would dominate)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.rand((d, n), generator=g, device=device, dtype=torch.float32)
+
+
+def device_brownian_step(p, eps: float, seed: int):
+    """One Brownian transition of device positions: per-axis Gaussian of scale
+    eps/sqrt(d), each displacement's Euclidean length clipped to 0.999 * eps (the
+    margin keeps the binary32 step within eps)."""
+    import torch
+    d = p.shape[0]
+    g = torch.Generator(device=p.device)
+    g.manual_seed(int(seed))
+    delta = torch.randn(p.shape, generator=g, device=p.device, dtype=torch.float32) * (eps / math.sqrt(d))
+    norm = torch.sqrt((delta * delta).sum(0, keepdim=True))
+    scale = torch.clamp((0.999 * eps) / torch.clamp(norm, min=1e-30), max=1.0)
+    return (p + delta * scale).contiguous()

@@ -185,6 +185,37 @@ def test_tiled_is_the_default_from_65536_points(nnc):
     run_parity(nnc, tr, G=128, strategy="rebuild")
 
 
+@pytest.mark.parametrize("n", [(1 << 21) + 1, 3 * (1 << 20) + 4097])
+def test_large_scene_filter_compaction(nnc, n):
+    """Above 2^21 points the filter counts, scans and writes in three passes: its
+    candidate list must be exactly the ascending indices with S_t >= e_i, read back
+    from the library's own keys (the certificates themselves are checked on a
+    sample by the all-pairs kernel)."""
+    d = 2
+    p0 = synth.device_uniform(n, d, seed=n)
+    p1 = synth.device_brownian_step(p0, 2e-4, seed=n + 1)
+    ctx = nnc.NNCert(n, d)
+    ctx.init_certificates(p0)
+    e = host(ctx.state()["e"])
+    ctx.step(p1, -1.0)
+    st = ctx.frontier_entropy(nnc.NNC_CANDIDATES)
+    cand = host(ctx.frontier_indices())
+    assert np.array_equal(cand, np.flatnonzero(st["S"] >= e).astype(np.int32))
+    assert cand.size > 0
+    ctx.repair()
+    g = np.random.default_rng(n)
+    q = np.sort(g.choice(n, 2048, replace=False)).astype(np.int32)
+    nn, d1, d2 = nnc.allpairs_top2(p1, dev(q))
+    state = ctx.state()
+    assert np.array_equal(host(state["nn"])[q], host(nn))
+    # recomputed certificates are fresh; the others keep the values of their step
+    fresh = np.isin(q, cand)
+    assert fresh.any()
+    assert np.array_equal(bits(host(state["d1"])[q][fresh]), bits(host(d1)[fresh]))
+    assert np.array_equal(bits(host(state["d2"])[q][fresh]), bits(host(d2)[fresh]))
+    ctx.close()
+
+
 @pytest.mark.parametrize("family", synth.FAMILIES)
 def test_cube_16k_families_full_size(nnc, family):
     """N = 16000, d = 3 at the default grid (G = 15), first 6 steps, every array checked."""
