@@ -9,16 +9,23 @@ scenes by one transition through the whole maintenance path: ingest
 (eps_t, cells), safety filter and ordered compaction, grid repair of the
 candidates (with the amortised grid refresh) and the failure-entropy reduction.
 
-Legs, all on the same inputs:
+Legs (--legs):
   repair    the method (Algorithm 1 with the clock), captured once in a HIP graph
-            and replayed: the headline value;
-  repair_eager  the same steps launched one call at a time;
+            and replayed, the five scenes as parallel branches: the headline
+            value; also one stream, eager launches, and per-kernel HIP events;
   rebuild   the O(N) grid rebuild competitor in place of the repair;
-  allpairs  the exact all-pairs top-2 competitor;
-plus a certification pass (every step audited by the GPU all-pairs oracle:
-zero missed failures and bitwise-equal fresh certificates), a kernel-timing
-pass (HIP events around the dominant kernel on the library's stream), and the
-CPU oracle timed on a bounded sample.
+  allpairs  the exact all-pairs top-2 competitor (VALU roofline);
+  sweep     N = 2^20 planar scene, candidate fractions 0.1 % to 50 %, localized
+            and diffuse motion: repair against rebuild, and H of the frontier;
+  batched   512 scenes of uneven N advanced together under four strategy
+            policies (repair, rebuild, size threshold, the learned selector),
+            against one context per scene; selector regret on fresh scenes;
+  scaling   the step, repair and rebuild kernels from N = 2^16 to 2^26 with
+            achieved bandwidth;
+plus a certification pass (every timed step of the repair and rebuild legs
+audited by the GPU all-pairs oracle: zero missed failures and bitwise-equal
+fresh certificates), HBM traffic of the dominant kernel from committed
+rocprofv3 counters, and the CPU oracle timed on a bounded sample.
 
 Prints one JSON line.
 """
@@ -405,7 +412,23 @@ def scaling_leg(args, nnc, synth, torch):
         times = {"ingest": prof[("repair", "ingest")], "filter": prof[("repair", "filter")],
                  "repair_query": prof[("repair", "query")], "grid": prof[("rebuild", "grid")],
                  "rebuild_query": prof[("rebuild", "query")]}
-        row = {"n": n, "G": G, "eps": eps, "candidates": nf, "sampled_mismatches": bad}
+        # reference: a plain random-permutation scatter of the same coordinates (torch's
+        # index_copy_), the pattern that moving points into slot order costs
+        perm = torch.randperm(n, generator=g, device="cuda")
+        src = frames[6].reshape(-1)
+        dst = torch.empty_like(src)
+        idx = torch.cat([perm + k * n for k in range(d)])
+        dst.index_copy_(0, idx, src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            dst.index_copy_(0, idx, src)
+        e1.record()
+        torch.cuda.synchronize()
+        scatter_us = e0.elapsed_time(e1) * 1e3 / 3
+        del perm, dst, idx
+        row = {"n": n, "G": G, "eps": eps, "candidates": nf, "sampled_mismatches": bad,
+               "reference_scatter_us": round(scatter_us, 2)}
         for kname, us in times.items():
             gbs = nbytes[kname] / (us * 1e-6) / 1e9 if us > 0 else 0.0
             row[kname] = {"us": round(us, 2), "bytes": int(nbytes[kname]), "GB_s": round(gbs, 1),

@@ -1,14 +1,16 @@
 // Single-scene kernels of the maintenance step (Algorithm 1 with the appendix's
 // clock) and of the O(N) grid rebuild, for gfx950.
 //
-//   k_ingest       per point: squared displacement (wave max -> one atomic per
-//                  wave), new cell id, occupancy counts and the occupied-cell
-//                  count C kept incrementally, and the point's current
-//                  coordinates written to its grid slot.
+//   k_ingest       per point: squared displacement, new cell id, occupancy
+//                  counts, the point's current coordinates written to its grid
+//                  slot; per workgroup one maximum and one occupied-cell change
+//                  into one of 64 spread slots (folded by the filter).
 //   k_filter*      clock advance and safety filter S_t >= e_i with an
 //                  order-preserving compaction into an ascending candidate
-//                  list (wave ballot + mbcnt, a per-tile scan in LDS; across
-//                  tiles a decoupled look-back, or one workgroup for small N).
+//                  list (wave ballot + mbcnt, a per-tile scan in LDS): one
+//                  workgroup for N <= 4096, a decoupled look-back across tiles
+//                  up to 2^21 points, above that reduce-then-scan (counts per
+//                  tile, one scan, ordered writes).
 //   k_scan_cells   exclusive scan of the occupancy counts -> cell-start table.
 //   k_scatter      counting-sort scatter: slot order (perm, rank) and the
 //                  coordinates in slot order.
@@ -19,8 +21,12 @@
 //                  ring until the second neighbour is provably enclosed
 //                  (Corollary 1); then the new certificate, expiry key,
 //                  failure flag and failure histogram.
+//   k_query_tiled  all-point query from N = 65536 on: cell patches with their
+//   k_finish_all   neighbourhood staged in LDS, slot-ordered records, then the
+//                  point-order certificates.
 //   k_entropy*     normalised entropy (Definition 2) from a scan of the cell
-//                  histogram (one workgroup, or partial sums for large grids).
+//                  histogram (one workgroup, or partial sums for large grids);
+//   k_cand_hist    the candidates' histogram for the same.
 #include <math.h>
 
 #include "device_common.hpp"
@@ -43,8 +49,8 @@ constexpr long long kReduceScanMinN = 1 << 21;  // above this, the reduce-then-s
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
 constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
-constexpr int kEntropyOneGroup4 = 1 << 15;
-constexpr int kIngestBlocks = 4096;  // at most 64 workgroups per spread slot  // histograms up to 2^17 cells: one-workgroup entropy
+constexpr int kEntropyOneGroup4 = 1 << 15;  // histograms up to 2^17 cells: one-workgroup entropy
+constexpr int kIngestBlocks = 4096;  // at most 64 workgroups per spread slot
 
 __device__ __forceinline__ unsigned long long pack_status(unsigned epoch, int flag, unsigned v)
 {
