@@ -285,7 +285,9 @@ struct QueryArgs {
     const int *cell_start, *perm, *cell;
     const int *list, *count_dev;
     int n, G, all, init, t, parity;
-    int *nn, *stamp, *hist, *touched;
+    int *nn, *stamp, *hist;
+    int *touched;              // a batch scene's list of touched cells (with its counters);
+                               // null for a single scene, whose entropy scans hist
     float *d1, *d2;
     double *e;
     uint8_t *fail;
@@ -377,6 +379,24 @@ __device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y,
         if (lane >= off) incl += v;
     }
     const int total = __shfl(incl, R - 1, L);
+    if constexpr (D == 3) {
+        // nine rows: each slot finds its row by a binary search over the rows'
+        // prefixes held by lanes 0..8 (lanes 9.. hold an empty row at the end)
+        const int pre = lane < R ? incl - rl : total;
+        for (int b = 0; b < total; b += L) {
+            const int k = b + lane;
+            const int kk = min(k, total - 1);
+            int lo = 0;
+#pragma unroll
+            for (int step = 8; step > 0; step >>= 1) {
+                const int p = __shfl(pre, lo + step, L);
+                if (p <= kk) lo += step;
+            }
+            const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
+            if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
+        }
+        return;
+    }
     int rstart[R], rpre[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -519,7 +539,8 @@ __device__ __forceinline__ double query_margin(double St, double S_grid)
 }
 
 // The new certificate of point i from its exact top-2 (old: its previous nearest
-// neighbour): distances, expiry key, stamp, failure flag, failure histogram.
+// neighbour): distances, expiry key, stamp, failure flag, failure histogram (and,
+// for a batch scene, its failure count and touched-cell list).
 __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old)
 {
     const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);

@@ -179,6 +179,13 @@ def test_tiled_all_point_query_families(nnc, family):
     run_parity(nnc, tr, G=20, strategy="alternate", all_query="tiled")
 
 
+def test_tiled_3d_at_the_automatic_threshold(nnc):
+    """N = 70000 in the cube, clustered: tiled rebuilds over cell patches (and the
+    widening pass) against the oracle."""
+    tr = synth.make_trajectory("clustered_drift", 70000, 3, 2, 5e-4, 4343)
+    run_parity(nnc, tr, G=40, strategy="rebuild")
+
+
 def test_tiled_is_the_default_from_65536_points(nnc):
     """N = 66000 in the plane: the automatic choice tiles; two rebuilds checked."""
     tr = synth.make_trajectory("uniform_brownian", 66000, 2, 2, 5e-4, 4242)
