@@ -40,11 +40,13 @@ namespace {
 using namespace kc;
 
 constexpr int kB = 256;            // threads per point-parallel workgroup
-constexpr int kRows = 8;           // items per thread in the tile scans
-constexpr int kTile = kB * kRows;  // items per look-back tile
+constexpr int kRows = 8;           // items per thread in the cell-scan tiles
+constexpr int kTile = kB * kRows;  // items per cell-scan look-back tile
+constexpr int kFiltRows = 4;                // items per thread in the filter tiles
+constexpr int kFiltTile = kB * kFiltRows;   // items per filter look-back tile
 constexpr int kSmallB = 1024;      // one-workgroup filter: threads
 constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
-constexpr int kSmallMaxN = 2 * kTile;  // scenes up to this size use the one-workgroup filter
+constexpr int kSmallMaxN = 4096;       // scenes up to this size use the one-workgroup filter
 constexpr long long kReduceScanMinN = 1 << 21;  // above this, the reduce-then-scan filter
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
@@ -188,17 +190,17 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
 {
     __shared__ int s_tile;
     __shared__ unsigned s_epoch;
-    __shared__ int s_cnt[kRows][kB / 64];
+    __shared__ int s_cnt[kFiltRows][kB / 64];
     __shared__ unsigned s_base;
     take_ticket(sy, &s_tile, &s_epoch);
     const int tile = s_tile;
     const double St = advance_clock(sc, parity, eps_decl, tile == 0 && threadIdx.x < 64);
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
-    const long long base = (long long)tile * kTile;
-    unsigned long long masks[kRows];
+    const long long base = (long long)tile * kFiltTile;
+    unsigned long long masks[kFiltRows];
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
+    for (int k = 0; k < kFiltRows; ++k) {
         const long long i = base + (long long)k * kB + threadIdx.x;
         bool cand = false;
         if (i < n) {
@@ -212,7 +214,7 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
     __shared__ int s_run;
     if (threadIdx.x == 0) {
         int run = 0;
-        for (int k = 0; k < kRows; ++k)
+        for (int k = 0; k < kFiltRows; ++k)
             for (int v = 0; v < kB / 64; ++v) {
                 const int c = s_cnt[k][v];
                 s_cnt[k][v] = run;
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
     __syncthreads();
     const unsigned b = s_base;
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
+    for (int k = 0; k < kFiltRows; ++k) {
         if ((masks[k] >> lane) & 1ull) {
             const long long i = base + (long long)k * kB + threadIdx.x;
             const unsigned at = b + s_cnt[k][w] + rank_below(masks[k]);
@@ -822,12 +824,12 @@ int launch_filter(nnc_ctx *c, float eps_declared)
     // one workgroup only for small scenes: above two tiles the look-back version,
     // whose tiles count in parallel, is faster (measured at N = 16000)
     const bool small = c->n <= (int64_t)kSmallMaxN;
-    if (!small && blocks_for(c->n, kTile) > c->nstatus) return NNC_E_INVAL;
+    if (!small && blocks_for(c->n, kFiltTile) > c->nstatus) return NNC_E_INVAL;
     if (small) {
         hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(kSmallB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
                            eps_declared, c->frontier, c->fail);
     } else {
-        const int tiles = blocks_for(c->n, kTile);
+        const int tiles = blocks_for(c->n, kFiltTile);
         hipLaunchKernelGGL(k_filter, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc, c->sync, parity,
                            eps_declared, c->frontier, c->fail, c->status);
     }
