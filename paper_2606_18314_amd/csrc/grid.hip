@@ -9,7 +9,7 @@
 //                  order-preserving compaction into an ascending candidate
 //                  list (wave ballot + mbcnt, a per-tile scan in LDS): one
 //                  workgroup for N <= 4096, a decoupled look-back across tiles
-//                  up to 2^21 points, above that reduce-then-scan (counts per
+//                  up to 2^19 points, above that reduce-then-scan (counts per
 //                  tile, one scan, ordered writes).
 //   k_scan_cells   exclusive scan of the occupancy counts -> cell-start table.
 //   k_scatter      counting-sort scatter: slot order (perm, rank) and the
@@ -42,12 +42,15 @@ using namespace kc;
 constexpr int kB = 256;            // threads per point-parallel workgroup
 constexpr int kRows = 8;           // items per thread in the cell-scan tiles
 constexpr int kTile = kB * kRows;  // items per cell-scan look-back tile
-constexpr int kFiltRows = 4;                // items per thread in the filter tiles
-constexpr int kFiltTile = kB * kFiltRows;   // items per filter look-back tile
+// filter look-back tiles: 512 items up to kFiltSmallTilesN points, 1024 above
+// (measured: shorter tiles win at small N, longer chains lose as N grows; from
+// kReduceScanMinN on the filter is reduce-then-scan)
+constexpr int kFiltRowsSmall = 2, kFiltRowsLarge = 4;
+constexpr long long kFiltSmallTilesN = 65536;
 constexpr int kSmallB = 1024;      // one-workgroup filter: threads
 constexpr int kSmallRows = 32;     // one-workgroup filter: items per thread (n <= 32768)
 constexpr int kSmallMaxN = 4096;       // scenes up to this size use the one-workgroup filter
-constexpr long long kReduceScanMinN = 1 << 21;  // above this, the reduce-then-scan filter
+constexpr long long kReduceScanMinN = 1 << 19;  // above this, the reduce-then-scan filter
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
 constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
@@ -184,6 +187,7 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
     publish_ingest_spread<kB>(sc, parity, s, dC);
 }
 
+template <int kFiltRows>
 __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int n, DevScalars *sc, DevSync *sy,
                                                int parity, float eps_decl, int *__restrict__ frontier,
                                                uint8_t *__restrict__ fail, unsigned long long *status)
@@ -197,6 +201,7 @@ __global__ void __launch_bounds__(kB) k_filter(const double *__restrict__ e, int
     const double St = advance_clock(sc, parity, eps_decl, tile == 0 && threadIdx.x < 64);
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
+    constexpr int kFiltTile = kB * kFiltRows;
     const long long base = (long long)tile * kFiltTile;
     unsigned long long masks[kFiltRows];
 #pragma unroll
@@ -824,14 +829,20 @@ int launch_filter(nnc_ctx *c, float eps_declared)
     // one workgroup only for small scenes: above two tiles the look-back version,
     // whose tiles count in parallel, is faster (measured at N = 16000)
     const bool small = c->n <= (int64_t)kSmallMaxN;
-    if (!small && blocks_for(c->n, kFiltTile) > c->nstatus) return NNC_E_INVAL;
+    const bool small_tiles = c->n <= kFiltSmallTilesN;
+    const int ftile = kB * (small_tiles ? kFiltRowsSmall : kFiltRowsLarge);
+    if (!small && blocks_for(c->n, ftile) > c->nstatus) return NNC_E_INVAL;
     if (small) {
         hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(kSmallB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
                            eps_declared, c->frontier, c->fail);
     } else {
-        const int tiles = blocks_for(c->n, kFiltTile);
-        hipLaunchKernelGGL(k_filter, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc, c->sync, parity,
-                           eps_declared, c->frontier, c->fail, c->status);
+        const int tiles = blocks_for(c->n, ftile);
+        if (small_tiles)
+            hipLaunchKernelGGL(k_filter<kFiltRowsSmall>, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc,
+                               c->sync, parity, eps_declared, c->frontier, c->fail, c->status);
+        else
+            hipLaunchKernelGGL(k_filter<kFiltRowsLarge>, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc,
+                               c->sync, parity, eps_declared, c->frontier, c->fail, c->status);
     }
     return check();
 }

@@ -192,9 +192,9 @@ def test_tiled_is_the_default_from_65536_points(nnc):
     run_parity(nnc, tr, G=128, strategy="rebuild")
 
 
-@pytest.mark.parametrize("n", [(1 << 21) + 1, 3 * (1 << 20) + 4097])
+@pytest.mark.parametrize("n", [(1 << 19) + 1, 3 * (1 << 20) + 4097])
 def test_large_scene_filter_compaction(nnc, n):
-    """Above 2^21 points the filter counts, scans and writes in three passes: its
+    """Above 2^19 points the filter counts, scans and writes in three passes: its
     candidate list must be exactly the ascending indices with S_t >= e_i, read back
     from the library's own keys (the certificates themselves are checked on a
     sample by the all-pairs kernel)."""
