@@ -24,7 +24,8 @@
  *   guard g (default 2^-18) that absorbs binary32 rounding; g = 0 is the
  *   paper's key;  candidate iff S_t >= e_i;
  *   cell of a point: per axis floor(fl32(x * G)) clamped to [0, G-1], linear id
- *   gx + G*(gy + G*gz) over the box [0,1]^d (points outside go to edge cells).
+ *   gx + G*(gy + G*gz) over the box [0,1]^d (points outside go to edge cells), or
+ *   over a domain box given at creation (nnc_config.lo / hi).
  *
  * Conventions for every call:
  *   - return 0 on success or a negative NNC_E_* code; no exception crosses the ABI;
@@ -84,6 +85,14 @@ typedef struct {
     uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC | NNC_QUERY_TILED | NNC_QUERY_POINTWISE */
     int32_t  block;       /* lanes that share one 2-NN query: 1 (one thread per query,
                              for large N), 16, 32 or 64; 0 = 32 for d = 3 and 16 for d = 2 */
+    /* Domain box of the grid: axis k is cut into grid_g equal cells over
+     * [lo[k], hi[k]); a point's cell on axis k is floor(fl32(fl32(x - lo[k]) * s_k))
+     * clamped to [0, grid_g - 1], s_k = fl32(grid_g / (hi[k] - lo[k])) with the
+     * division in binary64 (points outside fall into edge cells).  All zero = the
+     * unit box [0,1]^d, where the formula is floor(fl32(x * grid_g)).  Otherwise
+     * every used axis needs finite lo < hi (else NNC_E_INVAL). */
+    float    lo[3];
+    float    hi[3];
 } nnc_config;
 
 /* Default grid_g: cell width w = 2/sqrt(N) (d = 2) or (4/N)^(1/3) (d = 3) and

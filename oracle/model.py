@@ -158,12 +158,22 @@ def pair_sqdist32(pos, a, b):
 
 # --- the pieces of Algorithm 1 ------------------------------------------------------
 
-def cells(pos: np.ndarray, G: int) -> np.ndarray:
-    """Linear cell id of every point: x fastest, then y, then z (Algorithm 1's index order)."""
+def cells(pos: np.ndarray, G: int, lo=None, hi=None) -> np.ndarray:
+    """Linear cell id of every point: x fastest, then y, then z (Algorithm 1's index order).
+
+    The grid covers [0,1]^d, or the box [lo, hi) when given: per axis
+    floor(fl32(fl32(x - lo) * s)), s = fl32(G / (hi - lo)) with the division in binary64."""
     pos = _soa(pos)
     if not np.all(np.isfinite(pos)):
         raise FloatingPointError("non-finite coordinate")
-    q = pos * np.float32(G)                       # binary32 product
+    if lo is None:
+        q = pos * np.float32(G)                   # binary32 product
+    else:
+        d = pos.shape[0]
+        lo32 = np.asarray(lo, np.float32)[:d, None]
+        hi32 = np.asarray(hi, np.float32)[:d, None]
+        s = (np.float64(G) / (hi32.astype(np.float64) - lo32.astype(np.float64))).astype(np.float32)
+        q = (pos - lo32) * s                      # two binary32 roundings
     g = np.clip(np.floor(q), 0, G - 1).astype(np.int64)
     cid = g[-1].copy()
     for k in range(pos.shape[0] - 2, -1, -1):     # id = g0 + G*(g1 + G*g2)
@@ -234,6 +244,8 @@ class OracleScene:
     G: int
     guard: float = GUARD_DEFAULT
     rule: str = "clock"             # "clock" (appendix) or "literal" (Algorithm 1 alone)
+    lo: tuple = None                # domain box of the grid (None: the unit box)
+    hi: tuple = None
     pos: np.ndarray = None
     nn: np.ndarray = None
     d1: np.ndarray = None
@@ -264,7 +276,7 @@ class OracleScene:
         self.e = np.full(n, np.inf, np.float64)
         self.fail = np.zeros(n, bool)
         self.S = 0.0
-        self.cell = cells(self.pos, self.G)
+        self.cell = cells(self.pos, self.G, self.lo, self.hi)
         self._recompute(np.arange(n, dtype=np.int64))
         self.fail[:] = False
         self.pending = None
@@ -272,7 +284,7 @@ class OracleScene:
     def step(self, pos_new: np.ndarray) -> StepResult:
         pos_new = _soa(pos_new)
         eps = max_step(self.pos, pos_new)
-        self.cell = cells(pos_new, self.G)        # every cell current (Algorithm 1)
+        self.cell = cells(pos_new, self.G, self.lo, self.hi)  # every cell current (Algorithm 1)
         self.pos = pos_new.copy()
         self.S = float(np.float64(self.S) + np.float64(eps))
         self.last_eps = eps

@@ -61,7 +61,8 @@ class NNCError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("grid_g", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("guard", ctypes.c_double), ("refresh", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("flags", ctypes.c_uint32), ("block", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("block", ctypes.c_int32),
+                ("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3)]
 
 
 class Frontier(ctypes.Structure):
@@ -226,9 +227,10 @@ class NNCert:
 
     def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
                  copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0,
-                 all_query: str = "auto"):
+                 all_query: str = "auto", box=None):
         """all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
-        query every point (tiled by cells from N = 65536 on under "auto")."""
+        query every point (tiled by cells from N = 65536 on under "auto").
+        box: (lo, hi), per-axis bounds of the grid's domain (default the unit box)."""
         if all_query not in ("auto", "tiled", "pointwise"):
             raise ValueError("all_query: 'auto', 'tiled' or 'pointwise'")
         lib = load()
@@ -240,6 +242,11 @@ class NNCert:
                      | (NNC_QUERY_TILED if all_query == "tiled" else 0)
                      | (NNC_QUERY_POINTWISE if all_query == "pointwise" else 0),
                      block=int(lanes))
+        if box is not None:
+            lo, hi = box
+            for k in range(self.d):
+                cfg.lo[k] = float(lo[k])
+                cfg.hi[k] = float(hi[k])
         h = ctypes.c_void_p()
         check(lib.nnc_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_create")
         self.h = h.value

@@ -2,6 +2,7 @@
 // verification, entropy and snapshots.  Host code only; every computation is
 // in the kernels of grid.hip and allpairs.hip.
 #include <math.h>
+#include <cmath>
 #include <stdlib.h>
 #include <string.h>
 
@@ -183,6 +184,17 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
     const int G = cfg->grid_g > 0 ? cfg->grid_g : default_grid(cfg->n, cfg->d);
     const double cells = pow((double)G, (double)cfg->d);
     if (G < 1 || cells > (double)kMaxCells) return NNC_E_INVAL;
+    // domain box: all zero = the unit box; else finite with hi > lo on every used axis
+    bool unit = true;
+    for (int k = 0; k < 3; ++k) unit = unit && cfg->lo[k] == 0.0f && cfg->hi[k] == 0.0f;
+    float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {1.0f, 1.0f, 1.0f};
+    if (!unit)
+        for (int k = 0; k < cfg->d; ++k) {
+            if (!std::isfinite(cfg->lo[k]) || !std::isfinite(cfg->hi[k]) || !(cfg->hi[k] > cfg->lo[k]))
+                return NNC_E_INVAL;
+            lo[k] = cfg->lo[k];
+            hi[k] = cfg->hi[k];
+        }
     nnc_ctx *c = new (std::nothrow) nnc_ctx();
     if (!c) return NNC_E_NOMEM;
     c->d = cfg->d;
@@ -194,7 +206,22 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
                                                                                              : (cfg->d == 3 ? 32 : 16);
     c->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
     c->K = 1.0 / (4.0 + 4.0 * c->guard);
-    c->refresh_w = (cfg->refresh > 0.0 ? cfg->refresh : 0.25) / (double)G;
+    // cells: s = fl32(G / (hi - lo)) with the division in binary64, w = (hi - lo) / G;
+    // the boundary-rounding allowance grows with the coordinates' magnitude
+    double wmin = 1.0, mag = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        const double width = (double)hi[k] - (double)lo[k];
+        c->box.lo[k] = lo[k];
+        c->box.s[k] = (float)((double)G / width);
+        c->box.w[k] = width / (double)G;
+        if (k < cfg->d) {
+            wmin = fmin(wmin, width);
+            mag = fmax(mag, fmax(fabs((double)lo[k]), fabs((double)hi[k])));
+        }
+    }
+    c->fuzz = 0x1p-20 * mag;
+    c->unit_box = unit;
+    c->refresh_w = (cfg->refresh > 0.0 ? cfg->refresh : 0.25) * wmin / (double)G;
     c->stream = (hipStream_t)cfg->stream;
     c->flags = cfg->flags;
     c->grid.G = G;

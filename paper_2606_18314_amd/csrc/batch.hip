@@ -367,6 +367,13 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     q.sc = &a.sc[s];
     q.guard = a.guard;
     q.K = a.K;
+    // scenes of a batch live in the unit box
+    for (int k = 0; k < 3; ++k) {
+        q.box.lo[k] = 0.0f;
+        q.box.s[k] = (float)sd.G;
+        q.box.w[k] = 1.0 / (double)sd.G;
+    }
+    q.fuzz = kFuzz;
     return q;
 }
 
@@ -396,7 +403,7 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
     SceneDesc sd = a.desc[s];
     QueryArgs q = scene_view(a, sd, s, init);
     double St = a.sc[s].S[a.parity];
-    double margin = query_margin(St, a.sc[s].S_grid);
+    double margin = query_margin(St, a.sc[s].S_grid, kFuzz);
     for (int g = q0; g < q1; g += GPB) {
         while (g >= next) {  // uniform within the lane group
             ++s;
@@ -404,13 +411,13 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
             sd = a.desc[s];
             q = scene_view(a, sd, s, init);
             St = a.sc[s].S[a.parity];
-            margin = query_margin(St, a.sc[s].S_grid);
+            margin = query_margin(St, a.sc[s].S_grid, kFuzz);
         }
         const int local = g - a.qpre[s];
         if (sd.d == 3)
-            query_one<3, L>(q, local, St, margin, lane);
+            query_one<3, L, true>(q, local, St, margin, lane);
         else
-            query_one<2, L>(q, local, St, margin, lane);
+            query_one<2, L, true>(q, local, St, margin, lane);
     }
 }
 

@@ -77,6 +77,33 @@ __device__ __forceinline__ int cell_id(float x, float y, float z, int G)
     return id;
 }
 
+// The domain box of a scene: cells of axis k cover [lo_k, hi_k) in G equal parts,
+// s_k = fl32(G / (hi_k - lo_k)) (the division in binary64); w_k = (hi_k - lo_k) / G
+// in binary64 for distance bounds.  The unit box is lo = 0, s = G, w = 1/G, with
+// which the cell formula below is exactly floor(fl32(x * G)).
+struct Box {
+    float lo[3], s[3];
+    double w[3];
+};
+
+// Cell coordinate on one axis of a box: floor(fl32(fl32(x - lo) * s)) clamped to
+// [0, G-1].
+__device__ __forceinline__ int cell_axis(float x, float lo, float s, int G)
+{
+    const float q = (x - lo) * s;
+    const float f = floorf(q);
+    const float c = fminf(fmaxf(f, 0.0f), (float)(G - 1));
+    return (int)c;
+}
+
+template <int D>
+__device__ __forceinline__ int cell_id(float x, float y, float z, int G, const Box &b)
+{
+    int id = cell_axis(x, b.lo[0], b.s[0], G) + G * cell_axis(y, b.lo[1], b.s[1], G);
+    if constexpr (D == 3) id += G * G * cell_axis(z, b.lo[2], b.s[2], G);
+    return id;
+}
+
 template <int D>
 __device__ __forceinline__ bool all_finite(float x, float y, float z)
 {

@@ -134,7 +134,7 @@ __global__ void k_fill(int *p, int value, size_t count)
 }
 
 template <int D>
-__global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos, int n, int G,
+__global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos, int n, int G, Box box,
                                                    int *__restrict__ cell, int *__restrict__ counts,
                                                    DevScalars *sc)
 {
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos
         const float x = pos[i], y = pos[(size_t)n + i], z = D == 3 ? pos[2 * (size_t)n + i] : 0.f;
         int c = 0;
         if (all_finite<D>(x, y, z))
-            c = cell_id<D>(x, y, z, G);
+            c = cell_id<D>(x, y, z, G, box);
         else
             atomicOr(&sc->err, kErrNonFinite);
         cell[i] = c;
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos
 
 template <int D>
 __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, const float *__restrict__ pnew,
-                                               int n, int G, int *__restrict__ cell, int *__restrict__ counts,
+                                               int n, int G, Box box, int *__restrict__ cell, int *__restrict__ counts,
                                                const int *__restrict__ rank, float *__restrict__ sorted,
                                                DevScalars *sc, int parity)
 {
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
         if constexpr (D == 3) sorted[n2 + k] = z1;
         if (all_finite<D>(x1, y1, z1) && all_finite<D>(x0, y0, z0)) {
             s = fmaxf(s, sqdist<D>(x0, y0, z0, x1, y1, z1));
-            const int c = cell_id<D>(x1, y1, z1, G);
+            const int c = cell_id<D>(x1, y1, z1, G, box);
             const int old = cell[i];
             if (c != old) {
                 cell[i] = c;
@@ -472,16 +472,16 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
     if constexpr (D == 3) sorted[2 * (size_t)n + k] = pos[2 * (size_t)n + i];
 }
 
-template <int D, int L>
+template <int D, int L, bool UNIT>
 __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 {
     const int count = a.all ? a.n : min(*a.count_dev, a.n);
     const double St = a.sc->S[a.parity];
-    const double margin = query_margin(St, a.sc->S_grid);
+    const double margin = query_margin(St, a.sc->S_grid, a.fuzz);
     const int lane = threadIdx.x & (L - 1);
     constexpr int GPB = kB / L;
     for (int q = blockIdx.x * GPB + (int)(threadIdx.x / L); q < count; q += gridDim.x * GPB)
-        query_one<D, L>(a, q, St, margin, lane);
+        query_one<D, L, UNIT>(a, q, St, margin, lane);
 }
 
 // All-point query (rebuild and initialisation, right after a grid build), tiled
@@ -509,7 +509,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nt)
     return x * full + min(x, rem) + k;
 }
 
-template <int D>
+template <int D, bool UNIT>
 __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY, int nsx, int nsy,
                                                      int *__restrict__ wide, int4 *__restrict__ rec)
 {
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
     }
     __syncthreads();
     const double St = a.sc->S[a.parity];
-    const double margin = query_margin(St, a.sc->S_grid);
+    const double margin = query_margin(St, a.sc->S_grid, a.fuzz);
     const int qtotal = s_qoff[ty];
     int j = 0;
     for (int qq = (int)threadIdx.x; qq < qtotal; qq += kTB) {
@@ -592,7 +592,8 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         }
         Top2 t;
         t.init();
-        const int cx = cell_axis(x, G), cy = cell_axis(y, G), cz = D == 3 ? cell_axis(z, G) : 0;
+        const int cx = query_cell<UNIT>(a, x, 0), cy = query_cell<UNIT>(a, y, 1);
+        const int cz = D == 3 ? query_cell<UNIT>(a, z, 2) : 0;
         bool widen = false;
         if (staged && cx >= gx0 && cx < gx1 && cy >= gy0 && cy < gy1 && cz == gz) {
             const int ulo = max(cx - 1, 0) - gl, uhi = min(cx + 1, G - 1) - gl + 1;
@@ -611,11 +612,11 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                     }
                 }
             }
-            const double B = outside_bound<D>(x, y, z, cx, cy, cz, 1, G);
+            const double B = query_bound<D, UNIT>(a, x, y, z, cx, cy, cz, 1);
             const double Be = B - margin;
             widen = !__builtin_isinf(B) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel));
         } else {
-            group_search<D, 1>(a, x, y, z, i, margin, 0, t);
+            group_search<D, 1, UNIT>(a, x, y, z, i, margin, 0, t);
         }
         const int at = wave_append(&a.sc->nwide, widen);
         if (widen) {
@@ -764,7 +765,7 @@ inline int blocks_for(long long n, int per) { return (int)((n + per - 1) / per);
 inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP; }
 
 template <int D, int L>
-void launch_query_t(const QueryArgs &a, long long maxq, hipStream_t s)
+void launch_query_t(const QueryArgs &a, long long maxq, hipStream_t s, bool unit)
 {
     // at most 2048 workgroups (eight per CU) striding over the queries: enough
     // waves to fill the chip, and few idle ones when the count on the device is
@@ -773,7 +774,10 @@ void launch_query_t(const QueryArgs &a, long long maxq, hipStream_t s)
     long long blocks = (maxq + GPB - 1) / GPB;
     if (blocks < 1) blocks = 1;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((k_query<D, L>), dim3((unsigned)blocks), dim3(kB), 0, s, a);
+    if (unit)
+        hipLaunchKernelGGL((k_query<D, L, true>), dim3((unsigned)blocks), dim3(kB), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_query<D, L, false>), dim3((unsigned)blocks), dim3(kB), 0, s, a);
 }
 
 }  // namespace
@@ -791,10 +795,10 @@ int launch_cells_init(nnc_ctx *c, const float *pos)
     if (c->n == 0) return NNC_OK;
     const int blocks = blocks_for(c->n, kB);
     if (c->d == 2)
-        hipLaunchKernelGGL(k_cells_init<2>, dim3(blocks), dim3(kB), 0, c->stream, pos, (int)c->n, c->G, c->cell,
+        hipLaunchKernelGGL(k_cells_init<2>, dim3(blocks), dim3(kB), 0, c->stream, pos, (int)c->n, c->G, c->box, c->cell,
                            c->grid.counts, c->sc);
     else
-        hipLaunchKernelGGL(k_cells_init<3>, dim3(blocks), dim3(kB), 0, c->stream, pos, (int)c->n, c->G, c->cell,
+        hipLaunchKernelGGL(k_cells_init<3>, dim3(blocks), dim3(kB), 0, c->stream, pos, (int)c->n, c->G, c->box, c->cell,
                            c->grid.counts, c->sc);
     return check();
 }
@@ -805,10 +809,10 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
     const int parity = (int)(c->t & 1);
     const int blocks = blocks_for(c->n, kB) < kIngestBlocks ? blocks_for(c->n, kB) : kIngestBlocks;
     if (c->d == 2)
-        hipLaunchKernelGGL(k_ingest<2>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->cell,
+        hipLaunchKernelGGL(k_ingest<2>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->box, c->cell,
                            c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
     else
-        hipLaunchKernelGGL(k_ingest<3>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->cell,
+        hipLaunchKernelGGL(k_ingest<3>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->box, c->cell,
                            c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
     return check();
 }
@@ -895,6 +899,8 @@ QueryArgs query_args(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, 
     a.sc = c->sc;
     a.guard = c->guard;
     a.K = c->K;
+    a.box = c->box;
+    a.fuzz = c->fuzz;
     return a;
 }
 
@@ -902,15 +908,15 @@ void launch_pointwise(nnc_ctx *c, const QueryArgs &a)
 {
     const long long maxq = c->n;
     if (c->d == 2) {
-        if (c->lanes == 64) launch_query_t<2, 64>(a, maxq, c->stream);
-        else if (c->lanes == 32) launch_query_t<2, 32>(a, maxq, c->stream);
-        else if (c->lanes == 1) launch_query_t<2, 1>(a, maxq, c->stream);
-        else launch_query_t<2, 16>(a, maxq, c->stream);
+        if (c->lanes == 64) launch_query_t<2, 64>(a, maxq, c->stream, c->unit_box);
+        else if (c->lanes == 32) launch_query_t<2, 32>(a, maxq, c->stream, c->unit_box);
+        else if (c->lanes == 1) launch_query_t<2, 1>(a, maxq, c->stream, c->unit_box);
+        else launch_query_t<2, 16>(a, maxq, c->stream, c->unit_box);
     } else {
-        if (c->lanes == 64) launch_query_t<3, 64>(a, maxq, c->stream);
-        else if (c->lanes == 32) launch_query_t<3, 32>(a, maxq, c->stream);
-        else if (c->lanes == 1) launch_query_t<3, 1>(a, maxq, c->stream);
-        else launch_query_t<3, 16>(a, maxq, c->stream);
+        if (c->lanes == 64) launch_query_t<3, 64>(a, maxq, c->stream, c->unit_box);
+        else if (c->lanes == 32) launch_query_t<3, 32>(a, maxq, c->stream, c->unit_box);
+        else if (c->lanes == 1) launch_query_t<3, 1>(a, maxq, c->stream, c->unit_box);
+        else launch_query_t<3, 16>(a, maxq, c->stream, c->unit_box);
     }
 }
 
@@ -954,12 +960,19 @@ int launch_query_all(nnc_ctx *c, int init)
     const long long tiles = nsx * nsy * (c->d == 3 ? c->G : 1);
     if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
     const QueryArgs a = query_args(c, nullptr, nullptr, 1, init);
-    if (c->d == 2)
-        hipLaunchKernelGGL(k_query_tiled<2>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, TY, (int)nsx,
-                           (int)nsy, c->wide, c->rec);
+    const dim3 grid((unsigned)tiles), block(kTB);
+    if (c->d == 2 && c->unit_box)
+        hipLaunchKernelGGL((k_query_tiled<2, true>), grid, block, 0, c->stream, a, TX, TY, (int)nsx, (int)nsy, c->wide,
+                           c->rec);
+    else if (c->d == 2)
+        hipLaunchKernelGGL((k_query_tiled<2, false>), grid, block, 0, c->stream, a, TX, TY, (int)nsx, (int)nsy, c->wide,
+                           c->rec);
+    else if (c->unit_box)
+        hipLaunchKernelGGL((k_query_tiled<3, true>), grid, block, 0, c->stream, a, TX, TY, (int)nsx, (int)nsy, c->wide,
+                           c->rec);
     else
-        hipLaunchKernelGGL(k_query_tiled<3>, dim3((unsigned)tiles), dim3(kTB), 0, c->stream, a, TX, TY, (int)nsx,
-                           (int)nsy, c->wide, c->rec);
+        hipLaunchKernelGGL((k_query_tiled<3, false>), grid, block, 0, c->stream, a, TX, TY, (int)nsx, (int)nsy, c->wide,
+                           c->rec);
     hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, a, c->grid.rank,
                        (const int4 *)c->rec);
     launch_pointwise(c, query_args(c, c->wide, &c->sc->nwide, 0, init));

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/nncert.h"
+#include "device_common.hpp"
 
 namespace nnc {
 
@@ -83,6 +84,9 @@ struct nnc_ctx {
     int d, G, ncell, block;
     int64_t n;
     double guard, K, refresh_w;
+    nnc::Box box;                 // domain box of the cells
+    bool unit_box;                // the box is [0,1]^d (queries use the folded formula)
+    double fuzz;                  // cell-boundary rounding allowance of the queries
     hipStream_t stream;
     uint32_t flags;
 

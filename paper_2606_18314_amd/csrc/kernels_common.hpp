@@ -293,6 +293,8 @@ struct QueryArgs {
     uint8_t *fail;
     DevScalars *sc;
     double guard, K;
+    Box box;                   // the scene's domain box
+    double fuzz;               // cell-boundary rounding allowance for this box
 };
 
 // Lower bound on the distance from (x,y,z) to any point whose build-time cell
@@ -309,6 +311,22 @@ __device__ __forceinline__ double outside_bound(float x, float y, float z, int g
     for (int k = 0; k < D; ++k) {
         if (gc[k] - r > 0) B = fmin(B, (double)pc[k] - (double)(gc[k] - r) * invG);
         if (gc[k] + r < G - 1) B = fmin(B, (double)(gc[k] + r + 1) * invG - (double)pc[k]);
+    }
+    return B;
+}
+
+template <int D>
+__device__ __forceinline__ double outside_bound(float x, float y, float z, int gx, int gy, int gz, int r, int G,
+                                                const Box &b)
+{
+    double B = __builtin_inf();
+    const float pc[3] = {x, y, z};
+    const int gc[3] = {gx, gy, gz};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double lo = (double)b.lo[k], w = b.w[k];
+        if (gc[k] - r > 0) B = fmin(B, (double)pc[k] - (lo + (double)(gc[k] - r) * w));
+        if (gc[k] + r < G - 1) B = fmin(B, (lo + (double)(gc[k] + r + 1) * w) - (double)pc[k]);
     }
     return B;
 }
@@ -509,16 +527,37 @@ __device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, 
     }
 }
 
-template <int D, int L>
+// Cell of a query point and the enclosure bound: the unit box (UNIT, with the
+// constants folded) or the scene's domain box.
+template <bool UNIT>
+__device__ __forceinline__ int query_cell(const QueryArgs &a, float x, int k)
+{
+    if constexpr (UNIT)
+        return cell_axis(x, a.G);
+    else
+        return cell_axis(x, a.box.lo[k], a.box.s[k], a.G);
+}
+
+template <int D, bool UNIT>
+__device__ __forceinline__ double query_bound(const QueryArgs &a, float x, float y, float z, int gx, int gy, int gz,
+                                              int r)
+{
+    if constexpr (UNIT)
+        return outside_bound<D>(x, y, z, gx, gy, gz, r, a.G);
+    else
+        return outside_bound<D>(x, y, z, gx, gy, gz, r, a.G, a.box);
+}
+
+template <int D, int L, bool UNIT>
 __device__ void group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, int lane,
                              Top2 &t)
 {
-    const int G = a.G;
-    const int gx = cell_axis(x, G), gy = cell_axis(y, G), gz = D == 3 ? cell_axis(z, G) : 0;
+    const int gx = query_cell<UNIT>(a, x, 0), gy = query_cell<UNIT>(a, y, 1);
+    const int gz = D == 3 ? query_cell<UNIT>(a, z, 2) : 0;
     scan_block<D, L>(a, x, y, z, i, gx, gy, gz, lane, t);
     group_reduce<L>(t);
     for (int r = 1;; ++r) {
-        const double B = outside_bound<D>(x, y, z, gx, gy, gz, r, G);
+        const double B = query_bound<D, UNIT>(a, x, y, z, gx, gy, gz, r);
         if (__builtin_isinf(B)) break;  // the whole grid has been visited
         const double Be = B - margin;
         if (Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel)) break;
@@ -532,10 +571,10 @@ __device__ void group_search(const QueryArgs &a, float x, float y, float z, int 
 
 // Search margin: cell-boundary rounding plus the motion accumulated since the
 // grid was built (the clock difference bounds every point's displacement).
-__device__ __forceinline__ double query_margin(double St, double S_grid)
+__device__ __forceinline__ double query_margin(double St, double S_grid, double fuzz)
 {
     const double drift = St - S_grid;
-    return kFuzz + drift * (1.0 + kRel);
+    return fuzz + drift * (1.0 + kRel);
 }
 
 // The new certificate of point i from its exact top-2 (old: its previous nearest
@@ -574,7 +613,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
 // Query q of a scene (the q-th candidate, or the q-th slot when recomputing all
 // points) by the L lanes of one group; lane 0 writes the new certificate, its
 // expiry key, stamp and failure flag, and counts a failure in the histogram.
-template <int D, int L>
+template <int D, int L, bool UNIT>
 __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, double margin, int lane)
 {
     const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
@@ -595,7 +634,7 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     const int old = lane == 0 ? a.nn[i] : 0;  // fetched early, used at the end
     Top2 t;
     t.init();
-    group_search<D, L>(a, x, y, z, i, margin, lane, t);
+    group_search<D, L, UNIT>(a, x, y, z, i, margin, lane, t);
     if (lane == 0) write_certificate(a, i, t, St, old);
 }
 

@@ -99,12 +99,14 @@ def test_allpairs_cube_16k_size(nnc):
 
 # --- the state machine ---------------------------------------------------------------
 
-def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0, all_query="auto"):
+def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0, all_query="auto",
+               box=None):
     d, n = traj.d, traj.n
     frames = [dev(f) for f in traj.frames]
-    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query)
+    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query, box=box)
     assert ctx.grid_g == G
-    sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard)
+    sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard,
+                           lo=None if box is None else box[0], hi=None if box is None else box[1])
     ctx.init_certificates(frames[0])
     sc.init_certificates(traj.frames[0])
     assert_state_equal(ctx.state(), sc, "init")
@@ -228,6 +230,39 @@ def test_cube_16k_families_full_size(nnc, family):
     """N = 16000, d = 3 at the default grid (G = 15), first 6 steps, every array checked."""
     tr = synth.cube_16k(family, steps=6)
     run_parity(nnc, tr, G=15)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("all_query", ["pointwise", "tiled"])
+def test_domain_box(nnc, d, all_query):
+    """Scenes in a box other than the unit cube (some points outside it, in the edge
+    cells): cells, candidates, certificates and entropy against the oracle."""
+    tr = synth.make_trajectory("adversarial_crossing", 5000, d, 8, 5e-4, 55 + d)
+    frames = (tr.frames.astype(np.float64) * 6.0 - 2.5).astype(np.float32)   # about [-2.5, 3.5]
+    tr = synth.Trajectory(tr.family, d, tr.n, -1.0, frames)
+    lo, hi = (0.0, -0.1, 0.2), (1.2, 1.4, 1.0)
+    run_parity(nnc, tr, G=24, strategy="alternate", box=(lo, hi), all_query=all_query)
+
+
+def test_unit_box_given_explicitly_is_the_default(nnc):
+    tr = synth.plane_1k(steps=6)
+    a = nnc.NNCert(tr.n, 2, grid_g=15, box=((0.0, 0.0), (1.0, 1.0)))
+    b = nnc.NNCert(tr.n, 2, grid_g=15)
+    for c in (a, b):
+        c.init_certificates(dev(tr.frames[0]))
+        for t in range(1, 7):
+            c.step(dev(tr.frames[t]))
+            c.repair()
+    sa, sb = a.state(), b.state()
+    for k in ("nn", "d1", "d2", "e", "cell", "fail"):
+        assert torch.equal(sa[k], sb[k]), k
+    a.close()
+    b.close()
+
+
+def test_invalid_domain_box_is_rejected(nnc):
+    with pytest.raises(nnc.NNCError):
+        nnc.NNCert(100, 2, box=((0.0, 1.0), (1.0, 1.0)))   # hi = lo on y
 
 
 def test_guard_zero_literal_key(nnc):

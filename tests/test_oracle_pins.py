@@ -366,3 +366,19 @@ def test_entropy_lower_bounds_touched_cells_theorem4():
         assert 0.0 <= H <= 1.0 + 1e-12
         if F:
             assert m >= C ** H * (1 - 1e-12)
+
+
+def test_box_cells_equal_the_cells_of_exactly_normalised_coordinates():
+    """A domain box [-1, 3)^d maps by x -> (x + 1) / 4, exact for dyadic coordinates, so
+    the box formula must give the unit-box cells of the normalised points; the unit
+    box given explicitly is the default formula."""
+    g = np.random.default_rng(17)
+    for d in (2, 3):
+        k = g.integers(-40, 300, (d, 2000))            # some points outside the box
+        pos = (k / 64.0 - 1.0).astype(np.float32)
+        G = 24
+        boxed = model.cells(pos, G, lo=(-1.0,) * 3, hi=(3.0,) * 3)
+        unit = model.cells(((pos.astype(np.float64) + 1.0) / 4.0).astype(np.float32), G)
+        assert np.array_equal(boxed, unit)
+        p01 = g.random((d, 500)).astype(np.float32)
+        assert np.array_equal(model.cells(p01, 17, lo=(0.0,) * 3, hi=(1.0,) * 3), model.cells(p01, 17))
