@@ -50,9 +50,8 @@ size_t carve(nnc_ctx *c, char *base)
     c->frontier = k.take<int32_t>(n);
     c->grid.counts = k.take<int>(nc);
     c->grid.cell_start = k.take<int>(nc + 1);
-    c->grid.perm = k.take<int>(n);
     c->grid.rank = k.take<int>(n);
-    c->grid.sorted = k.take<float>(n * (size_t)c->d);
+    c->grid.slots = k.take<float4>(n);
     // histograms padded to whole int4 groups (the entropy scans them four cells at a time)
     c->hist_fail = k.take<int32_t>((nc + 3) / 4 * 4);
     c->hist_cand = k.take<int32_t>((nc + 3) / 4 * 4);

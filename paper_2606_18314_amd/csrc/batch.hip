@@ -52,8 +52,8 @@ struct BatchArgs {
     double guard, K;
     DevScalars *sc;
     const float *pos_prev, *pos_cur;
-    float *sorted;
-    int *cell, *counts, *rank, *perm, *cell_start, *cursor;
+    float4 *slots;  // slot records {x, y, z, point index}, indexed by poff + slot
+    int *cell, *counts, *rank, *cell_start, *cursor;
     int *nn, *stamp, *frontier, *hist_fail, *touched_fail, *hist_cand, *touched_cand;
     float *d1, *d2;
     double *e;
@@ -101,11 +101,7 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
         const bool d3 = sd.d == 3;
         const float x0 = po[i], y0 = po[n1 + i], z0 = d3 ? po[n2 + i] : 0.f;
         const float x1 = pn[i], y1 = pn[n1 + i], z1 = d3 ? pn[n2 + i] : 0.f;
-        const int k = a.rank[sd.poff + i];
-        float *so = a.sorted + sd.coff;
-        so[k] = x1;
-        so[n1 + k] = y1;
-        if (d3) so[n2 + k] = z1;
+        a.slots[sd.poff + a.rank[sd.poff + i]] = make_float4(x1, y1, z1, __int_as_float(i));
         const bool ok = d3 ? all_finite<3>(x1, y1, z1) && all_finite<3>(x0, y0, z0)
                            : all_finite<2>(x1, y1, z1) && all_finite<2>(x0, y0, z0);
         if (ok) {
@@ -324,18 +320,15 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
     __syncthreads();
     const size_t n1 = (size_t)sd.n;
     const float *p = a.pos_cur + sd.coff;
-    float *so = a.sorted + sd.coff;
+    float4 *so = a.slots + sd.poff;
     for (int i = (int)threadIdx.x; i < sd.n; i += kFB) {
         const int k = atomicAdd(&a.cursor[sd.goff + a.cell[sd.poff + i]], 1);
         if (k >= sd.n) {
             atomicOr(&a.sc[s].err, kErrOverflow);
             continue;
         }
-        a.perm[sd.poff + k] = i;
         a.rank[sd.poff + i] = k;
-        so[k] = p[i];
-        so[n1 + k] = p[n1 + i];
-        if (sd.d == 3) so[2 * n1 + k] = p[2 * n1 + i];
+        so[k] = make_float4(p[i], p[n1 + i], sd.d == 3 ? p[2 * n1 + i] : 0.0f, __int_as_float(i));
     }
 }
 
@@ -344,9 +337,8 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
 {
     QueryArgs q;
     q.pos = a.pos_cur + sd.coff;
-    q.sorted = a.sorted + sd.coff;
+    q.slots = a.slots + sd.poff;
     q.cell_start = a.cell_start + sd.soff;
-    q.perm = a.perm + sd.poff;
     q.cell = a.cell + sd.poff;
     q.list = a.frontier + sd.poff;
     q.count_dev = nullptr;
@@ -558,12 +550,12 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     b->NC = NC;
     b->NS = NS;
     b->ntiles = (int)b->tile_scene.size();
-    const size_t S = (size_t)b->S, Pp = (size_t)(P > 0 ? P : 1), Qq = (size_t)(Q > 0 ? Q : 1);
+    const size_t S = (size_t)b->S, Pp = (size_t)(P > 0 ? P : 1);
     const size_t T = (size_t)(b->ntiles > 0 ? b->ntiles : 1);
     size_t bytes = 0;
     bytes += al(S * sizeof(nnc::SceneDesc)) + al(S * sizeof(nnc::DevScalars));
-    bytes += al(Qq * 4);                                       // sorted
-    bytes += 4 * al(Pp * 4);                                   // cell, rank, perm, nn
+    bytes += al(Pp * 16);                                      // slot records
+    bytes += 3 * al(Pp * 4);                                   // cell, rank, nn
     bytes += 2 * al(Pp * 4) + al(Pp * 8) + al(Pp);             // d1, d2, e, fail
     bytes += 4 * al(Pp * 4);                                   // stamp, frontier, touched x2
     bytes += 4 * al((size_t)NC * 4) + al((size_t)NS * 4);      // counts, cursor, hist x2, cell_start
@@ -589,10 +581,9 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     memset(&a, 0, sizeof(a));
     a.desc = (const nnc::SceneDesc *)take(S * sizeof(nnc::SceneDesc));
     a.sc = (nnc::DevScalars *)take(S * sizeof(nnc::DevScalars));
-    a.sorted = (float *)take(Qq * 4);
+    a.slots = (float4 *)take(Pp * 16);
     a.cell = (int *)take(Pp * 4);
     a.rank = (int *)take(Pp * 4);
-    a.perm = (int *)take(Pp * 4);
     a.nn = (int *)take(Pp * 4);
     a.d1 = (float *)take(Pp * 4);
     a.d2 = (float *)take(Pp * 4);

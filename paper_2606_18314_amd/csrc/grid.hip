@@ -12,8 +12,8 @@
 //                  up to 2^19 points, above that reduce-then-scan (counts per
 //                  tile, one scan, ordered writes).
 //   k_scan_cells   exclusive scan of the occupancy counts -> cell-start table.
-//   k_scatter      counting-sort scatter: slot order (perm, rank) and the
-//                  coordinates in slot order.
+//   k_scatter      counting-sort scatter: rank (point -> slot) and the slot
+//                  records {x, y, z, point index}.
 //   k_query        exact 2-NN of each query through the grid, one group of L
 //                  lanes per query: the 3^d block's rows are spread over the
 //                  lanes (contiguous slots, coalesced loads), partial top-2s
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(kB) k_cells_init(const float *__restrict__ pos
 template <int D>
 __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, const float *__restrict__ pnew,
                                                int n, int G, Box box, int *__restrict__ cell, int *__restrict__ counts,
-                                               const int *__restrict__ rank, float *__restrict__ sorted,
+                                               const int *__restrict__ rank, float4 *__restrict__ slots,
                                                DevScalars *sc, int parity)
 {
     // grid-stride over at most kIngestBlocks workgroups, each adding its maximum and
@@ -167,10 +167,7 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
     for (int i = blockIdx.x * kB + (int)threadIdx.x; i < n; i += gridDim.x * kB) {
         const float x0 = pold[i], y0 = pold[n1 + i], z0 = D == 3 ? pold[n2 + i] : 0.f;
         const float x1 = pnew[i], y1 = pnew[n1 + i], z1 = D == 3 ? pnew[n2 + i] : 0.f;
-        const int k = rank[i];
-        sorted[k] = x1;
-        sorted[n1 + k] = y1;
-        if constexpr (D == 3) sorted[n2 + k] = z1;
+        slots[rank[i]] = make_float4(x1, y1, z1, __int_as_float(i));
         if (all_finite<D>(x1, y1, z1) && all_finite<D>(x0, y0, z0)) {
             s = fmaxf(s, sqdist<D>(x0, y0, z0, x1, y1, z1));
             const int c = cell_id<D>(x1, y1, z1, G, box);
@@ -454,9 +451,8 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
 
 template <int D>
 __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, const int *__restrict__ cell, int n,
-                                                int *__restrict__ cursor, int *__restrict__ perm,
-                                                int *__restrict__ rank, float *__restrict__ sorted,
-                                                DevScalars *sc)
+                                                int *__restrict__ cursor, int *__restrict__ rank,
+                                                float4 *__restrict__ slots, DevScalars *sc)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= n) return;
@@ -465,11 +461,8 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
         atomicOr(&sc->err, kErrOverflow);
         return;
     }
-    perm[k] = i;
     rank[i] = k;
-    sorted[k] = pos[i];
-    sorted[(size_t)n + k] = pos[(size_t)n + i];
-    if constexpr (D == 3) sorted[2 * (size_t)n + k] = pos[2 * (size_t)n + i];
+    slots[k] = make_float4(pos[i], pos[(size_t)n + i], D == 3 ? pos[2 * (size_t)n + i] : 0.0f, __int_as_float(i));
 }
 
 template <int D, int L, bool UNIT>
@@ -518,7 +511,6 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
     __shared__ int s_cs[kCsMax];
     __shared__ int s_lo[RMAX], s_off[RMAX + 1], s_qoff[kTYMax + 1];
     const int G = a.G;
-    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int sx = tile % nsx, rest = tile / nsx;
     const int sy = rest % nsy, gz = D == 3 ? rest / nsy : 0;
@@ -562,8 +554,7 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         for (int m = (int)threadIdx.x; m < total; m += kTB) {
             while (s_off[k + 1] <= m) ++k;  // m increases, so k only moves forward
             const int slot = s_lo[k] + (m - s_off[k]);
-            s_p[m] = make_float4(a.sorted[slot], a.sorted[n1 + slot], D == 3 ? a.sorted[n2 + slot] : 0.0f,
-                                 __int_as_float(a.perm[slot]));
+            s_p[m] = a.slots[slot];
         }
     }
     __syncthreads();
@@ -585,10 +576,11 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
             z = v.z;
             i = __float_as_int(v.w);
         } else {
-            x = a.sorted[slot];
-            y = a.sorted[n1 + slot];
-            if constexpr (D == 3) z = a.sorted[n2 + slot];
-            i = a.perm[slot];
+            const float4 v = a.slots[slot];
+            x = v.x;
+            y = v.y;
+            if constexpr (D == 3) z = v.z;
+            i = __float_as_int(v.w);
         }
         Top2 t;
         t.init();
@@ -810,10 +802,10 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
     const int blocks = blocks_for(c->n, kB) < kIngestBlocks ? blocks_for(c->n, kB) : kIngestBlocks;
     if (c->d == 2)
         hipLaunchKernelGGL(k_ingest<2>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->box, c->cell,
-                           c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
+                           c->grid.counts, c->grid.rank, c->grid.slots, c->sc, parity);
     else
         hipLaunchKernelGGL(k_ingest<3>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->box, c->cell,
-                           c->grid.counts, c->grid.rank, c->grid.sorted, c->sc, parity);
+                           c->grid.counts, c->grid.rank, c->grid.slots, c->sc, parity);
     return check();
 }
 
@@ -862,10 +854,10 @@ int launch_grid_build(nnc_ctx *c, const float *pos)
         const int blocks = blocks_for(c->n, kB);
         if (c->d == 2)
             hipLaunchKernelGGL(k_scatter<2>, dim3(blocks), dim3(kB), 0, c->stream, pos, c->cell, (int)c->n,
-                               c->grid.cursor, c->grid.perm, c->grid.rank, c->grid.sorted, c->sc);
+                               c->grid.cursor, c->grid.rank, c->grid.slots, c->sc);
         else
             hipLaunchKernelGGL(k_scatter<3>, dim3(blocks), dim3(kB), 0, c->stream, pos, c->cell, (int)c->n,
-                               c->grid.cursor, c->grid.perm, c->grid.rank, c->grid.sorted, c->sc);
+                               c->grid.cursor, c->grid.rank, c->grid.slots, c->sc);
     }
     return check();
 }
@@ -876,9 +868,8 @@ QueryArgs query_args(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, 
 {
     QueryArgs a;
     a.pos = c->pos_cur;
-    a.sorted = c->grid.sorted;
+    a.slots = c->grid.slots;
     a.cell_start = c->grid.cell_start;
-    a.perm = c->grid.perm;
     a.cell = c->cell;
     a.list = list;
     a.count_dev = count_dev;

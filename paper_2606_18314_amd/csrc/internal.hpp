@@ -53,17 +53,17 @@ struct DevSync {
 };
 
 // Loose uniform grid: slots are grouped by the cell each point had when the grid
-// was last built; sorted[] holds the points' CURRENT coordinates in slot order
-// (ingest rewrites them every step through rank[]), and queries widen their
-// search by the motion accumulated since the build.
+// was last built; slot k holds one 16-byte record {x, y, z, point index} with the
+// point's CURRENT coordinates (z = 0 in the plane; ingest rewrites the record
+// every step through rank[]), and queries widen their search by the motion
+// accumulated since the build.
 struct Grid {
     int G, ncell;
     int *counts;        // [ncell] occupancy of current cells
     int *cell_start;    // [ncell+1] slot ranges of the build-time cells
     int *cursor;        // [ncell] scatter cursors
-    int *perm;          // [n] slot -> point index
     int *rank;          // [n] point index -> slot
-    float *sorted;      // [d][n] current coordinates in slot order
+    float4 *slots;      // [n] slot records {x, y, z, bits of the point index}
 };
 
 }  // namespace nnc
@@ -126,7 +126,7 @@ struct nnc_ctx {
 
     int64_t t;
     int pending;
-    int grid_fresh;               // grid built at the current step (sorted coords current)
+    int grid_fresh;               // grid built at the current step (slot records current)
     double drift_host;            // accumulated declared eps since the grid build; <0 unknown
     int steps_since_grid;
     int lanes;                    // lanes per query (16, 32 or 64)

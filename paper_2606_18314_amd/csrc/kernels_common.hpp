@@ -281,8 +281,8 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred)
 
 struct QueryArgs {
     const float *pos;          // current coordinates, point order
-    const float *sorted;       // current coordinates, slot order
-    const int *cell_start, *perm, *cell;
+    const float4 *slots;       // slot records {x, y, z, point index}, current coordinates
+    const int *cell_start, *cell;
     const int *list, *count_dev;
     int n, G, all, init, t, parity;
     int *nn, *stamp, *hist;
@@ -346,12 +346,9 @@ __device__ __forceinline__ void group_reduce(Top2 &t)
 template <int D>
 __device__ __forceinline__ void visit_slot(const QueryArgs &a, int k, float x, float y, float z, int i, Top2 &t)
 {
-    const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
-    const float xj = a.sorted[k];
-    const float yj = a.sorted[n1 + k];
-    const float zj = D == 3 ? a.sorted[n2 + k] : 0.0f;
-    const int j = a.perm[k];
-    const float s = sqdist<D>(x, y, z, xj, yj, zj);
+    const float4 r = a.slots[k];
+    const int j = __float_as_int(r.w);
+    const float s = sqdist<D>(x, y, z, r.x, r.y, r.z);
     if (j != i) t.push(s, j);
 }
 
@@ -620,10 +617,11 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     int i;
     float x, y, z = 0.f;
     if (a.all) {
-        i = a.perm[q];
-        x = a.sorted[q];
-        y = a.sorted[n1 + q];
-        if constexpr (D == 3) z = a.sorted[n2 + q];
+        const float4 r = a.slots[q];
+        i = __float_as_int(r.w);
+        x = r.x;
+        y = r.y;
+        if constexpr (D == 3) z = r.z;
     } else {
         i = a.list[q];
         if (i < 0 || i >= a.n) return;  // caller-supplied lists are checked
