@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
             const double Be = B - margin;
             widen = !__builtin_isinf(B) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel));
         } else {
-            group_search<D, 1, UNIT>(a, x, y, z, i, margin, 0, t);
+            group_search<D, 1, UNIT>(a, x, y, z, i, margin, __builtin_inf(), 0, t);
         }
         const int at = wave_append(&a.sc->nwide, widen);
         if (widen) {

@@ -12,6 +12,7 @@ namespace kc {
 
 constexpr double kFuzz = 0x1p-20;  // cell-boundary rounding allowance (coordinates)
 constexpr double kRel = 0x1p-20;   // relative allowance on drift and distances
+constexpr double kCutSlack = 0x1p-16;  // relative slack of the repair cut-off
 
 // Exclusive scan of one value per thread over a workgroup of NT threads.
 template <int NT>
@@ -352,41 +353,120 @@ __device__ __forceinline__ void visit_slot(const QueryArgs &a, int k, float x, f
     if (j != i) t.push(s, j);
 }
 
-// Cells of the 3^d block around (gx,gy,gz), clipped to the grid: 3^(d-1) rows,
-// each a contiguous run of slots.  Lanes first fetch one row's bounds each,
-// then walk the concatenated slots with stride L.
+// Axis gaps from a query point to the faces of its own cell, binary64: glo[k] to
+// the lower face, ghi[k] to the upper one (clamped at 0: the rounded cell id can
+// put a point a hair outside its cell; the search margin covers that).  A cell
+// of the block at offset -1 (+1) along axis k is at least glo[k] (ghi[k]) away
+// along that axis.
+template <int D, bool UNIT>
+__device__ __forceinline__ void cell_gaps(const QueryArgs &a, float x, float y, float z, int gx, int gy, int gz,
+                                          double (&glo)[3], double (&ghi)[3])
+{
+    const float pc[3] = {x, y, z};
+    const int gc[3] = {gx, gy, gz};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double f0, f1;
+        if constexpr (UNIT) {
+            const double invG = 1.0 / (double)a.G;
+            f0 = (double)gc[k] * invG;
+            f1 = (double)(gc[k] + 1) * invG;
+        } else {
+            const double lo = (double)a.box.lo[k], w = a.box.w[k];
+            f0 = lo + (double)gc[k] * w;
+            f1 = lo + (double)(gc[k] + 1) * w;
+        }
+        glo[k] = fmax((double)pc[k] - f0, 0.0);
+        ghi[k] = fmax(f1 - (double)pc[k], 0.0);
+    }
+}
+
+// Squared distance bound from the query to the row of cells at offsets (dy, dz),
+// over the y and z axes only.
+template <int D>
+__device__ __forceinline__ double row_gap2(const double (&glo)[3], const double (&ghi)[3], int dy, int dz)
+{
+    double g = dy < 0 ? glo[1] * glo[1] : dy > 0 ? ghi[1] * ghi[1] : 0.0;
+    if constexpr (D == 3) g += dz < 0 ? glo[2] * glo[2] : dz > 0 ? ghi[2] * ghi[2] : 0.0;
+    return g;
+}
+
+// The part of row (dy, dz) of the 3^d block that lies within T of the query
+// (T2 = T^2; +inf keeps the whole block): x range [xlo, xhi] (empty when xlo >
+// xhi); `cut` is set when a cell of the row inside the grid is left out.
+template <int D>
+__device__ __forceinline__ void block_row(const double (&glo)[3], const double (&ghi)[3], double T2, int gx, int G,
+                                          int dy, int dz, int &xlo, int &xhi, bool &cut)
+{
+    xlo = max(gx - 1, 0);
+    xhi = min(gx + 1, G - 1);
+    cut = false;
+    if (T2 == __builtin_inf()) return;
+    const double yz = row_gap2<D>(glo, ghi, dy, dz);
+    if (yz > T2) {
+        xlo = 1;
+        xhi = 0;
+        cut = true;
+        return;
+    }
+    if (gx > 0 && yz + glo[0] * glo[0] > T2) {
+        xlo = gx;
+        cut = true;
+    }
+    if (gx < G - 1 && yz + ghi[0] * ghi[0] > T2) {
+        xhi = gx;
+        cut = true;
+    }
+}
+
+// The cells of the 3^d block around (gx,gy,gz) that lie within T of the query,
+// clipped to the grid: 3^(d-1) rows, each a contiguous run of slots.  Lanes first
+// fetch one row's bounds each, then walk the concatenated slots with stride L.
+// Returns (to every lane of the group) whether a cell of the block was left out.
 template <int D, int L>
-__device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
-                                           int gz, int lane, Top2 &t)
+__device__ __forceinline__ bool scan_block(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
+                                           int gz, const double (&glo)[3], const double (&ghi)[3], double T2,
+                                           int lane, Top2 &t)
 {
     constexpr int R = D == 3 ? 9 : 3;
     const int G = a.G;
     if constexpr (L == 1) {
         // one thread per query: walk the block's rows one after another
-        const int xlo = max(gx - 1, 0), xhi = min(gx + 1, G - 1);
+        bool any = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int cy = gy + r % 3 - 1;
-            const int cz = D == 3 ? gz + r / 3 - 1 : 0;
+            const int dy = r % 3 - 1, dz = D == 3 ? r / 3 - 1 : 0;
+            const int cy = gy + dy, cz = gz + dz;
             if (cy < 0 || cy >= G || cz < 0 || cz >= (D == 3 ? G : 1)) continue;
+            int xlo, xhi;
+            bool cut;
+            block_row<D>(glo, ghi, T2, gx, G, dy, dz, xlo, xhi, cut);
+            any |= cut;
+            if (xlo > xhi) continue;
             const int row = (cz * G + cy) * G;
             const int k1 = a.cell_start[row + xhi + 1];
             for (int k = a.cell_start[row + xlo]; k < k1; ++k) visit_slot<D>(a, k, x, y, z, i, t);
         }
-        return;
+        return any;
     }
     static_assert(L == 1 || L >= R, "a group needs one lane per row");
     int rs = 0, rl = 0;
+    bool cut = false;
     if (lane < R) {
-        const int cy = gy + lane % 3 - 1;
-        const int cz = D == 3 ? gz + lane / 3 - 1 : 0;
+        const int dy = lane % 3 - 1, dz = D == 3 ? lane / 3 - 1 : 0;
+        const int cy = gy + dy, cz = gz + dz;
         if (cy >= 0 && cy < G && cz >= 0 && cz < (D == 3 ? G : 1)) {
-            const int row = (cz * G + cy) * G;
-            const int xlo = max(gx - 1, 0), xhi = min(gx + 1, G - 1);
-            rs = a.cell_start[row + xlo];
-            rl = a.cell_start[row + xhi + 1] - rs;
+            int xlo, xhi;
+            block_row<D>(glo, ghi, T2, gx, G, dy, dz, xlo, xhi, cut);
+            if (xlo <= xhi) {
+                const int row = (cz * G + cy) * G;
+                rs = a.cell_start[row + xlo];
+                rl = a.cell_start[row + xhi + 1] - rs;
+            }
         }
     }
+    const unsigned long long gmask = L == 64 ? ~0ull : ((1ull << L) - 1) << (lane_id() & ~(unsigned)(L - 1));
+    const bool any = (__ballot(cut) & gmask) != 0;
     int incl = rl;
 #pragma unroll
     for (int off = 1; off < R; off <<= 1) {
@@ -410,7 +490,7 @@ __device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y,
             const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
             if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
         }
-        return;
+        return any;
     }
     int rstart[R], rpre[R];
 #pragma unroll
@@ -429,6 +509,7 @@ __device__ __forceinline__ void scan_block(const QueryArgs &a, float x, float y,
         }
         visit_slot<D>(a, sr + (k - pr), x, y, z, i, t);
     }
+    return any;
 }
 
 // One x-contiguous run of the ring of cells at Chebyshev distance exactly r
@@ -481,23 +562,21 @@ __device__ __forceinline__ bool ring_run(int u, int r, int gx, int gy, int gz, i
     return true;
 }
 
-// Visit every slot of the ring r >= 2.  Runs are taken L at a time: each lane
+// Visit every slot of a list of x-contiguous runs of cells; run(u, row, xlo,
+// xhi) gives run u (false: empty).  Runs are taken L at a time: each lane
 // fetches one run's slot range, a group scan concatenates them, and the lanes
 // walk the concatenation with stride L, finding each slot's run by a binary
 // search over the group (all loops are uniform over the group, so every
 // shuffle reads an active lane).
-template <int D, int L>
-__device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
-                                          int gz, int r, int lane, Top2 &t)
+template <int D, int L, class Run>
+__device__ __forceinline__ void scan_runs(const QueryArgs &a, float x, float y, float z, int i, int nruns,
+                                          int lane, Top2 &t, Run run)
 {
-    const int G = a.G;
-    const int m2 = 2 * r - 1;
-    const int nruns = D == 3 ? 2 * (2 * r + 1) + 2 * m2 + 2 * m2 * m2 : 2 + 2 * m2;
     for (int c0 = 0; c0 < nruns; c0 += L) {
         const int u = c0 + lane;
         int rs = 0, rl = 0;
         int row, xlo, xhi;
-        if (u < nruns && ring_run<D>(u, r, gx, gy, gz, G, row, xlo, xhi)) {
+        if (u < nruns && run(u, row, xlo, xhi)) {
             rs = a.cell_start[row + xlo];
             rl = a.cell_start[row + xhi + 1] - rs;
         }
@@ -524,6 +603,54 @@ __device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, 
     }
 }
 
+// Every slot of the ring r >= 2.
+template <int D, int L>
+__device__ __forceinline__ void scan_ring(const QueryArgs &a, float x, float y, float z, int i, int gx, int gy,
+                                          int gz, int r, int lane, Top2 &t)
+{
+    const int G = a.G;
+    const int m2 = 2 * r - 1;
+    const int nruns = D == 3 ? 2 * (2 * r + 1) + 2 * m2 + 2 * m2 * m2 : 2 + 2 * m2;
+    scan_runs<D, L>(a, x, y, z, i, nruns, lane, t, [&](int u, int &row, int &xlo, int &xhi) {
+        return ring_run<D>(u, r, gx, gy, gz, G, row, xlo, xhi);
+    });
+}
+
+// The cells of the 3^d block that scan_block left out for the same T2: per row
+// two runs, the whole row when it was cut entirely, else its cut end cells.
+template <int D, int L>
+__device__ __forceinline__ void scan_block_rest(const QueryArgs &a, float x, float y, float z, int i, int gx,
+                                                int gy, int gz, const double (&glo)[3], const double (&ghi)[3],
+                                                double T2, int lane, Top2 &t)
+{
+    constexpr int R = D == 3 ? 9 : 3;
+    const int G = a.G;
+    scan_runs<D, L>(a, x, y, z, i, 2 * R, lane, t, [&](int u, int &row, int &xlo, int &xhi) {
+        const int r = u >> 1, side = u & 1;
+        const int dy = r % 3 - 1, dz = D == 3 ? r / 3 - 1 : 0;
+        const int cy = gy + dy, cz = gz + dz;
+        if (cy < 0 || cy >= G || cz < 0 || cz >= (D == 3 ? G : 1)) return false;
+        int klo, khi;
+        bool cut;
+        block_row<D>(glo, ghi, T2, gx, G, dy, dz, klo, khi, cut);
+        if (!cut) return false;
+        row = (cz * G + cy) * G;
+        if (klo > khi) {  // the whole row was left out
+            xlo = max(gx - 1, 0);
+            xhi = min(gx + 1, G - 1);
+            return side == 0;
+        }
+        if (side == 0) {
+            xlo = max(gx - 1, 0);
+            xhi = klo - 1;
+        } else {
+            xlo = khi + 1;
+            xhi = min(gx + 1, G - 1);
+        }
+        return xlo <= xhi;
+    });
+}
+
 // Cell of a query point and the enclosure bound: the unit box (UNIT, with the
 // constants folded) or the scene's domain box.
 template <bool UNIT>
@@ -545,14 +672,36 @@ __device__ __forceinline__ double query_bound(const QueryArgs &a, float x, float
         return outside_bound<D>(x, y, z, gx, gy, gz, r, a.G, a.box);
 }
 
+// Exact top-2 of (x,y,z) (point i excluded).  T is a cut-off on cell distance:
+// an upper bound on the distance to the second neighbour plus the search margin
+// (+inf: no bound known).  The first pass scans only the cells of the 3^d block
+// within T; if its result is not enclosed by the cells it scanned (a left-out
+// cell's points are farther than T - margin), the rest of the block is scanned
+// and the search widens ring by ring as without a bound.  The bound only decides
+// the order of the work: the result is exact for any T.
 template <int D, int L, bool UNIT>
-__device__ void group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, int lane,
-                             Top2 &t)
+__device__ void group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, double T,
+                             int lane, Top2 &t)
 {
     const int gx = query_cell<UNIT>(a, x, 0), gy = query_cell<UNIT>(a, y, 1);
     const int gz = D == 3 ? query_cell<UNIT>(a, z, 2) : 0;
-    scan_block<D, L>(a, x, y, z, i, gx, gy, gz, lane, t);
+    double glo[3] = {0.0, 0.0, 0.0}, ghi[3] = {0.0, 0.0, 0.0};
+    double T2 = __builtin_inf();
+    if (T < __builtin_inf()) {
+        cell_gaps<D, UNIT>(a, x, y, z, gx, gy, gz, glo, ghi);
+        T2 = T * T;
+    }
+    const bool cut = scan_block<D, L>(a, x, y, z, i, gx, gy, gz, glo, ghi, T2, lane, t);
     group_reduce<L>(t);
+    if (cut) {
+        // the cells left out are farther than T, their points farther than T - margin
+        const double B = query_bound<D, UNIT>(a, x, y, z, gx, gy, gz, 1);
+        const double Be = fmin(B, T) - margin;
+        if (Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel)) return;
+        if (lane != 0) t.init();
+        scan_block_rest<D, L>(a, x, y, z, i, gx, gy, gz, glo, ghi, T2, lane, t);
+        group_reduce<L>(t);
+    }
     for (int r = 1;; ++r) {
         const double B = query_bound<D, UNIT>(a, x, y, z, gx, gy, gz, r);
         if (__builtin_isinf(B)) break;  // the whole grid has been visited
@@ -607,6 +756,23 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
     }
 }
 
+// First-pass cut-off of a repair query from the point's previous certificate
+// (d1, d2, expiry key e, made at clock S_i): every point has moved at most
+// S_t - S_i since (the clock sums the measured maximum steps), so the two old
+// neighbours lie within d2 + 2 (S_t - S_i) of the query, which bounds its new
+// second-neighbour distance.  S_i is recovered from the key (e - (c - g d2) K).
+// The relative slack covers the rounding of the stored values; a bound that is
+// still too small only costs the second pass of group_search.
+__device__ __forceinline__ double repair_cutoff(float d1, float d2, double e, double St, double guard, double K,
+                                                double margin)
+{
+    if (!(d2 < kInf) || !(e < __builtin_inf())) return __builtin_inf();
+    const float c = d2 - d1;
+    const double Si = e - ((double)c - guard * (double)d2) * K;
+    const double dS = fmax(St - Si, 0.0);
+    return ((double)d2 + 2.0 * dS) * (1.0 + kCutSlack) + margin;
+}
+
 // Query q of a scene (the q-th candidate, or the q-th slot when recomputing all
 // points) by the L lanes of one group; lane 0 writes the new certificate, its
 // expiry key, stamp and failure flag, and counts a failure in the histogram.
@@ -630,9 +796,11 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
         if constexpr (D == 3) z = a.pos[n2 + i];
     }
     const int old = lane == 0 ? a.nn[i] : 0;  // fetched early, used at the end
+    double T = __builtin_inf();
+    if (!a.all && !a.init) T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
     Top2 t;
     t.init();
-    group_search<D, L, UNIT>(a, x, y, z, i, margin, lane, t);
+    group_search<D, L, UNIT>(a, x, y, z, i, margin, T, lane, t);
     if (lane == 0) write_certificate(a, i, t, St, old);
 }
 
