@@ -797,7 +797,7 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     }
     const int old = lane == 0 ? a.nn[i] : 0;  // fetched early, used at the end
     double T = __builtin_inf();
-    if (!a.all && !a.init) T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
+    if (!a.init) T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
     Top2 t;
     t.init();
     group_search<D, L, UNIT>(a, x, y, z, i, margin, T, lane, t);
