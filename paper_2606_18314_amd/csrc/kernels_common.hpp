@@ -756,7 +756,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
     }
 }
 
-// First-pass cut-off of a repair query from the point's previous certificate
+// First-pass cut-off of a query (repair or rebuild) from the point's previous certificate
 // (d1, d2, expiry key e, made at clock S_i): every point has moved at most
 // S_t - S_i since (the clock sums the measured maximum steps), so the two old
 // neighbours lie within d2 + 2 (S_t - S_i) of the query, which bounds its new
