@@ -300,6 +300,29 @@ def test_isolated_point_forces_widening(nnc):
     run_parity(nnc, synth.Trajectory("custom", 3, n, -1.0, p3.astype(np.float32)), G=25, lanes=32)
 
 
+@pytest.mark.parametrize("lanes", [1, 16, 64])
+@pytest.mark.parametrize("d", [2, 3])
+def test_cutoff_with_mixed_density_and_large_steps(nnc, d, lanes):
+    """Dense clusters beside sparse outliers on a fine grid, with steps that vary
+    tenfold: the first pass of a query scans only the block cells within the cut-off
+    from its previous certificate; outliers fail the enclosure test and must scan the
+    cells left out and widen, dense points are enclosed by the cut-off alone.  Every
+    step (repairs and, every fourth, a rebuild) against the oracle."""
+    g = np.random.default_rng(600 + d + lanes)
+    n = 3000
+    p = g.random((d, n))
+    dense = n - 120                      # 120 uniform outliers, the rest in 4 clusters
+    centres = 0.2 + 0.6 * g.random((d, 4))
+    lab = g.integers(0, 4, dense)
+    p[:, :dense] = centres[:, lab] + 0.01 * g.standard_normal((d, dense))
+    frames = [p]
+    for t in range(10):
+        scale = 2e-5 if t % 3 else 2e-4
+        frames.append(frames[-1] + scale * g.standard_normal((d, n)))
+    tr = synth.Trajectory("custom", d, n, -1.0, np.array(frames, dtype=np.float32))
+    run_parity(nnc, tr, G=90 if d == 3 else 300, lanes=lanes, strategy="alternate")
+
+
 def test_points_outside_the_box_and_one_cell(nnc):
     g = np.random.default_rng(2)
     n = 600
