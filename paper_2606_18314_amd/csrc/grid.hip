@@ -637,7 +637,7 @@ __global__ void __launch_bounds__(kB) k_finish_all(QueryArgs a, const int *__res
     t.s1 = __int_as_float(r.y);
     t.s2 = __int_as_float(r.z);
     const double St = a.sc->S[a.parity];
-    write_certificate(a, i, t, St, a.nn[i]);
+    write_certificate(a, i, t, St, a.nn[i], -1);
 }
 
 // Normalised entropy (Definition 2) of the failures (which = 0) or candidates

@@ -678,13 +678,15 @@ __device__ __forceinline__ double query_bound(const QueryArgs &a, float x, float
 // within T; if its result is not enclosed by the cells it scanned (a left-out
 // cell's points are farther than T - margin), the rest of the block is scanned
 // and the search widens ring by ring as without a bound.  The bound only decides
-// the order of the work: the result is exact for any T.
+// the order of the work: the result is exact for any T.  Returns the linear id of
+// the query's cell (the same formula as the cell ids of the ingest).
 template <int D, int L, bool UNIT>
-__device__ void group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, double T,
-                             int lane, Top2 &t)
+__device__ int group_search(const QueryArgs &a, float x, float y, float z, int i, double margin, double T,
+                            int lane, Top2 &t)
 {
     const int gx = query_cell<UNIT>(a, x, 0), gy = query_cell<UNIT>(a, y, 1);
     const int gz = D == 3 ? query_cell<UNIT>(a, z, 2) : 0;
+    const int cell = gx + a.G * gy + (D == 3 ? a.G * a.G * gz : 0);
     double glo[3] = {0.0, 0.0, 0.0}, ghi[3] = {0.0, 0.0, 0.0};
     double T2 = __builtin_inf();
     if (T < __builtin_inf()) {
@@ -697,7 +699,7 @@ __device__ void group_search(const QueryArgs &a, float x, float y, float z, int 
         // the cells left out are farther than T, their points farther than T - margin
         const double B = query_bound<D, UNIT>(a, x, y, z, gx, gy, gz, 1);
         const double Be = fmin(B, T) - margin;
-        if (Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel)) return;
+        if (Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel)) return cell;
         if (lane != 0) t.init();
         scan_block_rest<D, L>(a, x, y, z, i, gx, gy, gz, glo, ghi, T2, lane, t);
         group_reduce<L>(t);
@@ -713,6 +715,7 @@ __device__ void group_search(const QueryArgs &a, float x, float y, float z, int 
         scan_ring<D, L>(a, x, y, z, i, gx, gy, gz, r + 1, lane, t);
         group_reduce<L>(t);
     }
+    return cell;
 }
 
 // Search margin: cell-boundary rounding plus the motion accumulated since the
@@ -725,8 +728,10 @@ __device__ __forceinline__ double query_margin(double St, double S_grid, double 
 
 // The new certificate of point i from its exact top-2 (old: its previous nearest
 // neighbour): distances, expiry key, stamp, failure flag, failure histogram (and,
-// for a batch scene, its failure count and touched-cell list).
-__device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old)
+// for a batch scene, its failure count and touched-cell list).  cell: the point's
+// current cell id, or -1 to read it.
+__device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old,
+                                                 int cell)
 {
     const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
     a.nn[i] = t.nn;
@@ -738,7 +743,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
     a.fail[i] = f ? 1 : 0;
     if (a.touched == nullptr) {
         // histogram only (the entropy scans it): no shared counters
-        if (f) atomicAdd(&a.hist[a.cell[i]], 1);
+        if (f) atomicAdd(&a.hist[cell >= 0 ? cell : a.cell[i]], 1);
         return;
     }
     // failure count and first touch of each cell: one counter atomic per wave
@@ -748,7 +753,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
         int c = 0;
         bool first = false;
         if (f) {
-            c = a.cell[i];
+            c = cell >= 0 ? cell : a.cell[i];
             first = atomicAdd(&a.hist[c], 1) == 0;
         }
         const int at = wave_append(&a.sc->ntouched, first);
@@ -800,8 +805,8 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     if (!a.init) T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
     Top2 t;
     t.init();
-    group_search<D, L, UNIT>(a, x, y, z, i, margin, T, lane, t);
-    if (lane == 0) write_certificate(a, i, t, St, old);
+    const int cell = group_search<D, L, UNIT>(a, x, y, z, i, margin, T, lane, t);
+    if (lane == 0) write_certificate(a, i, t, St, old, cell);
 }
 
 // Selector features of one scene-step (the same six numbers for a single scene
