@@ -353,6 +353,40 @@ __device__ __forceinline__ void visit_slot(const QueryArgs &a, int k, float x, f
     if (j != i) t.push(s, j);
 }
 
+// Visit the `total` slots of a concatenation of runs, L lanes at a time;
+// slot_of(k) maps position k of the concatenation to its slot (it may shuffle
+// within the group, so every lane calls it).  Past the first L positions the
+// positions are taken four strides at a time: the four slots are found first and
+// their records loaded together, so a long walk waits for one memory round trip
+// per 4L slots instead of one per L.  Positions past the end load the last slot
+// (a valid address) and are not visited.
+template <int D, int L, class SlotOf>
+__device__ __forceinline__ void walk_slots(const QueryArgs &a, float x, float y, float z, int i, int total,
+                                           int lane, Top2 &t, SlotOf slot_of)
+{
+    constexpr int U = 4;
+    if (total <= 0) return;
+    if (total <= L) {
+        const int slot = slot_of(min(lane, total - 1));
+        if (lane < total) visit_slot<D>(a, slot, x, y, z, i, t);
+        return;
+    }
+    for (int b = 0; b < total; b += U * L) {
+        int sl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) sl[u] = slot_of(min(b + u * L + lane, total - 1));
+        float4 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = a.slots[sl[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = __float_as_int(r[u].w);
+            const float s2 = sqdist<D>(x, y, z, r[u].x, r[u].y, r[u].z);
+            if (b + u * L + lane < total && j != i) t.push(s2, j);
+        }
+    }
+}
+
 // Axis gaps from a query point to the faces of its own cell, binary64: glo[k] to
 // the lower face, ghi[k] to the upper one (clamped at 0: the rounded cell id can
 // put a point a hair outside its cell; the search margin covers that).  A cell
@@ -478,18 +512,15 @@ __device__ __forceinline__ bool scan_block(const QueryArgs &a, float x, float y,
         // nine rows: each slot finds its row by a binary search over the rows'
         // prefixes held by lanes 0..8 (lanes 9.. hold an empty row at the end)
         const int pre = lane < R ? incl - rl : total;
-        for (int b = 0; b < total; b += L) {
-            const int k = b + lane;
-            const int kk = min(k, total - 1);
+        walk_slots<D, L>(a, x, y, z, i, total, lane, t, [&](int kk) {
             int lo = 0;
 #pragma unroll
             for (int step = 8; step > 0; step >>= 1) {
                 const int p = __shfl(pre, lo + step, L);
                 if (p <= kk) lo += step;
             }
-            const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
-            if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
-        }
+            return __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
+        });
         return any;
     }
     int rstart[R], rpre[R];
@@ -498,17 +529,16 @@ __device__ __forceinline__ bool scan_block(const QueryArgs &a, float x, float y,
         rstart[r] = __shfl(rs, r, L);
         rpre[r] = __shfl(incl - rl, r, L);
     }
-#pragma unroll 4
-    for (int k = lane; k < total; k += L) {
+    walk_slots<D, L>(a, x, y, z, i, total, lane, t, [&](int kk) {
         int sr = rstart[0], pr = rpre[0];
 #pragma unroll
         for (int u = 1; u < R; ++u) {
-            const bool in = k >= rpre[u];
+            const bool in = kk >= rpre[u];
             sr = in ? rstart[u] : sr;
             pr = in ? rpre[u] : pr;
         }
-        visit_slot<D>(a, sr + (k - pr), x, y, z, i, t);
-    }
+        return sr + (kk - pr);
+    });
     return any;
 }
 
@@ -588,18 +618,15 @@ __device__ __forceinline__ void scan_runs(const QueryArgs &a, float x, float y, 
         }
         const int total = __shfl(incl, L - 1, L);
         const int pre = incl - rl;
-        for (int b = 0; b < total; b += L) {
-            const int k = b + lane;
-            const int kk = min(k, total - 1);
+        walk_slots<D, L>(a, x, y, z, i, total, lane, t, [&](int kk) {
             int lo = 0;
 #pragma unroll
             for (int step = L / 2; step > 0; step >>= 1) {
                 const int p = __shfl(pre, lo + step, L);
                 if (p <= kk) lo += step;
             }
-            const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
-            if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
-        }
+            return __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
+        });
     }
 }
 
