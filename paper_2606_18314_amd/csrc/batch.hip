@@ -342,6 +342,7 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     q.cell = a.cell + sd.poff;
     q.list = a.frontier + sd.poff;
     q.count_dev = nullptr;
+    q.list_cap = 0;
     q.n = sd.n;
     q.G = sd.G;
     q.all = a.strategy[s];

@@ -468,13 +468,18 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
 template <int D, int L, bool UNIT>
 __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 {
+    const int lane = threadIdx.x & (L - 1);
+    constexpr int GPB = kB / L;
+    int q = blockIdx.x * GPB + (int)(threadIdx.x / L);
+    // the first list entry is read in the same round trip as the count (an entry
+    // past the count is never used)
+    const bool pre = !a.all && q < a.list_cap;
+    const int i_pre = pre ? a.list[q] : 0;
     const int count = a.all ? a.n : min(*a.count_dev, a.n);
     const double St = a.sc->S[a.parity];
     const double margin = query_margin(St, a.sc->S_grid, a.fuzz);
-    const int lane = threadIdx.x & (L - 1);
-    constexpr int GPB = kB / L;
-    for (int q = blockIdx.x * GPB + (int)(threadIdx.x / L); q < count; q += gridDim.x * GPB)
-        query_one<D, L, UNIT>(a, q, St, margin, lane);
+    for (bool first = true; q < count; q += gridDim.x * GPB, first = false)
+        query_one<D, L, UNIT>(a, q, St, margin, lane, first && pre, i_pre);
 }
 
 // All-point query (rebuild and initialisation, right after a grid build), tiled
@@ -873,6 +878,7 @@ QueryArgs query_args(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, 
     a.cell = c->cell;
     a.list = list;
     a.count_dev = count_dev;
+    a.list_cap = list == c->frontier || list == c->wide ? (int)c->n : 0;
     a.n = (int)c->n;
     a.G = c->G;
     a.all = all;

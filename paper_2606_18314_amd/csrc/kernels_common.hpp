@@ -285,6 +285,8 @@ struct QueryArgs {
     const float4 *slots;       // slot records {x, y, z, point index}, current coordinates
     const int *cell_start, *cell;
     const int *list, *count_dev;
+    int list_cap;              // entries of list readable past the count (the library's own
+                               // lists hold n; 0 for a caller's list)
     int n, G, all, init, t, parity;
     int *nn, *stamp, *hist;
     int *touched;              // a batch scene's list of touched cells (with its counters);
@@ -809,7 +811,8 @@ __device__ __forceinline__ double repair_cutoff(float d1, float d2, double e, do
 // points) by the L lanes of one group; lane 0 writes the new certificate, its
 // expiry key, stamp and failure flag, and counts a failure in the histogram.
 template <int D, int L, bool UNIT>
-__device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, double margin, int lane)
+__device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, double margin, int lane,
+                                          bool have_i = false, int i_pre = 0)
 {
     const size_t n1 = (size_t)a.n, n2 = 2 * (size_t)a.n;
     int i;
@@ -821,7 +824,7 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
         y = r.y;
         if constexpr (D == 3) z = r.z;
     } else {
-        i = a.list[q];
+        i = have_i ? i_pre : a.list[q];
         if (i < 0 || i >= a.n) return;  // caller-supplied lists are checked
         x = a.pos[i];
         y = a.pos[n1 + i];
