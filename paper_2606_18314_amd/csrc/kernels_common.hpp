@@ -361,7 +361,9 @@ __device__ __forceinline__ void visit_slot(const QueryArgs &a, int k, float x, f
 // positions are taken four strides at a time: the four slots are found first and
 // their records loaded together, so a long walk waits for one memory round trip
 // per 4L slots instead of one per L.  Positions past the end load the last slot
-// (a valid address) and are not visited.
+// (a valid address) and are not visited.  Used for the 3^3 block of a query in
+// the cube, whose walks are long; the shorter walks of the plane and of the rings
+// keep a plain stride-L loop, which measured faster there.
 template <int D, int L, class SlotOf>
 __device__ __forceinline__ void walk_slots(const QueryArgs &a, float x, float y, float z, int i, int total,
                                            int lane, Top2 &t, SlotOf slot_of)
@@ -531,16 +533,17 @@ __device__ __forceinline__ bool scan_block(const QueryArgs &a, float x, float y,
         rstart[r] = __shfl(rs, r, L);
         rpre[r] = __shfl(incl - rl, r, L);
     }
-    walk_slots<D, L>(a, x, y, z, i, total, lane, t, [&](int kk) {
+#pragma unroll 4
+    for (int k = lane; k < total; k += L) {
         int sr = rstart[0], pr = rpre[0];
 #pragma unroll
         for (int u = 1; u < R; ++u) {
-            const bool in = kk >= rpre[u];
+            const bool in = k >= rpre[u];
             sr = in ? rstart[u] : sr;
             pr = in ? rpre[u] : pr;
         }
-        return sr + (kk - pr);
-    });
+        visit_slot<D>(a, sr + (k - pr), x, y, z, i, t);
+    }
     return any;
 }
 
@@ -620,15 +623,18 @@ __device__ __forceinline__ void scan_runs(const QueryArgs &a, float x, float y, 
         }
         const int total = __shfl(incl, L - 1, L);
         const int pre = incl - rl;
-        walk_slots<D, L>(a, x, y, z, i, total, lane, t, [&](int kk) {
+        for (int b = 0; b < total; b += L) {
+            const int k = b + lane;
+            const int kk = min(k, total - 1);
             int lo = 0;
 #pragma unroll
             for (int step = L / 2; step > 0; step >>= 1) {
                 const int p = __shfl(pre, lo + step, L);
                 if (p <= kk) lo += step;
             }
-            return __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
-        });
+            const int slot = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
+            if (k < total) visit_slot<D>(a, slot, x, y, z, i, t);
+        }
     }
 }
 
