@@ -146,9 +146,9 @@ int timed(nnc_ctx *c, int cls, F &&launch)
     return rc;
 }
 
-int build_grid(nnc_ctx *c)
+int build_grid(nnc_ctx *c, bool from_slots = true)
 {
-    const int rc = timed(c, NNC_K_GRID, [&] { return nnc::launch_grid_build(c, c->pos_cur); });
+    const int rc = timed(c, NNC_K_GRID, [&] { return nnc::launch_grid_build(c, c->pos_cur, from_slots); });
     c->grid_fresh = 1;
     c->drift_host = 0.0;
     c->steps_since_grid = 0;
@@ -264,7 +264,7 @@ int nnc_init_certificates(nnc_ctx *c, const float *pos)
     // everything but the status words (whose epochs keep increasing) starts at zero
     if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
     int rc = nnc::launch_cells_init(c, c->pos_cur);
-    if (rc == NNC_OK) rc = build_grid(c);
+    if (rc == NNC_OK) rc = build_grid(c, false);  // no slot records yet
     if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query_all(c, 1); });
     c->inited = rc == NNC_OK;
     return rc;

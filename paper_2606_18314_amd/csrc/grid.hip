@@ -13,7 +13,10 @@
 //                  tile, one scan, ordered writes).
 //   k_scan_cells   exclusive scan of the occupancy counts -> cell-start table.
 //   k_scatter      counting-sort scatter: rank (point -> slot) and the slot
-//                  records {x, y, z, point index}.
+//                  records {x, y, z, point index}, in point order (the first
+//                  build); k_scatter_slots the same from the previous slot
+//                  order (every later build: runs of equal cells share one
+//                  atomic and write in sequence), then k_copy4 copies back.
 //   k_query        exact 2-NN of each query through the grid, one group of L
 //                  lanes per query: the 3^d block's rows are spread over the
 //                  lanes (contiguous slots, coalesced loads), partial top-2s
@@ -131,6 +134,11 @@ __global__ void k_fill(int *p, int value, size_t count)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         p[i] = value;
+}
+
+__global__ void __launch_bounds__(kB) k_copy4(const float4 *__restrict__ src, float4 *__restrict__ dst, int n)
+{
+    for (int k = blockIdx.x * kB + (int)threadIdx.x; k < n; k += gridDim.x * kB) dst[k] = src[k];
 }
 
 template <int D>
@@ -463,6 +471,57 @@ __global__ void __launch_bounds__(kB) k_scatter(const float *__restrict__ pos, c
     }
     rank[i] = k;
     slots[k] = make_float4(pos[i], pos[(size_t)n + i], D == 3 ? pos[2 * (size_t)n + i] : 0.0f, __int_as_float(i));
+}
+
+// Counting-sort scatter from the previous slot order (every grid build after the
+// first): slot k's record already holds its point's current coordinates, and
+// neighbouring slots mostly land in one new cell, so each run of equal cells over
+// consecutive lanes of a wave takes its slots with one atomic (by the run's last
+// lane) and writes them in sequence.  The cell is the ingest's formula on the same
+// coordinates (the maintained cell id for a non-finite point).  Records go to
+// `out`, to be copied back over the slots; rank[i] to the new slot.
+template <int D>
+__global__ void __launch_bounds__(kB) k_scatter_slots(const float4 *__restrict__ slots,
+                                                      const int *__restrict__ cell, int n, int G, Box box,
+                                                      int *__restrict__ cursor, int *__restrict__ rank,
+                                                      float4 *__restrict__ out, DevScalars *sc)
+{
+    const int k = blockIdx.x * kB + threadIdx.x;
+    float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int c = -1, i = 0;
+    bool act = k < n;
+    if (act) {
+        r = slots[k];
+        i = __float_as_int(r.w);
+        if (i < 0 || i >= n) {  // unreachable: the slots hold a permutation of the points
+            atomicOr(&sc->err, kErrOverflow);
+            act = false;
+        } else {
+            c = all_finite<D>(r.x, r.y, r.z) ? cell_id<D>(r.x, r.y, r.z, G, box) : cell[i];
+        }
+    }
+    // runs of equal cells: every lane finds the first (h) and last (e) lane of its run
+    const int lane = (int)lane_id();
+    const int cp = __shfl_up(c, 1), cn = __shfl_down(c, 1);
+    int h = lane == 0 || cp != c ? lane : 0;
+    int e = lane == 63 || cn != c ? lane : 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int vh = __shfl_up(h, off), ve = __shfl_down(e, off);
+        if (lane >= off) h = max(h, vh);
+        if (lane + off < 64) e = min(e, ve);
+    }
+    int base = 0;
+    if (act && lane == e) base = atomicAdd(&cursor[c], e - h + 1);
+    base = __shfl(base, e);
+    if (!act) return;
+    const int kn = base + (lane - h);
+    if (kn >= n) {  // unreachable while the counts match the cells
+        atomicOr(&sc->err, kErrOverflow);
+        return;
+    }
+    out[kn] = r;
+    rank[i] = kn;
 }
 
 template <int D, int L, bool UNIT>
@@ -848,14 +907,29 @@ int launch_filter(nnc_ctx *c, float eps_declared)
     return check();
 }
 
-int launch_grid_build(nnc_ctx *c, const float *pos)
+int launch_grid_build(nnc_ctx *c, const float *pos, bool from_slots)
 {
     const int parity = (int)(c->t & 1);
     const int tiles = blocks_for(c->ncell, kTile);
     if (tiles > c->nstatus) return NNC_E_INVAL;
     hipLaunchKernelGGL(k_scan_cells, dim3(tiles), dim3(kB), 0, c->stream, c->grid.counts, c->ncell,
                        c->grid.cell_start, c->grid.cursor, c->sc, c->sync, parity, c->status);
-    if (c->n > 0) {
+    if (c->n > 0 && from_slots) {
+        // the tiled pass's record buffer (16 bytes per point) holds the new order
+        // until it is copied back over the slots
+        const int blocks = blocks_for(c->n, kB);
+        float4 *tmp = reinterpret_cast<float4 *>(c->rec);
+        if (c->d == 2)
+            hipLaunchKernelGGL(k_scatter_slots<2>, dim3(blocks), dim3(kB), 0, c->stream,
+                               (const float4 *)c->grid.slots, (const int *)c->cell, (int)c->n, c->G, c->box,
+                               c->grid.cursor, c->grid.rank, tmp, c->sc);
+        else
+            hipLaunchKernelGGL(k_scatter_slots<3>, dim3(blocks), dim3(kB), 0, c->stream,
+                               (const float4 *)c->grid.slots, (const int *)c->cell, (int)c->n, c->G, c->box,
+                               c->grid.cursor, c->grid.rank, tmp, c->sc);
+        hipLaunchKernelGGL(k_copy4, dim3(blocks < 4096 ? blocks : 4096), dim3(kB), 0, c->stream,
+                           (const float4 *)tmp, c->grid.slots, (int)c->n);
+    } else if (c->n > 0) {
         const int blocks = blocks_for(c->n, kB);
         if (c->d == 2)
             hipLaunchKernelGGL(k_scatter<2>, dim3(blocks), dim3(kB), 0, c->stream, pos, c->cell, (int)c->n,

@@ -146,7 +146,9 @@ namespace nnc {
 int launch_cells_init(nnc_ctx *c, const float *pos);
 int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew);
 int launch_filter(nnc_ctx *c, float eps_declared);
-int launch_grid_build(nnc_ctx *c, const float *pos);
+// from_slots: the slot records hold every point's current coordinates (any build
+// after the first), and the scatter reads them in their previous order
+int launch_grid_build(nnc_ctx *c, const float *pos, bool from_slots);
 int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init);
 int launch_query_all(nnc_ctx *c, int init);
 int launch_entropy(nnc_ctx *c, int which);
