@@ -63,7 +63,8 @@ extern "C" {
 #define NNC_COPY_POSITIONS 1u  /* keep a private copy of each position frame */
 #define NNC_SYNC           2u  /* nnc_step synchronises and fills count_host */
 /* All-point queries (initialisation, rebuild) run tiled by grid cells with the
- * neighbourhood staged in LDS from N = 65536 on, pointwise below; these force one. */
+ * neighbourhood staged in LDS from N = 65536 on for initialisation and from
+ * N = 2^17 (d = 2) or 2^19 (d = 3) on for a rebuild, pointwise below; these force one. */
 #define NNC_QUERY_TILED     4u
 #define NNC_QUERY_POINTWISE 8u
 

@@ -229,7 +229,8 @@ class NNCert:
                  copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0,
                  all_query: str = "auto", box=None):
         """all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
-        query every point (tiled by cells from N = 65536 on under "auto").
+        query every point (under "auto" tiled by cells from N = 65536 on at
+        initialisation, from 2^17 (d = 2) or 2^19 (d = 3) on at a rebuild).
         box: (lo, hi), per-axis bounds of the grid's domain (default the unit box)."""
         if all_query not in ("auto", "tiled", "pointwise"):
             raise ValueError("all_query: 'auto', 'tiled' or 'pointwise'")

@@ -56,7 +56,12 @@ constexpr int kSmallMaxN = 4096;       // scenes up to this size use the one-wor
 constexpr long long kReduceScanMinN = 1 << 19;  // above this, the reduce-then-scan filter
 constexpr int kFlagA = 1, kFlagP = 2;
 constexpr unsigned kSpinLimit = 1u << 24;
-constexpr long long kTiledMinN = 65536;  // all-point queries are tiled from this size on
+// automatic choice of the all-point query: tiled from these sizes on.  A rebuild's
+// pointwise queries take the cut-off from the previous certificates, which keeps
+// them ahead of the tiled pass up to 2^17 points in the plane and 2^19 in the cube
+// (measured); initialisation has no certificates and tiles from 2^16.
+constexpr long long kTiledMinN = 65536;
+constexpr long long kTiledMinNRebuild2 = 1 << 17, kTiledMinNRebuild3 = 1 << 19;
 constexpr int kEntropyOneGroup4 = 1 << 15;  // histograms up to 2^17 cells: one-workgroup entropy
 constexpr int kIngestBlocks = 4096;  // at most 64 workgroups per spread slot
 
@@ -1005,8 +1010,8 @@ int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int 
 int launch_query_all(nnc_ctx *c, int init)
 {
     if (c->n == 0) return NNC_OK;
-    const bool tiled = (c->flags & NNC_QUERY_TILED) ||
-                       (!(c->flags & NNC_QUERY_POINTWISE) && c->n >= kTiledMinN);
+    const long long from = init ? kTiledMinN : c->d == 3 ? kTiledMinNRebuild3 : kTiledMinNRebuild2;
+    const bool tiled = (c->flags & NNC_QUERY_TILED) || (!(c->flags & NNC_QUERY_POINTWISE) && c->n >= from);
     if (!tiled) return launch_query(c, nullptr, nullptr, 1, init);
     // tile shape: the most queries per staged neighbour at the mean occupancy,
     // within the LDS stage and the cell-start table

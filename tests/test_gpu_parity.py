@@ -181,17 +181,21 @@ def test_tiled_all_point_query_families(nnc, family):
     run_parity(nnc, tr, G=20, strategy="alternate", all_query="tiled")
 
 
-def test_tiled_3d_at_the_automatic_threshold(nnc):
-    """N = 70000 in the cube, clustered: tiled rebuilds over cell patches (and the
-    widening pass) against the oracle."""
+def test_tiled_3d_rebuilds_at_70000_points(nnc):
+    """N = 70000 in the cube, clustered: tiled initialisation (the automatic choice)
+    and tiled rebuilds over cell patches (and the widening pass) against the oracle."""
     tr = synth.make_trajectory("clustered_drift", 70000, 3, 2, 5e-4, 4343)
-    run_parity(nnc, tr, G=40, strategy="rebuild")
+    run_parity(nnc, tr, G=40, strategy="rebuild", all_query="tiled")
 
 
-def test_tiled_is_the_default_from_65536_points(nnc):
-    """N = 66000 in the plane: the automatic choice tiles; two rebuilds checked."""
+def test_automatic_all_point_query_around_its_thresholds(nnc):
+    """The automatic choice: N = 66000 in the plane tiles its initialisation and
+    queries its rebuilds pointwise with the certificate cut-off; N = 140000 in the
+    plane tiles both.  Against the oracle (two rebuilds, then one)."""
     tr = synth.make_trajectory("uniform_brownian", 66000, 2, 2, 5e-4, 4242)
     run_parity(nnc, tr, G=128, strategy="rebuild")
+    tr = synth.make_trajectory("uniform_brownian", 140000, 2, 1, 5e-4, 4244)
+    run_parity(nnc, tr, G=187, strategy="rebuild")
 
 
 @pytest.mark.parametrize("n", [(1 << 19) + 1, 3 * (1 << 20) + 4097])
