@@ -657,14 +657,30 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         const int cz = D == 3 ? query_cell<UNIT>(a, z, 2) : 0;
         bool widen = false;
         if (staged && cx >= gx0 && cx < gx1 && cy >= gy0 && cy < gy1 && cz == gz) {
-            const int ulo = max(cx - 1, 0) - gl, uhi = min(cx + 1, G - 1) - gl + 1;
+            // a rebuild in the cube scans only the block cells within the cut-off
+            // from the point's previous certificate (initialisation, and the plane,
+            // whose blocks hold few points: the whole block; measured)
+            double T = __builtin_inf(), glo[3] = {0.0, 0.0, 0.0}, ghi[3] = {0.0, 0.0, 0.0};
+            if (D == 3 && !a.init) {
+                T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
+                cell_gaps<D, UNIT>(a, x, y, z, cx, cy, cz, glo, ghi);
+            }
+            const double T2 = T < __builtin_inf() ? T * T : __builtin_inf();
+            bool cut = false;
             const int k0 = cy - gy0;  // row of dy = -1 in each plane
 #pragma unroll
             for (int pz = 0; pz < (D == 3 ? 3 : 1); ++pz) {
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
+                    const int cyy = cy + dy - 1, czz = cz + pz - 1;
+                    if (cyy < 0 || cyy >= G || (D == 3 && (czz < 0 || czz >= G))) continue;  // empty rows
+                    int xlo, xhi;
+                    bool rc;
+                    block_row<D>(glo, ghi, T2, cx, G, dy - 1, pz - 1, xlo, xhi, rc);
+                    cut |= rc;
+                    if (xlo > xhi) continue;
                     const int k = k0 + dy + pz * ry;
-                    const int lo = s_cs[k * w1 + ulo], hi = s_cs[k * w1 + uhi];
+                    const int lo = s_cs[k * w1 + xlo - gl], hi = s_cs[k * w1 + xhi - gl + 1];
                     for (int m = lo; m < hi; ++m) {
                         const float4 v = s_p[m];
                         const float s = sqdist<D>(x, y, z, v.x, v.y, v.z);
@@ -674,8 +690,8 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                 }
             }
             const double B = query_bound<D, UNIT>(a, x, y, z, cx, cy, cz, 1);
-            const double Be = B - margin;
-            widen = !__builtin_isinf(B) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel));
+            const double Be = (cut ? fmin(B, T) : B) - margin;
+            widen = (cut || !__builtin_isinf(B)) && !(Be > 0.0 && (double)t.s2 < Be * Be * (1.0 - kRel));
         } else {
             group_search<D, 1, UNIT>(a, x, y, z, i, margin, __builtin_inf(), 0, t);
         }
