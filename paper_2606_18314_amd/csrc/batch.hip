@@ -370,47 +370,51 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     return q;
 }
 
-// Every workgroup takes one contiguous chunk of the concatenated query list (all
-// scenes' queries, scene by scene); its lane groups stride through the chunk, so
-// neighbouring groups take neighbouring queries.  A group finds the scene of its
-// first query once and steps to the next scene when it crosses a boundary.
+// Every wave takes one contiguous chunk of the concatenated query list (all
+// scenes' queries, scene by scene) and works on one scene at a time: per step its
+// 64 / L lane groups take the next queries of the current scene (fewer at the
+// scene's end), then the wave moves on.  The scene index is uniform over the wave,
+// so the scene's descriptor and pointers sit in scalar registers and a wave never
+// runs the plane and the cube search side by side.
 template <int L>
 __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
 {
-    constexpr int GPB = kB / L;
+    constexpr int GPW = 64 / L;  // lane groups per wave
     const int total = a.qpre[a.scenes];
     const int lane = threadIdx.x & (L - 1);
-    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int chunk = (per + GPB - 1) / GPB * GPB;
-    const int q0 = (int)blockIdx.x * chunk + (int)(threadIdx.x / L);
-    const int q1 = min((int)blockIdx.x * chunk + chunk, total);
-    if (q0 >= q1) return;
-    int lo = 0, hi = a.scenes;  // the last s with qpre[s] <= q0
+    const int grp = (int)(threadIdx.x & 63) / L;
+    const int nw = (int)gridDim.x * (kB / 64);
+    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kB / 64) + (int)(threadIdx.x >> 6));
+    const int per = (total + nw - 1) / nw;
+    int g = w * per;
+    const int q1 = min(g + per, total);
+    if (g >= q1) return;
+    int lo = 0, hi = a.scenes;  // the last s with qpre[s] <= g
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (a.qpre[mid] <= q0) lo = mid;
+        if (a.qpre[mid] <= g) lo = mid;
         else hi = mid;
     }
-    int s = lo;
-    int next = a.qpre[s + 1];
-    SceneDesc sd = a.desc[s];
-    QueryArgs q = scene_view(a, sd, s, init);
-    double St = a.sc[s].S[a.parity];
-    double margin = query_margin(St, a.sc[s].S_grid, kFuzz);
-    for (int g = q0; g < q1; g += GPB) {
-        while (g >= next) {  // uniform within the lane group
-            ++s;
-            next = a.qpre[s + 1];
-            sd = a.desc[s];
-            q = scene_view(a, sd, s, init);
-            St = a.sc[s].S[a.parity];
-            margin = query_margin(St, a.sc[s].S_grid, kFuzz);
+    int s = __builtin_amdgcn_readfirstlane(lo);
+    while (g < q1) {
+        const int first = a.qpre[s], next = a.qpre[s + 1];
+        if (g < next) {
+            const SceneDesc sd = a.desc[s];
+            const QueryArgs q = scene_view(a, sd, s, init);
+            const double St = a.sc[s].S[a.parity];
+            const double margin = query_margin(St, a.sc[s].S_grid, kFuzz);
+            const int end = min(next, q1);
+            for (; g < end; g += GPW) {
+                if (g + grp < end) {
+                    if (sd.d == 3)
+                        query_one<3, L, true>(q, g + grp - first, St, margin, lane);
+                    else
+                        query_one<2, L, true>(q, g + grp - first, St, margin, lane);
+                }
+            }
+            g = end;
         }
-        const int local = g - a.qpre[s];
-        if (sd.d == 3)
-            query_one<3, L, true>(q, local, St, margin, lane);
-        else
-            query_one<2, L, true>(q, local, St, margin, lane);
+        ++s;
     }
 }
 
