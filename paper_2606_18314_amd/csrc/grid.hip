@@ -19,12 +19,13 @@
 //                  atomic and write in sequence), then k_copy4 copies back.
 //   k_query        exact 2-NN of each query through the grid, one group of L
 //                  lanes per query: the 3^d block's rows are spread over the
-//                  lanes (contiguous slots, coalesced loads), partial top-2s
-//                  are merged by a butterfly, and the search widens ring by
-//                  ring until the second neighbour is provably enclosed
-//                  (Corollary 1); then the new certificate, expiry key,
-//                  failure flag and failure histogram.
-//   k_query_tiled  all-point query from N = 65536 on: cell patches with their
+//                  lanes (contiguous slots, coalesced loads; with a previous
+//                  certificate only the cells within its cut-off first),
+//                  partial top-2s are merged by a butterfly, and the search
+//                  widens ring by ring until the second neighbour is provably
+//                  enclosed (Corollary 1); then the new certificate, expiry
+//                  key, failure flag and failure histogram.
+//   k_query_tiled  all-point query of large scenes: cell patches with their
 //   k_finish_all   neighbourhood staged in LDS, slot-ordered records, then the
 //                  point-order certificates.
 //   k_entropy*     normalised entropy (Definition 2) from a scan of the cell
