@@ -318,6 +318,38 @@ def test_cube_16k_families_no_miss_reduced(family):
         assert sc.audit().size == 0
 
 
+@pytest.mark.parametrize("family", ["uniform_brownian", "adversarial_crossing", "clustered_drift"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_previous_certificate_bounds_the_new_second_distance(family, d):
+    """The search cut-off of the GPU queries: every point has moved at most S_t - S_i
+    since its certificate was made at clock S_i (the clock sums the measured maximum
+    steps), so its two old neighbours, hence its new second neighbour, lie within
+    d2 + 2 (S_t - S_i).  Checked against binary64 brute force at every step of
+    repaired trajectories, with S_i both tracked and recovered from the expiry key
+    as the kernels do (e - (c - gamma d2) K), within the kernels' relative slack."""
+    n = 1500
+    tr = synth.make_trajectory(family, n, d, 25, 2e-3, 900 + d)
+    sc = model.OracleScene(d=d, n=n, G=8)
+    sc.init_certificates(tr.frames[0])
+    K = 1.0 / (4.0 + 4.0 * sc.guard)
+    Si = np.zeros(n)                     # clock of each point's certificate
+    slack = 2.0 ** -16
+    for t in range(1, tr.steps + 1):
+        d1_old, d2_old, e_old = sc.d1.copy(), sc.d2.copy(), sc.e.copy()
+        res = sc.step(tr.frames[t])
+        c = (d2_old - d1_old).astype(np.float32).astype(np.float64)
+        Si_key = e_old - (c - sc.guard * d2_old.astype(np.float64)) * K
+        assert np.allclose(Si_key, Si, rtol=0, atol=1e-12)
+        p = tr.frames[t].astype(np.float64)
+        dist = np.sqrt(((p[:, :, None] - p[:, None, :]) ** 2).sum(axis=0))
+        np.fill_diagonal(dist, np.inf)
+        d2_true = np.partition(dist, 1, axis=1)[:, 1]
+        bound = (d2_old.astype(np.float64) + 2.0 * (res.S - Si)) * (1.0 + slack)
+        assert np.all(d2_true <= bound), f"step {t}"
+        sc.repair()
+        Si[res.candidates] = res.S
+
+
 def test_literal_algorithm_with_stale_certificates_misses_failures():
     """Read step by step with the clearance of possibly stale certificates, the
     filter of Algorithm 1 does miss failures; the appendix's clock does not."""
