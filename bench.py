@@ -22,6 +22,10 @@ Legs (--legs):
             against one context per scene; selector regret on fresh scenes;
   scaling   the step, repair and rebuild kernels from N = 2^16 to 2^26 with
             achieved bandwidth;
+  audit     the certificate-failure audit of Table 1 on the five families
+            (d = 2 and 3, three step scales, N = 16000): failure fraction,
+            misses of the safety rule and its over-flagging, and the local
+            predictor rho's recall and false flags;
 plus a certification pass (every timed step of the repair and rebuild legs
 audited by the GPU all-pairs oracle: zero missed failures and bitwise-equal
 fresh certificates), HBM traffic of the dominant kernel from committed
@@ -57,7 +61,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling")
+    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling,audit")
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--scaling-exps", default="16,18,20,22,24,26",
                     help="log2 N of the scaling leg's scenes")
@@ -351,6 +355,46 @@ def sweep_leg(args, nnc, synth, torch):
                                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                           "frac": rbytes / (rep50["repair_query_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
                                           "avg_launch_us": rep50["repair_query_us"], "bytes_per_launch": rbytes}}
+
+
+def audit_leg(args, nnc, synth, torch):
+    """Table 1's certificate-failure audit on the five families: N = 16000, d = 2 and 3,
+    eps in {5e-4, 2e-3, 8e-3}, 24 repaired steps each; every step checked by the
+    exact all-pairs oracle.  Per family, pooled: the mean fraction of certificates
+    that fail per step, the safety rule's misses (must be 0) and the fraction of
+    still-valid certificates it flags, and the local predictor rho_i > 1/2's recall
+    (flagged failures / failures) and false flags (flagged valid / valid)."""
+    n, steps = 16000, 24
+    table = {}
+    for fi, fam in enumerate(synth.FAMILIES):
+        acc = dict(steps=0, fail=0, valid=0, missed=0, cand_false=0, rho_hit=0, rho_false=0, frac=0.0)
+        for d in (2, 3):
+            for k, eps in enumerate((5e-4, 2e-3, 8e-3)):
+                tr = synth.make_trajectory(fam, n, d, steps, eps, (6000 + fi, d, k))
+                frames = [torch.from_numpy(f).cuda() for f in tr.frames]
+                ctx = nnc.NNCert(n, d)
+                ctx.init_certificates(frames[0])
+                for t in range(1, steps + 1):
+                    ctx.step(frames[t], eps)
+                    ctx.rho_predict()
+                    ctx.repair()
+                    a = ctx.oracle_verify()
+                    f = a["n_true_fail"]
+                    acc["steps"] += 1
+                    acc["fail"] += f
+                    acc["valid"] += n - f
+                    acc["frac"] += f / n
+                    acc["missed"] += a["n_missed"]
+                    acc["cand_false"] += a["n_false"]
+                    acc["rho_hit"] += a["rho_hit"]
+                    acc["rho_false"] += a["rho_flagged"] - a["rho_hit"]
+                ctx.close()
+        table[fam] = {"invalid": acc["frac"] / acc["steps"], "miss_safe": acc["missed"],
+                      "false_safe": acc["cand_false"] / max(acc["valid"], 1),
+                      "recall_rho": acc["rho_hit"] / max(acc["fail"], 1),
+                      "false_rho": acc["rho_false"] / max(acc["valid"], 1), "steps": acc["steps"]}
+        progress(f"audit {fam}: " + ", ".join(f"{k} {v:.3f}" for k, v in table[fam].items() if k != "steps"))
+    return {"n": n, "steps_per_run": steps, "eps": [5e-4, 2e-3, 8e-3], "d": [2, 3], "families": table}
 
 
 def scaling_leg(args, nnc, synth, torch):
@@ -684,6 +728,8 @@ def main():
         progress("sweep done")
     if "scaling" in legs_req:
         legs["scaling"] = scaling_leg(args, nnc, synth, torch)
+    if "audit" in legs_req:
+        legs["audit"] = audit_leg(args, nnc, synth, torch)
 
     # ---- batched scenes (512 scenes, log-uniform N, mixed d and families) ------------------
     if "batched" in legs_req:

@@ -126,6 +126,9 @@ typedef struct {
     int64_t n_false;          /* candidates that did not fail */
     int64_t n_value_mismatch; /* fresh certificates whose d1/d2 differ from brute force */
     uint64_t nn_hash;         /* 64-bit hash of nn[] (order-dependent, deterministic) */
+    int64_t rho_flagged;      /* points the local predictor flagged for the last step
+                                 (nnc_rho_predict), -1 if it was not evaluated */
+    int64_t rho_hit;          /* flagged points that failed, -1 likewise */
 } nnc_audit;
 
 typedef struct {
@@ -177,6 +180,17 @@ int nnc_rebuild(nnc_ctx *ctx);
  * the state: nn of every point, d1/d2 bitwise of points certified at the last
  * step.  Synchronises. */
 int nnc_oracle_verify(nnc_ctx *ctx, nnc_audit *out);
+
+/* The local failure predictor the paper reports beside the safety rule (Section 4,
+ * Table 1): rho_i = delta_i / c_i > 1/2, where c_i = d2 - d1 of point i's kept
+ * certificate and delta_i the last step's motion of i plus that of its kept nearest
+ * neighbour j (each the correctly rounded square root of the binary32 squared
+ * displacement, summed in binary32); i is flagged iff 2 delta_i > c_i (never when
+ * d2 = +inf or nn = -1).  Call after nnc_step and before nnc_repair or nnc_rebuild;
+ * the next nnc_oracle_verify reports how many points were flagged and how many of
+ * them failed.  An audit tool, not part of the maintenance step.  Asynchronous.
+ * NNC_E_STATE without a pending step. */
+int nnc_rho_predict(nnc_ctx *ctx);
 
 /* Normalised entropy (Definition 2) of the failed set or of the last step's
  * candidates, over the current cells.  Synchronises. */

@@ -285,6 +285,7 @@ class OracleScene:
         pos_new = _soa(pos_new)
         eps = max_step(self.pos, pos_new)
         self.cell = cells(pos_new, self.G, self.lo, self.hi)  # every cell current (Algorithm 1)
+        self.pos_prev = self.pos
         self.pos = pos_new.copy()
         self.S = float(np.float64(self.S) + np.float64(eps))
         self.last_eps = eps
@@ -297,6 +298,30 @@ class OracleScene:
             raise ValueError(self.rule)
         self.pending = StepResult(eps, self.S, cand.astype(np.int64))
         return self.pending
+
+    def rho_flags(self) -> np.ndarray:
+        """The local predictor the paper reports beside the safety rule (Section 4,
+        Table 1) for the pending step: rho_i = delta_i / c_i > 1/2, with c_i the kept
+        certificate's binary32 clearance and delta_i the step's motion of i plus that of
+        its kept nearest neighbour (the paper leaves delta_i undefined; this is the
+        reading), each motion sqrt of the binary32 squared displacement (the formula of
+        eps_t), summed in binary32; flagged iff 2 delta_i > c_i."""
+        if self.pending is None:
+            raise RuntimeError("rho without a pending step")
+        p0, p1 = self.pos_prev, self.pos
+        dx = p1[0] - p0[0]
+        s = dx * dx
+        for k in range(1, p0.shape[0]):
+            dk = p1[k] - p0[k]
+            s = s + dk * dk
+        move = np.sqrt(s)                      # binary32, correctly rounded
+        j = self.nn
+        ok = (j >= 0) & (j < self.n)
+        delta = move + move[np.where(ok, j, 0)]
+        c = clearance(self.d1, self.d2)
+        with np.errstate(invalid="ignore"):
+            flag = (np.float32(2.0) * delta) > c
+        return ok & flag
 
     def repair(self, frontier=None):
         if self.pending is None:

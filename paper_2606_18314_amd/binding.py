@@ -37,7 +37,7 @@ NNC_CANDIDATES = 1
 
 EXPORTS = (
     "nnc_create", "nnc_destroy", "nnc_init_certificates", "nnc_step", "nnc_repair", "nnc_rebuild",
-    "nnc_oracle_verify", "nnc_frontier_entropy", "nnc_get_state", "nnc_snapshot", "nnc_restore",
+    "nnc_oracle_verify", "nnc_rho_predict", "nnc_frontier_entropy", "nnc_get_state", "nnc_snapshot", "nnc_restore",
     "nnc_snap_free", "nnc_allpairs_top2", "nnc_strerror", "nnc_profile_enable", "nnc_profile_read",
     "nnc_batch_create", "nnc_batch_destroy", "nnc_batch_offsets", "nnc_batch_init", "nnc_batch_step",
     "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
@@ -79,7 +79,7 @@ class State(ctypes.Structure):
 class Audit(ctypes.Structure):
     _fields_ = [("n_checked", ctypes.c_int64), ("n_detect", ctypes.c_int64), ("n_true_fail", ctypes.c_int64),
                 ("n_missed", ctypes.c_int64), ("n_false", ctypes.c_int64), ("n_value_mismatch", ctypes.c_int64),
-                ("nn_hash", ctypes.c_uint64)]
+                ("nn_hash", ctypes.c_uint64), ("rho_flagged", ctypes.c_int64), ("rho_hit", ctypes.c_int64)]
 
 
 class Entropy(ctypes.Structure):
@@ -126,6 +126,7 @@ def load():
     lib.nnc_repair.argtypes = [P, ctypes.POINTER(Frontier)]
     lib.nnc_rebuild.argtypes = [P]
     lib.nnc_oracle_verify.argtypes = [P, ctypes.POINTER(Audit)]
+    lib.nnc_rho_predict.argtypes = [P]
     lib.nnc_frontier_entropy.argtypes = [P, ctypes.c_int, ctypes.POINTER(Entropy)]
     lib.nnc_get_state.argtypes = [P, ctypes.POINTER(State)]
     lib.nnc_snapshot.argtypes = [P, ctypes.POINTER(P)]
@@ -292,6 +293,10 @@ class NNCert:
         a = Audit()
         check(_lib.nnc_oracle_verify(self.h, ctypes.byref(a)), "nnc_oracle_verify")
         return {k: getattr(a, k) for k, _ in Audit._fields_}
+
+    def rho_predict(self) -> None:
+        """The local failure predictor (audit only), between step and repair/rebuild."""
+        check(_lib.nnc_rho_predict(self.h), "nnc_rho_predict")
 
     def frontier_entropy(self, which: int = NNC_FAILED) -> dict:
         e = Entropy()

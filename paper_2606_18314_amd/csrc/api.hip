@@ -71,6 +71,7 @@ size_t carve(nnc_ctx *c, char *base)
     c->a_nn = k.take<int32_t>(n);
     c->a_d1 = k.take<float>(n);
     c->a_d2 = k.take<float>(n);
+    c->rho = k.take<uint8_t>(n);
     if (c->flags & NNC_COPY_POSITIONS) {
         c->pos_copy[0] = k.take<float>(n * (size_t)c->d);
         c->pos_copy[1] = k.take<float>(n * (size_t)c->d);
@@ -261,6 +262,7 @@ int nnc_init_certificates(nnc_ctx *c, const float *pos)
     c->pos_prev = nullptr;
     c->t = 0;
     c->pending = 0;
+    c->rho_step = -1;
     // everything but the status words (whose epochs keep increasing) starts at zero
     if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
     int rc = nnc::launch_cells_init(c, c->pos_cur);
@@ -337,7 +339,10 @@ int nnc_oracle_verify(nnc_ctx *c, nnc_audit *out)
     if (!c->inited) return NNC_E_STATE;
     int rc = nnc::launch_allpairs(c->pos_cur, c->n, c->d, nullptr, c->n, c->a_nn, c->a_d1, c->a_d2, c->stream);
     if (rc != NNC_OK) return rc;
-    if (hipMemsetAsync(c->sc->audit, 0, sizeof(c->sc->audit), c->stream) != hipSuccess) return NNC_E_HIP;
+    // the rho counter ([6]) belongs to nnc_rho_predict
+    if (hipMemsetAsync(c->sc->audit, 0, 6 * sizeof(c->sc->audit[0]), c->stream) != hipSuccess ||
+        hipMemsetAsync(&c->sc->audit[7], 0, sizeof(c->sc->audit[7]), c->stream) != hipSuccess)
+        return NNC_E_HIP;
     rc = nnc::launch_audit(c);
     if (rc != NNC_OK) return rc;
     DevScalars h;
@@ -350,7 +355,20 @@ int nnc_oracle_verify(nnc_ctx *c, nnc_audit *out)
     out->n_false = (int64_t)h.nfront - (int64_t)h.audit[5];
     out->n_value_mismatch = (int64_t)h.audit[1];
     out->nn_hash = h.audit[4];
+    const bool rho = c->rho_step == c->t;
+    out->rho_flagged = rho ? (int64_t)h.audit[6] : -1;
+    out->rho_hit = rho ? (int64_t)h.audit[7] : -1;
     return take_error(c, h);
+}
+
+int nnc_rho_predict(nnc_ctx *c)
+{
+    if (!c) return NNC_E_INVAL;
+    if (!c->pending || !c->pos_prev) return NNC_E_STATE;
+    if (hipMemsetAsync(&c->sc->audit[6], 0, sizeof(c->sc->audit[6]), c->stream) != hipSuccess) return NNC_E_HIP;
+    const int rc = nnc::launch_rho(c);
+    if (rc == NNC_OK) c->rho_step = c->t;
+    return rc;
 }
 
 int nnc_frontier_entropy(nnc_ctx *c, int which, nnc_entropy *out)
@@ -454,6 +472,7 @@ int nnc_restore(nnc_ctx *c, const nnc_snap *s)
     c->pos_cur = s->pos_cur;
     c->pos_prev = s->pos_prev;
     c->steps_since_grid = s->steps_since_grid;
+    c->rho_step = -1;
     return NNC_OK;
 }
 

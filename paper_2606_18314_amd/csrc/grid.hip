@@ -799,10 +799,10 @@ __global__ void __launch_bounds__(kB) k_audit(int n, const int *__restrict__ nn,
                                               const float *__restrict__ d2, const int *__restrict__ stamp, int t,
                                               const uint8_t *__restrict__ fail, const int *__restrict__ a_nn,
                                               const float *__restrict__ a_d1, const float *__restrict__ a_d2,
-                                              DevScalars *sc)
+                                              const uint8_t *__restrict__ rho, DevScalars *sc)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
-    int missed = 0, vm = 0, tf = 0, fresh = 0;
+    int missed = 0, vm = 0, tf = 0, fresh = 0, hit = 0;
     unsigned long long h = 0;
     if (i < n) {
         missed = a_nn[i] != nn[i];
@@ -810,9 +810,11 @@ __global__ void __launch_bounds__(kB) k_audit(int n, const int *__restrict__ nn,
         vm = fresh && (__float_as_uint(a_d1[i]) != __float_as_uint(d1[i]) ||
                        __float_as_uint(a_d2[i]) != __float_as_uint(d2[i]));
         tf = fail[i] != 0;
+        hit = rho != nullptr && tf && rho[i] != 0;
         h = mix64(((unsigned long long)(unsigned)i << 32) | (unsigned)nn[i]);
     }
     missed = wave_sum(missed);
+    hit = wave_sum(hit);
     vm = wave_sum(vm);
     tf = wave_sum(tf);
     fresh = wave_sum(fresh);
@@ -824,7 +826,37 @@ __global__ void __launch_bounds__(kB) k_audit(int n, const int *__restrict__ nn,
         atomicAdd(&sc->audit[2], (unsigned long long)tf);
         atomicAdd(&sc->audit[3], (unsigned long long)fresh);
         atomicAdd(&sc->audit[4], h);
+        if (hit) atomicAdd(&sc->audit[7], (unsigned long long)hit);
     }
+}
+
+// The local failure predictor of the audit (Section 4, Table 1): point i is flagged
+// when twice its last-step motion plus its kept neighbour's exceeds the kept
+// certificate's clearance, 2 (|dp_i| + |dp_j|) > d2 - d1, all in binary32.
+template <int D>
+__global__ void __launch_bounds__(kB) k_rho(int n, const float *__restrict__ pold, const float *__restrict__ pnew,
+                                            const int *__restrict__ nn, const float *__restrict__ d1,
+                                            const float *__restrict__ d2, uint8_t *__restrict__ rho,
+                                            DevScalars *sc)
+{
+    const int i = blockIdx.x * kB + threadIdx.x;
+    int f = 0;
+    if (i < n) {
+        const int j = nn[i];
+        if (j >= 0 && j < n) {
+            const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
+            const float si = sqdist<D>(pold[i], pold[n1 + i], D == 3 ? pold[n2 + i] : 0.0f, pnew[i], pnew[n1 + i],
+                                       D == 3 ? pnew[n2 + i] : 0.0f);
+            const float sj = sqdist<D>(pold[j], pold[n1 + j], D == 3 ? pold[n2 + j] : 0.0f, pnew[j], pnew[n1 + j],
+                                       D == 3 ? pnew[n2 + j] : 0.0f);
+            const float delta = sqrtf(si) + sqrtf(sj);
+            const float c = d2[i] - d1[i];
+            f = 2.0f * delta > c ? 1 : 0;
+        }
+        rho[i] = (uint8_t)f;
+    }
+    f = wave_sum(f);
+    if (lane_id() == 0 && f) atomicAdd(&sc->audit[6], (unsigned long long)f);
 }
 
 // Failures among the candidates (for the false-repair count).
@@ -1106,9 +1138,23 @@ int launch_audit(nnc_ctx *c)
     if (c->n == 0) return NNC_OK;
     const int blocks = blocks_for(c->n, kB);
     hipLaunchKernelGGL(k_audit, dim3(blocks), dim3(kB), 0, c->stream, (int)c->n, c->nn, c->d1, c->d2, c->stamp,
-                       (int)c->t, c->fail, c->a_nn, c->a_d1, c->a_d2, c->sc);
+                       (int)c->t, c->fail, c->a_nn, c->a_d1, c->a_d2,
+                       (const uint8_t *)(c->rho_step == c->t ? c->rho : nullptr), c->sc);
     hipLaunchKernelGGL(k_audit_cand, dim3(blocks < 4096 ? blocks : 4096), dim3(kB), 0, c->stream, c->frontier,
                        c->fail, c->sc);
+    return check();
+}
+
+int launch_rho(nnc_ctx *c)
+{
+    if (c->n == 0) return NNC_OK;
+    const int blocks = blocks_for(c->n, kB);
+    if (c->d == 2)
+        hipLaunchKernelGGL(k_rho<2>, dim3(blocks), dim3(kB), 0, c->stream, (int)c->n, c->pos_prev, c->pos_cur, c->nn,
+                           c->d1, c->d2, c->rho, c->sc);
+    else
+        hipLaunchKernelGGL(k_rho<3>, dim3(blocks), dim3(kB), 0, c->stream, (int)c->n, c->pos_prev, c->pos_cur, c->nn,
+                           c->d1, c->d2, c->rho, c->sc);
     return check();
 }
 

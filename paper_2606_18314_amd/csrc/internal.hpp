@@ -36,7 +36,9 @@ struct DevScalars {
     int F[2];
     int Cres[2];
     // audit counters
-    unsigned long long audit[6];
+    // [0] missed, [1] value mismatches, [2] failures, [3] fresh, [4] nn hash,
+    // [5] candidates that failed, [6] rho-flagged points, [7] flagged that failed
+    unsigned long long audit[8];
     // ingest results spread over kSpread words (workgroup b adds into slot b % kSpread),
     // folded by the filter's leading wave: displacement maxima per parity, and
     // changes of the occupied-cell count
@@ -115,6 +117,8 @@ struct nnc_ctx {
     // audit scratch
     int32_t *a_nn;
     float *a_d1, *a_d2;
+    uint8_t *rho;                 // local predictor flags of the step rho_step (-1: none)
+    int64_t rho_step;
     // one arena holds every buffer above
     void *arena;
     size_t arena_bytes;
@@ -154,6 +158,7 @@ int launch_query_all(nnc_ctx *c, int init);
 int launch_entropy(nnc_ctx *c, int which);
 int launch_cand_hist(nnc_ctx *c);
 int launch_audit(nnc_ctx *c);
+int launch_rho(nnc_ctx *c);
 int launch_features(nnc_ctx *c, float *out);
 int launch_fill(void *p, int value, size_t count, hipStream_t s);
 

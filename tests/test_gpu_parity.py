@@ -327,6 +327,40 @@ def test_cutoff_with_mixed_density_and_large_steps(nnc, d, lanes):
     run_parity(nnc, tr, G=90 if d == 3 else 300, lanes=lanes, strategy="alternate")
 
 
+@pytest.mark.parametrize("family", ["uniform_brownian", "adversarial_crossing", "shear_band"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_rho_predictor_audit_counts(nnc, family, d):
+    """The local predictor (nnc_rho_predict) against the oracle's rho_flags, step by
+    step: the flagged count and the flagged-and-failed count reported by
+    nnc_oracle_verify are the oracle's exactly; without a prediction for the step
+    both read -1."""
+    tr = synth.make_trajectory(family, 3000, d, 8, 2e-3, 700 + d)
+    frames = [dev(f) for f in tr.frames]
+    G = 12 if d == 3 else 40
+    ctx = nnc.NNCert(tr.n, d, grid_g=G)
+    sc = model.OracleScene(d=d, n=tr.n, G=G)
+    ctx.init_certificates(frames[0])
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, tr.steps + 1):
+        ctx.step(frames[t], tr.eps)
+        sc.step(tr.frames[t])
+        predict = t % 3 != 0
+        if predict:
+            ctx.rho_predict()
+            flags = sc.rho_flags()
+        ctx.repair()
+        sc.repair()
+        a = ctx.oracle_verify()
+        assert a["n_missed"] == 0
+        assert a["n_true_fail"] == int(sc.fail.sum())
+        if predict:
+            assert a["rho_flagged"] == int(flags.sum()), f"step {t}"
+            assert a["rho_hit"] == int((flags & sc.fail).sum()), f"step {t}"
+        else:
+            assert a["rho_flagged"] == -1 and a["rho_hit"] == -1
+    ctx.close()
+
+
 def test_points_outside_the_box_and_one_cell(nnc):
     g = np.random.default_rng(2)
     n = 600

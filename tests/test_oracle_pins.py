@@ -350,6 +350,40 @@ def test_previous_certificate_bounds_the_new_second_distance(family, d):
         Si[res.candidates] = res.S
 
 
+def test_rho_predictor_on_exact_dyadic_scenes():
+    """The local predictor rho_i = delta_i / c_i > 1/2 on three collinear points whose
+    distances, clearances and motions are dyadic (exact in binary32): p0 = 0,
+    p1 = 1/4, p2 = 1 give nn = (1, 0, 1) and c = (3/4, 1/2, 1/4).  The flags are worked
+    out by hand, including the strict boundary 2 delta = c (not flagged), a point
+    whose own motion is zero but whose neighbour's is not, and N = 2 (d2 = +inf) and
+    N = 1 (no neighbour), which are never flagged."""
+    def run(p_old, p_new):
+        sc = model.OracleScene(d=2, n=p_old.shape[1], G=4)
+        sc.init_certificates(np.asarray(p_old, np.float32))
+        sc.step(np.asarray(p_new, np.float32))
+        return sc.rho_flags()
+    p = np.array([[0.0, 0.25, 1.0], [0.0, 0.0, 0.0]])
+    # p0 moves 1/8: delta = (1/8, 1/8, 0) + neighbour motion -> 2 delta = (1/4, 1/4, 0)
+    q = p.copy(); q[0, 0] += 0.125
+    assert run(p, q).tolist() == [False, False, False]
+    # p2 moves 1/8 in y: 2 delta_2 = 1/4 = c_2 exactly -> not flagged (strict)
+    q = p.copy(); q[1, 2] += 0.125
+    assert run(p, q).tolist() == [False, False, False]
+    # p2 moves 1/4: 2 delta_2 = 1/2 > 1/4 -> flagged; p0, p1 unmoved and their
+    # neighbours (p1, p0) unmoved -> not flagged
+    q = p.copy(); q[1, 2] += 0.25
+    assert run(p, q).tolist() == [False, False, True]
+    # p0 moves 3/16: 2 delta_0 = 3/8 < 3/4; p1's neighbour p0 moved: 2 delta_1 = 3/8 <
+    # 1/2; p2's neighbour p1 unmoved -> none; then 5/16: 2 delta_1 = 5/8 > 1/2 -> p1 only
+    q = p.copy(); q[0, 0] -= 0.1875
+    assert run(p, q).tolist() == [False, False, False]
+    q = p.copy(); q[0, 0] -= 0.3125
+    assert run(p, q).tolist() == [False, True, False]
+    # N = 2: d2 = +inf, c = +inf; N = 1: nn = -1
+    assert run(np.array([[0.0, 0.5], [0.0, 0.0]]), np.array([[0.4, 0.1], [0.0, 0.0]])).tolist() == [False, False]
+    assert run(np.array([[0.5], [0.5]]), np.array([[0.0], [0.0]])).tolist() == [False]
+
+
 def test_literal_algorithm_with_stale_certificates_misses_failures():
     """Read step by step with the clearance of possibly stale certificates, the
     filter of Algorithm 1 does miss failures; the appendix's clock does not."""
