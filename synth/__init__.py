@@ -28,6 +28,28 @@ these definitions:
   direction.
 * ``shear_band``: start uniform; each step moves a point by ((y - 0.5) * eps) along x.
 
+The other five families of the paper's list (``EXTRA_FAMILIES``, used by the
+failure audit) are read as follows; in d = 3 the planar ones keep a static
+z = 0.5 + N(0, 1e-3^2) layer:
+
+* ``vortex``: start uniform in the disc of radius 0.45 about the centre; each step
+  rotates a point about the centre with linear speed eps * exp(-r / 0.15) (a fast
+  core, a slow rim: differential rotation), so no point moves more than eps.
+* ``filament``: points on the closed three-lobed curve r(theta) = 0.3 + 0.08 sin(3
+  theta) about the centre, each with a fixed radial offset N(0, 2e-3^2); each step
+  advances theta by eps / (2 * 0.46) for every point (flow along the curve; 0.46
+  bounds the curve's speed |dp/dtheta|, so a step moves at most eps / 2).
+* ``split_merge``: one Gaussian cluster (sigma 0.05) at the centre; the points of
+  one half move by eps per step along a fixed random unit direction u, the other
+  half along -u, for the first half of the trajectory, then both halves return.
+* ``grid_jitter``: the first n points of a regular lattice with ceil(n^(1/d))
+  points per axis (cell-centred), in random order; each step adds Brownian jitter
+  clipped to eps (a near-lattice scene: many near-equal distances).
+* ``spiral``: an Archimedean spiral r = 0.05 + 0.4 * theta / (6 pi) over three
+  turns with Gaussian thickness 1e-3, rotated rigidly about the centre by the
+  angle that moves radius 0.46 by eps / 2 per step, plus Brownian jitter clipped
+  to eps / 2, the step clipped to eps (jitter lets points drift past 0.46).
+
 Point indices are a random permutation of the generation order, so an index
 carries no spatial information in any family.
 """
@@ -44,6 +66,14 @@ FAMILIES = (
     "adversarial_crossing",
     "clustered_drift",
     "shear_band",
+)
+
+EXTRA_FAMILIES = (
+    "vortex",
+    "filament",
+    "split_merge",
+    "grid_jitter",
+    "spiral",
 )
 
 
@@ -80,6 +110,15 @@ class Trajectory:
         return self.frames.shape[0] - 1
 
 
+def _planar(g: np.random.Generator, d: int, n: int, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    p = np.empty((d, n))
+    p[0] = x
+    p[1] = y
+    if d == 3:
+        p[2] = 0.5 + 1e-3 * g.standard_normal(n)
+    return p
+
+
 def initial_positions(family: str, n: int, d: int, g: np.random.Generator):
     """Frame-0 positions (float64 [d, n]) and per-family motion parameters."""
     if d not in (2, 3):
@@ -113,11 +152,39 @@ def initial_positions(family: str, n: int, d: int, g: np.random.Generator):
         u /= np.sqrt(np.sum(u * u, axis=0))
         params["label"] = label
         params["direction"] = u
+    elif family == "vortex":
+        r = 0.45 * np.sqrt(g.random(n))
+        theta = g.random(n) * (2.0 * math.pi)
+        p = _planar(g, d, n, 0.5 + r * np.cos(theta), 0.5 + r * np.sin(theta))
+    elif family == "filament":
+        theta = g.random(n) * (2.0 * math.pi)
+        params["offset"] = 2e-3 * g.standard_normal(n)
+        params["theta"] = theta
+        r = 0.3 + 0.08 * np.sin(3.0 * theta) + params["offset"]
+        p = _planar(g, d, n, 0.5 + r * np.cos(theta), 0.5 + r * np.sin(theta))
+    elif family == "split_merge":
+        p = 0.5 + 0.05 * g.standard_normal((d, n))
+        u = g.standard_normal(d)
+        params["direction"] = u / math.sqrt(float(np.sum(u * u)))
+        params["side"] = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    elif family == "grid_jitter":
+        m = int(math.ceil(n ** (1.0 / d) - 1e-9))
+        while m ** d < n:
+            m += 1
+        idx = np.arange(n)
+        p = np.empty((d, n))
+        for k in range(d):
+            p[k] = ((idx // (m ** k)) % m + 0.5) / m
+    elif family == "spiral":
+        s = g.random(n)
+        theta = s * (6.0 * math.pi)
+        r = 0.05 + 0.4 * s + 1e-3 * g.standard_normal(n)
+        p = _planar(g, d, n, 0.5 + r * np.cos(theta), 0.5 + r * np.sin(theta))
     else:
         raise ValueError(f"unknown family {family!r}")
     perm = g.permutation(n)
     p = p[:, perm]
-    for key in ("side", "label"):
+    for key in ("side", "label", "offset", "theta"):
         if key in params:
             params[key] = params[key][perm]
     return p, params
@@ -152,6 +219,39 @@ def make_trajectory(family: str, n: int, d: int, steps: int, eps: float, seed) -
         elif family == "shear_band":
             nxt = cur.copy()
             nxt[0] += (cur[1] - 0.5) * eps
+        elif family == "vortex":
+            x = cur[0] - centre
+            y = cur[1] - centre
+            r = np.sqrt(x * x + y * y)
+            ang = eps * np.exp(-r / 0.15) / np.maximum(r, 1e-9)
+            ang = np.minimum(ang, 1.0)  # the chord 2 r sin(a/2) stays below r a <= eps
+            ca, sa = np.cos(ang), np.sin(ang)
+            nxt = cur.copy()
+            nxt[0] = centre + (ca * x - sa * y)
+            nxt[1] = centre + (sa * x + ca * y)
+        elif family == "filament":
+            params["theta"] = params["theta"] + eps / (2.0 * 0.46)
+            th = params["theta"]
+            r = 0.3 + 0.08 * np.sin(3.0 * th) + params["offset"]
+            nxt = cur.copy()
+            nxt[0] = centre + r * np.cos(th)
+            nxt[1] = centre + r * np.sin(th)
+        elif family == "split_merge":
+            sign = 1.0 if t < steps // 2 else -1.0
+            nxt = cur + (sign * eps) * params["direction"][:, None] * params["side"][None, :]
+        elif family == "grid_jitter":
+            nxt = cur + _brownian(g, d, n, eps)
+        elif family == "spiral":
+            x = cur[0] - centre
+            y = cur[1] - centre
+            a = (0.5 * eps) / 0.46
+            ca, sa = math.cos(a), math.sin(a)
+            rot = np.zeros_like(cur)
+            rot[0] = (ca * x - sa * y) - x
+            rot[1] = (sa * x + ca * y) - y
+            # jitter accumulates, so a point may drift past radius 0.46: the whole
+            # step is clipped to eps
+            nxt = cur + _clip_norm(rot + _brownian(g, d, n, 0.5 * eps), eps)
         else:  # pragma: no cover - rejected by initial_positions
             raise ValueError(family)
         frames[t + 1] = _f32(nxt)

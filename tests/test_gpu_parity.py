@@ -156,6 +156,15 @@ def test_cube_16k_families_reduced(nnc, family):
     run_parity(nnc, tr, G=9, strategy="alternate")
 
 
+@pytest.mark.parametrize("family", synth.EXTRA_FAMILIES)
+@pytest.mark.parametrize("d", [2, 3])
+def test_extra_families_reduced(nnc, family, d):
+    """The other five families of the paper's list (vortex, filament, split/merge,
+    grid jitter, spiral) through repairs and rebuilds, every step against the oracle."""
+    tr = synth.make_trajectory(family, 4000, d, 24, 2e-3, 2100 + synth.EXTRA_FAMILIES.index(family))
+    run_parity(nnc, tr, G=9 if d == 3 else 32, strategy="alternate")
+
+
 @pytest.mark.parametrize("lanes", [1, 16, 32, 64])
 @pytest.mark.parametrize("d", [2, 3])
 def test_lanes_per_query_and_fine_grids(nnc, lanes, d):

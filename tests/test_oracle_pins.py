@@ -318,6 +318,35 @@ def test_cube_16k_families_no_miss_reduced(family):
         assert sc.audit().size == 0
 
 
+@pytest.mark.parametrize("family", synth.FAMILIES + synth.EXTRA_FAMILIES)
+@pytest.mark.parametrize("d", [2, 3])
+def test_family_steps_stay_within_eps(family, d):
+    """Every family's binary32 frames move no point farther than eps per step (to
+    the binary32 rounding of the coordinates), so eps is a valid declared bound."""
+    eps = 2e-3
+    tr = synth.make_trajectory(family, 2000, d, 20, eps, 31 + d)
+    fr = tr.frames.astype(np.float64)
+    step = np.sqrt(((fr[1:] - fr[:-1]) ** 2).sum(axis=1)).max()
+    assert step <= eps * (1.0 + 2.0 ** -20) + 2.0 ** -23
+
+
+@pytest.mark.parametrize("family", synth.EXTRA_FAMILIES)
+@pytest.mark.parametrize("d", [2, 3])
+def test_extra_families_no_miss_reduced(family, d):
+    """The other five families of the paper's list: no missed failure on every step,
+    repairs with a rebuild every fifth step."""
+    tr = synth.make_trajectory(family, 2500, d, 25, 2e-3, 2100 + synth.EXTRA_FAMILIES.index(family))
+    sc = model.OracleScene(d=d, n=2500, G=9 if d == 3 else 30)
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, tr.steps + 1):
+        sc.step(tr.frames[t])
+        if t % 5 == 0:
+            sc.rebuild()
+        else:
+            sc.repair()
+        assert sc.audit().size == 0
+
+
 @pytest.mark.parametrize("family", ["uniform_brownian", "adversarial_crossing", "clustered_drift"])
 @pytest.mark.parametrize("d", [2, 3])
 def test_previous_certificate_bounds_the_new_second_distance(family, d):
