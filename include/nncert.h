@@ -116,6 +116,8 @@ typedef struct {
     const uint8_t *fail;  /* device [n], 1 if nn changed at the last repair/rebuild */
     int64_t n;
     int32_t d, grid_g;
+    const uint8_t *rho;   /* device [n], flags of the local predictor (nnc_rho_predict) of
+                             the last step; meaningful only after that call, NULL in a batch */
 } nnc_state;
 
 typedef struct {
@@ -221,6 +223,13 @@ void nnc_snap_free(nnc_snap *snap);
 int nnc_allpairs_top2(const float *pos, int64_t n, int32_t d, const int32_t *qidx, int64_t nq,
                       int32_t *nn, float *d1, float *d2, void *stream);
 
+/* Square root of every element of x (device float32 [n]) into out (device float32
+ * [n]), by the routine that computes d1 = sqrt(s1), d2 = sqrt(s2) (Definition 1)
+ * and eps_t in every kernel; the certificates are bit-exact only if it is
+ * correctly rounded, which this call lets a test check over all binary32 inputs.
+ * stream: hipStream_t or NULL.  Asynchronous.  NNC_E_INVAL for n < 0 or NULL arrays. */
+int nnc_sqrt_f32(const float *x, float *out, int64_t n, void *stream);
+
 /* ---- kernel timing ------------------------------------------------------ */
 /* Kernel classes timed by the profiler. */
 #define NNC_K_INGEST  0   /* displacement, eps_t, cell update */
@@ -273,12 +282,14 @@ typedef struct {
     double guard;            /* as in nnc_config */
     double refresh;          /* as in nnc_config */
     void *stream;            /* hipStream_t */
-    uint32_t flags;          /* NNC_BATCH_FEATURES */
+    uint32_t flags;          /* NNC_BATCH_FEATURES | NNC_BATCH_EAGER */
 } nnc_batch_config;
 
 /* Compute the candidate histogram, H of the candidates and the selector features
  * at every step (otherwise only under NNC_POLICY_LEARNED). */
 #define NNC_BATCH_FEATURES 1u
+/* Launch the step's kernels one by one instead of through the library's graph. */
+#define NNC_BATCH_EAGER    2u
 
 typedef struct {
     double  eps;             /* eps_t of the last step */
@@ -309,12 +320,22 @@ int nnc_batch_offsets(const nnc_batch *b, int64_t *point_off, int64_t *coord_off
  * borrowed like nnc_init_certificates).  Asynchronous. */
 int nnc_batch_init(nnc_batch *b, const float *pos);
 
-/* One maintenance step of every scene: measure eps_t, advance the clock, update
- * the cells, filter and compact, compute the features, choose the strategy by
- * policy, rebuild or refresh grids where needed, run every scene's queries in
- * one launch, and reduce the failure entropy.  pos_new is borrowed.
- * Asynchronous; safe to capture in a HIP graph (no allocation, no memset, no
- * synchronisation). */
+/* One maintenance step of every scene (Algorithm 1 per scene, with the clock of
+ * the appendix): measure eps_t, advance the clock, update the cells, filter and
+ * compact, compute the features, choose the strategy by policy, rebuild or
+ * refresh grids where needed, run every scene's queries in one launch, and
+ * reduce the failure entropy (Definition 2).  pos_new (device, concatenated) is
+ * read during the step only: the previous coordinates are kept by the library.
+ * Asynchronous.  The step's five kernels are captured into a HIP graph on the
+ * first call and the graph is replayed while pos_new, policy and tau repeat
+ * (write each new frame into the same buffer); another pointer, policy or tau
+ * re-captures the graph (a host cost of tens of microseconds).  Under a caller's
+ * own stream capture, on the null stream, or with NNC_BATCH_EAGER the kernels are
+ * launched directly.  The step counter, the clocks and the previous coordinates
+ * live in device memory, so a caller may also capture one call and replay it for
+ * successive steps: each replay advances every scene by one step, reading the
+ * positions from the captured pos_new buffer.  No allocation, memset or
+ * synchronisation happens inside a step. */
 int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau);
 
 /* Load the selector's parameters (device float32 [NNC_SELECTOR_PARAMS]); copied. */

@@ -133,6 +133,8 @@ def nn_f64(pos: np.ndarray, queries=None):
 
 
 def pair_sqdist64(pos, a, b):
+    """Binary64 squared distance of the listed pairs (a[k], b[k]) of binary32 points
+    (the distance of the tie audit: exact up to binary64 rounding)."""
     pos = _soa(pos)
     d, n = pos.shape
     a = np.ascontiguousarray(a, np.int64)
@@ -287,6 +289,7 @@ class OracleScene:
         self.cell = cells(pos_new, self.G, self.lo, self.hi)  # every cell current (Algorithm 1)
         self.pos_prev = self.pos
         self.pos = pos_new.copy()
+        self.S_prev = self.S
         self.S = float(np.float64(self.S) + np.float64(eps))
         self.last_eps = eps
         if self.rule == "clock":
@@ -322,6 +325,37 @@ class OracleScene:
         with np.errstate(invalid="ignore"):
             flag = (np.float32(2.0) * delta) > c
         return ok & flag
+
+    def features(self) -> np.ndarray:
+        """The six repair-strategy selector inputs of the pending step, as the library
+        defines them (Section 3 labels a transition by its fastest strategy; the
+        selector predicts that label from these descriptors of the candidate set):
+        |F|/N; H of the candidates (Definition 2); ln N; d; m_cand / G^d, the fraction
+        of all cells the candidates meet; and eps_t over the median remaining motion
+        budget r_i = e_i - S_{t-1} of the certificates with 0 < r_i < inf, the median
+        read from a 64-bin histogram of r by binary exponent (bin = ilogb(r) + 48,
+        clamped to [0, 63]; the first bin whose running count reaches half of all,
+        represented by 1.5 * 2^(bin - 48)); 0 when no certificate has a finite budget.
+        Returned in binary64; the library rounds each to binary32."""
+        if self.pending is None:
+            raise RuntimeError("features without a pending step")
+        n = self.n
+        cand = self.pending.candidates
+        H, m, C, F = self.frontier_entropy(CANDIDATES, cand)
+        r = self.e - self.S_prev
+        r = r[(r > 0) & np.isfinite(r)]
+        h = np.zeros(64, np.int64)
+        if r.size:
+            ex = np.frexp(r)[1] - 1          # ilogb of a positive finite binary64
+            np.add.at(h, np.clip(ex + 48, 0, 63), 1)
+        V = int(h.sum())
+        radius = 0.0
+        if V:
+            b = int(np.argmax(2 * np.cumsum(h) >= V))
+            radius = 1.5 * 2.0 ** (b - 48)
+        return np.array([F / n if n else 0.0, H, math.log(n) if n else 0.0, self.d,
+                         m / float(self.G) ** self.d,
+                         float(self.pending.eps) / radius if radius > 0 else 0.0])
 
     def repair(self, frontier=None):
         if self.pending is None:

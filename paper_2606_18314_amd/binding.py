@@ -42,6 +42,7 @@ EXPORTS = (
     "nnc_batch_create", "nnc_batch_destroy", "nnc_batch_offsets", "nnc_batch_init", "nnc_batch_step",
     "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
     "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
+    "nnc_sqrt_f32",
 )
 
 POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
@@ -73,7 +74,8 @@ class Frontier(ctypes.Structure):
 class State(ctypes.Structure):
     _fields_ = [("nn", ctypes.c_void_p), ("d1", ctypes.c_void_p), ("d2", ctypes.c_void_p),
                 ("e", ctypes.c_void_p), ("cell", ctypes.c_void_p), ("fail", ctypes.c_void_p),
-                ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("grid_g", ctypes.c_int32)]
+                ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("grid_g", ctypes.c_int32),
+                ("rho", ctypes.c_void_p)]
 
 
 class Audit(ctypes.Structure):
@@ -153,6 +155,7 @@ def load():
     lib.nnc_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, P]
     lib.nnc_mlp_forward.argtypes = [P, P, ctypes.c_int, P, P]
+    lib.nnc_sqrt_f32.argtypes = [P, P, ctypes.c_int64, P]
     lib.nnc_strerror.argtypes = [ctypes.c_int]
     lib.nnc_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -200,6 +203,16 @@ def copy_from_device(dst: torch.Tensor, src_ptr: int, nbytes: int, stream: int |
     return dst
 
 
+def copy_to_device(dst_ptr: int, src: torch.Tensor, stream: int | None = None) -> None:
+    """Copy a contiguous CUDA tensor into library-owned device memory at dst_ptr, ordered on ``stream``."""
+    nbytes = src.numel() * src.element_size()
+    if nbytes:
+        s = _stream() if stream is None else stream
+        rc = hip().hipMemcpyAsync(dst_ptr, _ptr(src), nbytes, 3, s)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
 def allpairs_top2(pos: torch.Tensor, qidx: torch.Tensor | None = None):
     """Exact all-pairs top-2 of float32 [d, n] positions: (nn, d1, d2) CUDA tensors."""
     d, n = pos.shape
@@ -211,6 +224,13 @@ def allpairs_top2(pos: torch.Tensor, qidx: torch.Tensor | None = None):
     check(load().nnc_allpairs_top2(_ptr(pos), n, d, _ptr(qidx), nq, _ptr(nn), _ptr(d1), _ptr(d2), _stream()),
           "nnc_allpairs_top2")
     return nn, d1, d2
+
+
+def sqrt_f32(x: torch.Tensor) -> torch.Tensor:
+    """Elementwise square root of a float32 CUDA tensor by the certificates' routine."""
+    out = torch.empty_like(x)
+    check(load().nnc_sqrt_f32(_ptr(x), _ptr(out), x.numel(), _stream()), "nnc_sqrt_f32")
+    return out
 
 
 class Snapshot:
@@ -326,6 +346,19 @@ class NNCert:
         torch.cuda.synchronize()
         return out
 
+    def rho_flags(self) -> torch.Tensor:
+        """Per-point flags of the last nnc_rho_predict (CUDA uint8 tensor)."""
+        t = torch.empty(self.n, dtype=torch.uint8, device="cuda")
+        copy_from_device(t, self._state.rho, self.n, self.stream)
+        torch.cuda.synchronize()
+        return t
+
+    def state_pointers(self) -> dict:
+        """Raw device addresses of the state arrays (nnc_get_state)."""
+        st = State()
+        check(_lib.nnc_get_state(self.h, ctypes.byref(st)), "nnc_get_state")
+        return {k: getattr(st, k) for k, _ in State._fields_}
+
     def features(self) -> torch.Tensor:
         """The six selector features of the pending step (CUDA float32 tensor)."""
         out = torch.empty(NFEATURES, dtype=torch.float32, device="cuda")
@@ -361,7 +394,8 @@ class NNCBatch:
     [d_s, n_s] block starting at ``coord_off[s]``."""
 
     def __init__(self, ns, ds, grids=None, lanes: int = 0, guard: float = -1.0, refresh: float = 0.0,
-                 stream: int | None = None, features: bool = False):
+                 stream: int | None = None, features: bool = False, eager: bool = False):
+        """eager: launch each step's kernels directly instead of through the library's graph."""
         import numpy as np
         lib = load()
         self.S = len(ns)
@@ -372,7 +406,7 @@ class NNCBatch:
         cfg = BatchConfig(scenes=self.S, n=self._n.ctypes.data, d=self._d.ctypes.data,
                           grid_g=0 if self._g is None else self._g.ctypes.data, lanes=int(lanes),
                           guard=float(guard), refresh=float(refresh), stream=self.stream,
-                          flags=1 if features else 0)
+                          flags=(1 if features else 0) | (2 if eager else 0))
         h = ctypes.c_void_p()
         check(lib.nnc_batch_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_batch_create")
         self.h = h.value

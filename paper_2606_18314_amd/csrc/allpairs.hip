@@ -81,8 +81,8 @@ __global__ void __launch_bounds__(64 * S) k_allpairs(const float *__restrict__ p
     if constexpr (S == 1) {
         if (active) {
             nn_out[q] = nn;
-            d1_out[q] = sqrtf(s1);
-            d2_out[q] = sqrtf(s2);
+            d1_out[q] = cert_sqrt(s1);
+            d2_out[q] = cert_sqrt(s2);
         }
     } else {
         s_s1[w][lane] = s1;
@@ -97,8 +97,8 @@ __global__ void __launch_bounds__(64 * S) k_allpairs(const float *__restrict__ p
 #pragma unroll
             for (int k = 1; k < S; ++k) t.merge(s_s1[k][lane], s_s2[k][lane], s_nn[k][lane]);
             nn_out[q] = t.nn;
-            d1_out[q] = sqrtf(t.s1);
-            d2_out[q] = sqrtf(t.s2);
+            d1_out[q] = cert_sqrt(t.s1);
+            d2_out[q] = cert_sqrt(t.s2);
         }
     }
 }
@@ -134,7 +134,22 @@ int launch_d(const float *pos, int n, const int32_t *qidx, int nq, int32_t *nn, 
     return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP;
 }
 
+__global__ void __launch_bounds__(256) k_sqrt(const float *__restrict__ x, float *__restrict__ out, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = cert_sqrt(x[i]);
+}
+
 }  // namespace
+
+int launch_sqrt(const float *x, float *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return NNC_OK;
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_sqrt, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, x, out,
+                       (long long)n);
+    return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP;
+}
 
 int launch_allpairs(const float *pos, int64_t n, int d, const int32_t *qidx, int64_t nq, int32_t *nn, float *d1,
                     float *d2, hipStream_t s)

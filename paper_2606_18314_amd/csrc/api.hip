@@ -415,6 +415,7 @@ int nnc_get_state(nnc_ctx *c, nnc_state *v)
     v->n = c->n;
     v->d = c->d;
     v->grid_g = c->G;
+    v->rho = c->rho;
     return NNC_OK;
 }
 
@@ -522,6 +523,12 @@ int nnc_allpairs_top2(const float *pos, int64_t n, int32_t d, const int32_t *qid
     if (!qidx && nq != n) return NNC_E_INVAL;
     if (nq > 0 && (!pos || !nn || !d1 || !d2)) return NNC_E_INVAL;
     return nnc::launch_allpairs(pos, n, d, qidx, nq, nn, d1, d2, (hipStream_t)stream);
+}
+
+int nnc_sqrt_f32(const float *x, float *out, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !out))) return NNC_E_INVAL;
+    return nnc::launch_sqrt(x, out, n, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -44,14 +44,20 @@ struct SceneDesc {
     double refresh_w;
 };
 
+// Launch arguments of the step kernels.  Everything that changes from one step
+// to the next lives in device memory (the step counter, the clocks, the previous
+// coordinates in the slot records, whether selector parameters are loaded), so a
+// captured step replays as a fresh call would run: only the position buffer, the
+// policy and tau are fixed by the launch.
 struct BatchArgs {
     const SceneDesc *desc;
-    int scenes, parity, t, policy;
+    int scenes, init, policy;
     float tau;
-    int have_params, features_on;
+    int features_on;
     double guard, K;
     DevScalars *sc;
-    const float *pos_prev, *pos_cur;
+    int *tdev;                // [0] completed steps, [1] selector parameters loaded
+    const float *pos_cur;
     float4 *slots;  // slot records {x, y, z, point index}, indexed by poff + slot
     int *cell, *counts, *rank, *cell_start, *cursor;
     int *nn, *stamp, *frontier, *hist_fail, *touched_fail, *hist_cand, *touched_cand;
@@ -65,6 +71,10 @@ struct BatchArgs {
 };
 
 namespace {
+
+// Step number t of the running launch (0 during initialisation); step t reads the
+// clock of parity (t - 1) & 1 and writes that of parity t & 1.
+__device__ __forceinline__ int step_number(const BatchArgs &a) { return a.init ? 0 : a.tdev[0] + 1; }
 
 __global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
 {
@@ -93,15 +103,19 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
     const int s = a.tile_scene[blockIdx.x];
     const SceneDesc sd = a.desc[s];
     const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x;
+    const int parity = step_number(a) & 1;
     float sq = 0.0f;
     int dC = 0;
     if (i < sd.n) {
-        const float *po = a.pos_prev + sd.coff, *pn = a.pos_cur + sd.coff;
+        // the slot record holds the point's coordinates of the previous step
+        const float *pn = a.pos_cur + sd.coff;
         const size_t n1 = (size_t)sd.n, n2 = 2 * (size_t)sd.n;
         const bool d3 = sd.d == 3;
-        const float x0 = po[i], y0 = po[n1 + i], z0 = d3 ? po[n2 + i] : 0.f;
+        float4 *rec = a.slots + sd.poff + a.rank[sd.poff + i];
+        const float4 old4 = *rec;
+        const float x0 = old4.x, y0 = old4.y, z0 = old4.z;
         const float x1 = pn[i], y1 = pn[n1 + i], z1 = d3 ? pn[n2 + i] : 0.f;
-        a.slots[sd.poff + a.rank[sd.poff + i]] = make_float4(x1, y1, z1, __int_as_float(i));
+        *rec = make_float4(x1, y1, z1, __int_as_float(i));
         const bool ok = d3 ? all_finite<3>(x1, y1, z1) && all_finite<3>(x0, y0, z0)
                            : all_finite<2>(x1, y1, z1) && all_finite<2>(x0, y0, z0);
         if (ok) {
@@ -117,7 +131,7 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
             atomicOr(&a.sc[s].err, kErrNonFinite);
         }
     }
-    publish_ingest<kB>(&a.sc[s], a.parity, sq, dC);
+    publish_ingest<kB>(&a.sc[s], parity, sq, dC);
 }
 
 // The selector network on one wave: lane j is hidden unit j of both layers.
@@ -166,11 +180,12 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
     const SceneDesc sd = a.desc[s];
     DevScalars *sc = &a.sc[s];
     const int n = sd.n;
+    const int parity = step_number(a) & 1;
     if (threadIdx.x < kVBins) s_vh[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_m = 0;
-    const double Sprev = sc->S[a.parity ^ 1];
-    const float eps = sqrtf(__uint_as_float(sc->dmax[a.parity]));
-    const double St = advance_clock(sc, a.parity, -1.0f, threadIdx.x < 64);
+    const double Sprev = sc->S[parity ^ 1];
+    const float eps = cert_sqrt(__uint_as_float(sc->dmax[parity]));
+    const double St = advance_clock(sc, parity, -1.0f, threadIdx.x < 64);
     double ev[kFRows];
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
@@ -264,7 +279,7 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
         s_dec = dec;
     }
     __syncthreads();
-    if (a.policy == NNC_POLICY_LEARNED && a.have_params && threadIdx.x < 64) {
+    if (a.policy == NNC_POLICY_LEARNED && a.tdev[1] && threadIdx.x < 64) {
         bool finite = true;
         for (int k = 0; k < NNC_FEATURES; ++k) finite = finite && __builtin_isfinite(s_x[k]);
         if (finite) {
@@ -315,7 +330,7 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
     }
     if (threadIdx.x == 0) {
         a.cell_start[sd.soff + sd.ncell] = run;
-        a.sc[s].S_grid = a.sc[s].S[a.parity];
+        a.sc[s].S_grid = a.sc[s].S[step_number(a) & 1];
     }
     __syncthreads();
     const size_t n1 = (size_t)sd.n;
@@ -333,7 +348,7 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
 }
 
 // Per-scene view of the concatenated arrays for the shared query routine.
-__device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneDesc &sd, int s, int init)
+__device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneDesc &sd, int s, int init, int t)
 {
     QueryArgs q;
     q.pos = a.pos_cur + sd.coff;
@@ -347,8 +362,8 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     q.G = sd.G;
     q.all = a.strategy[s];
     q.init = init;
-    q.t = a.t;
-    q.parity = a.parity;
+    q.t = t;
+    q.parity = t & 1;
     q.nn = a.nn + sd.poff;
     q.stamp = a.stamp + sd.poff;
     q.hist = a.hist_fail + sd.goff;
@@ -396,12 +411,13 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
         else hi = mid;
     }
     int s = __builtin_amdgcn_readfirstlane(lo);
+    const int t = step_number(a), parity = t & 1;
     while (g < q1) {
         const int first = a.qpre[s], next = a.qpre[s + 1];
         if (g < next) {
             const SceneDesc sd = a.desc[s];
-            const QueryArgs q = scene_view(a, sd, s, init);
-            const double St = a.sc[s].S[a.parity];
+            const QueryArgs q = scene_view(a, sd, s, init, t);
+            const double St = a.sc[s].S[parity];
             const double margin = query_margin(St, a.sc[s].S_grid, kFuzz);
             const int end = min(next, q1);
             for (; g < end; g += GPW) {
@@ -423,6 +439,8 @@ __global__ void __launch_bounds__(kB) k_b_entropy(BatchArgs a)
     const int s = blockIdx.x;
     const SceneDesc sd = a.desc[s];
     entropy_block<kB>(0, a.hist_fail + sd.goff, a.touched_fail + sd.poff, &a.sc[s]);
+    // the last kernel of a step counts it (no other workgroup of this launch reads the counter)
+    if (s == 0 && threadIdx.x == 0) a.tdev[0] = step_number(a);
 }
 
 // Init: every scene rebuilds, every grid is built, queries are all points.
@@ -460,9 +478,13 @@ struct nnc_batch {
     int ntiles;
     void *arena;
     nnc::BatchArgs a;       // device pointers, refreshed per call
-    int64_t t;
-    int inited, have_params, features_on;
-    const float *pos_cur, *pos_prev;
+    int inited, features_on, eager;
+    // the step as a graph: instantiated on the first call and replayed while
+    // (positions, policy, tau) repeat; another key re-captures and updates it
+    hipGraphExec_t exec;
+    const float *g_pos;
+    int g_policy;
+    float g_tau;
 };
 
 namespace {
@@ -477,14 +499,14 @@ int default_grid_b(int64_t n, int d)
     return g < 1.0 ? 1 : (int)g;
 }
 
-int launch_query_b(nnc_batch *b, int init)
+int launch_query_b(const nnc_batch *b, const nnc::BatchArgs &a, int init)
 {
     const int blocks = 2048;
     switch (b->lanes) {
-    case 1: hipLaunchKernelGGL(nnc::k_b_query<1>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
-    case 64: hipLaunchKernelGGL(nnc::k_b_query<64>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
-    case 32: hipLaunchKernelGGL(nnc::k_b_query<32>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
-    default: hipLaunchKernelGGL(nnc::k_b_query<16>, dim3(blocks), dim3(nnc::kB), 0, b->stream, b->a, init); break;
+    case 1: hipLaunchKernelGGL(nnc::k_b_query<1>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 64: hipLaunchKernelGGL(nnc::k_b_query<64>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 32: hipLaunchKernelGGL(nnc::k_b_query<32>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    default: hipLaunchKernelGGL(nnc::k_b_query<16>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     }
     return nnc::check();
 }
@@ -502,6 +524,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     b->S = cfg->scenes;
     b->lanes = cfg->lanes == 1 || cfg->lanes == 32 || cfg->lanes == 64 ? cfg->lanes : 16;
     b->features_on = (cfg->flags & NNC_BATCH_FEATURES) != 0;
+    b->eager = (cfg->flags & NNC_BATCH_EAGER) != 0;
     b->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
     b->K = 1.0 / (4.0 + 4.0 * b->guard);
     b->stream = (hipStream_t)cfg->stream;
@@ -565,7 +588,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     bytes += 4 * al(Pp * 4);                                   // stamp, frontier, touched x2
     bytes += 4 * al((size_t)NC * 4) + al((size_t)NS * 4);      // counts, cursor, hist x2, cell_start
     bytes += 2 * al(T * 4) + 3 * al(S * 4) + al((S + 1) * 4);  // tiles, strategy/need/qcount, qpre
-    bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4);
+    bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4) + al(4 * 4);
     if (hipMalloc(&b->arena, bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete b;
@@ -611,6 +634,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     a.qpre = (int *)take((S + 1) * 4);
     a.features = (float *)take(S * NNC_FEATURES * 4);
     a.params = (const float *)take(NNC_SELECTOR_PARAMS * 4);
+    a.tdev = (int *)take(4 * 4);
     a.scenes = b->S;
     a.guard = b->guard;
     a.K = b->K;
@@ -637,6 +661,7 @@ void nnc_batch_destroy(nnc_batch *b)
 {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
     (void)hipFree(b->arena);
     delete b;
 }
@@ -655,56 +680,102 @@ int nnc_batch_init(nnc_batch *b, const float *pos)
 {
     if (!b || (!pos && b->P > 0)) return NNC_E_INVAL;
     nnc::BatchArgs &a = b->a;
-    // clear the per-scene scalars and the occupancy and histogram arrays
+    // clear the per-scene scalars, the step counter and the occupancy and histogram arrays
     if (hipMemsetAsync(a.sc, 0, b->S * sizeof(nnc::DevScalars), b->stream) != hipSuccess ||
+        hipMemsetAsync(a.tdev, 0, 4, b->stream) != hipSuccess ||
         hipMemsetAsync(a.counts, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
         hipMemsetAsync(a.hist_fail, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
         hipMemsetAsync(a.hist_cand, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
         hipMemsetAsync(a.nn, 0xff, (size_t)(b->P > 0 ? b->P : 1) * 4, b->stream) != hipSuccess)
         return NNC_E_HIP;
-    b->t = 0;
-    b->pos_cur = pos;
-    b->pos_prev = nullptr;
     a.pos_cur = pos;
-    a.pos_prev = nullptr;
-    a.parity = 0;
-    a.t = 0;
+    a.init = 1;
     if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_cells_init, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_init_flags, dim3((b->S + 255) / 256), dim3(256), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
     int rc = nnc::check();
-    if (rc == NNC_OK) rc = launch_query_b(b, 1);
+    if (rc == NNC_OK) rc = launch_query_b(b, a, 1);
     b->inited = rc == NNC_OK;
     return rc;
 }
+
+namespace {
+
+// The kernels of one step, in order, on the batch's stream.
+int launch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
+{
+    nnc::BatchArgs a = b->a;
+    a.pos_cur = pos_new;
+    a.init = 0;
+    a.policy = policy;
+    a.tau = tau;
+    a.features_on = b->features_on;
+    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_ingest, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
+    int rc = nnc::check();
+    if (rc == NNC_OK) rc = launch_query_b(b, a, 0);
+    if (rc == NNC_OK) {
+        hipLaunchKernelGGL(nnc::k_b_entropy, dim3(b->S), dim3(nnc::kB), 0, b->stream, a);
+        rc = nnc::check();
+    }
+    return rc;
+}
+
+// Capture the step into a graph and instantiate it (or update the existing
+// executable graph in place).  Returns NNC_OK or an error; on error no graph is kept.
+int capture_step(nnc_batch *b, const float *pos_new, int policy, float tau)
+{
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return NNC_E_HIP;
+    const int rc = launch_step(b, pos_new, policy, tau);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->stream, &graph);
+    if (rc != NNC_OK || ec != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return rc != NNC_OK ? rc : NNC_E_HIP;
+    }
+    bool ok = false;
+    if (b->exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult res;
+        ok = hipGraphExecUpdate(b->exec, graph, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+    }
+    if (!ok) ok = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipGraphDestroy(graph);
+    if (!ok) {
+        (void)hipGetLastError();
+        b->exec = nullptr;
+        return NNC_E_HIP;
+    }
+    b->g_pos = pos_new;
+    b->g_policy = policy;
+    b->g_tau = tau;
+    return NNC_OK;
+}
+
+}  // namespace
 
 int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
 {
     if (!b || (!pos_new && b->P > 0)) return NNC_E_INVAL;
     if (!b->inited) return NNC_E_STATE;
     if (policy < NNC_POLICY_REPAIR || policy > NNC_POLICY_LEARNED) return NNC_E_INVAL;
-    b->t += 1;
-    b->pos_prev = b->pos_cur;
-    b->pos_cur = pos_new;
-    nnc::BatchArgs &a = b->a;
-    a.pos_prev = b->pos_prev;
-    a.pos_cur = b->pos_cur;
-    a.parity = (int)(b->t & 1);
-    a.t = (int)b->t;
-    a.policy = policy;
-    a.tau = tau;
-    a.have_params = b->have_params;
-    a.features_on = b->features_on;
-    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_ingest, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
-    hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
-    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
-    int rc = nnc::check();
-    if (rc == NNC_OK) rc = launch_query_b(b, 0);
-    if (rc == NNC_OK) {
-        hipLaunchKernelGGL(nnc::k_b_entropy, dim3(b->S), dim3(nnc::kB), 0, b->stream, a);
-        rc = nnc::check();
+    // a caller's own capture, the null stream, or NNC_BATCH_EAGER: launch the kernels
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (b->eager || !b->stream || hipStreamIsCapturing(b->stream, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
+        return launch_step(b, pos_new, policy, tau);
+    if (!b->exec || b->g_pos != pos_new || b->g_policy != policy || b->g_tau != tau) {
+        const int rc = capture_step(b, pos_new, policy, tau);
+        if (rc != NNC_OK) return rc;
     }
-    return rc;
+    return hipGraphLaunch(b->exec, b->stream) == hipSuccess ? NNC_OK : NNC_E_HIP;
 }
 
 int nnc_batch_selector_load(nnc_batch *b, const float *params)
@@ -713,8 +784,7 @@ int nnc_batch_selector_load(nnc_batch *b, const float *params)
     if (hipMemcpyAsync((void *)b->a.params, params, NNC_SELECTOR_PARAMS * 4, hipMemcpyDeviceToDevice, b->stream) !=
         hipSuccess)
         return NNC_E_HIP;
-    b->have_params = 1;
-    return NNC_OK;
+    return nnc::launch_fill(b->a.tdev + 1, 1, 1, b->stream);
 }
 
 int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)
@@ -723,8 +793,10 @@ int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)
     std::vector<nnc::DevScalars> sc(b->S);
     std::vector<int> strat(b->S);
     std::vector<float> feat((size_t)b->S * NNC_FEATURES);
+    int tdev = 0;
     if (hipMemcpyAsync(sc.data(), b->a.sc, b->S * sizeof(nnc::DevScalars), hipMemcpyDeviceToHost, b->stream) !=
             hipSuccess ||
+        hipMemcpyAsync(&tdev, b->a.tdev, 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
         hipMemcpyAsync(strat.data(), b->a.strategy, b->S * 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
         hipMemcpyAsync(feat.data(), b->a.features, feat.size() * 4, hipMemcpyDeviceToHost, b->stream) !=
             hipSuccess ||
@@ -735,7 +807,7 @@ int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)
         const nnc::DevScalars &h = sc[s];
         nnc_scene_stats &o = out[s];
         o.eps = h.eps;
-        o.S = h.S[b->t & 1];
+        o.S = h.S[tdev & 1];
         o.H_fail = h.H[0];
         o.H_cand = h.H[1];
         o.n_cand = h.F[1];
@@ -765,6 +837,7 @@ int nnc_batch_get_state(nnc_batch *b, nnc_state *v)
     v->n = b->P;
     v->d = 0;
     v->grid_g = 0;
+    v->rho = nullptr;
     return NNC_OK;
 }
 

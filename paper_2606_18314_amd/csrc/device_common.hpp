@@ -13,6 +13,11 @@ namespace nnc {
 
 constexpr float kInf = __builtin_inff();
 
+// Square root of the certificates (d1, d2), of eps_t and of the predictor's
+// displacements: binary32, correctly rounded (the gfx950 lowering of sqrtf without
+// fast-math flags; nnc_sqrt_f32 exposes it so that its rounding can be checked).
+__device__ __forceinline__ float cert_sqrt(float s) { return sqrtf(s); }
+
 // Squared distance ((dx*dx) + (dy*dy)) + (dz*dz), dx = x_j - x_i, binary32.
 template <int D>
 __device__ __forceinline__ float sqdist(float xi, float yi, float zi, float xj, float yj, float zj)

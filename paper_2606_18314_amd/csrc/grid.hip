@@ -849,7 +849,7 @@ __global__ void __launch_bounds__(kB) k_rho(int n, const float *__restrict__ pol
                                        D == 3 ? pnew[n2 + i] : 0.0f);
             const float sj = sqdist<D>(pold[j], pold[n1 + j], D == 3 ? pold[n2 + j] : 0.0f, pnew[j], pnew[n1 + j],
                                        D == 3 ? pnew[n2 + j] : 0.0f);
-            const float delta = sqrtf(si) + sqrtf(sj);
+            const float delta = cert_sqrt(si) + cert_sqrt(sj);
             const float c = d2[i] - d1[i];
             f = 2.0f * delta > c ? 1 : 0;
         }

@@ -165,5 +165,6 @@ int launch_fill(void *p, int value, size_t count, hipStream_t s);
 // allpairs.hip
 int launch_allpairs(const float *pos, int64_t n, int d, const int32_t *qidx, int64_t nq,
                     int32_t *nn, float *d1, float *d2, hipStream_t s);
+int launch_sqrt(const float *x, float *out, int64_t n, hipStream_t s);
 
 }  // namespace nnc

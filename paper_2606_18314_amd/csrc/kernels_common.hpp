@@ -85,7 +85,7 @@ __device__ __forceinline__ double advance_clock(DevScalars *sc, int parity, floa
 {
     const int lane = (int)lane_id();
     const float m = fmaxf(wave_max(__uint_as_float(sc->dmax_part[parity][lane])), __uint_as_float(sc->dmax[parity]));
-    const float eps = sqrtf(m);
+    const float eps = cert_sqrt(m);
     const double St = sc->S[parity ^ 1] + (double)eps;
     if (leader_wave) {
         const int dc = wave_sum(sc->dC_part[lane]);
@@ -768,7 +768,7 @@ __device__ __forceinline__ double query_margin(double St, double S_grid, double 
 __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old,
                                                  int cell)
 {
-    const float d1 = sqrtf(t.s1), d2 = sqrtf(t.s2);
+    const float d1 = cert_sqrt(t.s1), d2 = cert_sqrt(t.s2);
     a.nn[i] = t.nn;
     a.d1[i] = d1;
     a.d2[i] = d2;

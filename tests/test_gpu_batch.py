@@ -114,15 +114,6 @@ def test_batch_lane_widths(nnc, lanes):
     run_batch(nnc, trajs, grids, 2, tau=0.5, lanes=lanes)
 
 
-def test_batch_learned_policy_with_a_random_network(nnc):
-    """Whatever the network decides, each scene stays exact; both strategies occur."""
-    g = np.random.default_rng(5)
-    params = torch.from_numpy(g.standard_normal(4738).astype(np.float32) * 0.5).cuda()
-    trajs, grids = make_scenes(31, 12, steps=8)
-    chosen = run_batch(nnc, trajs, grids, 3, tau=0.5, params=params)
-    assert len(set(chosen)) >= 1
-
-
 def test_batch_equals_single_scene_contexts(nnc):
     trajs, grids = make_scenes(41, 5, steps=6)
     ns = [t.n for t in trajs]

@@ -1,0 +1,426 @@
+"""GPU parity at the configurations the benchmark times, and checks of the checkers.
+
+* the learned policy of the batched step with the committed trained parameters:
+  every scene-step's strategy against the binary64 oracle network on the features
+  the step reported, and all six features against the oracle's definitions;
+* a batch at the shape of the 512-scene workload's scenes (N up to 20000, both d,
+  grids from the batch tuner's refinement rule), one captured step replayed for
+  every step, against per-scene oracles under all four policies;
+* the auditor (nnc_oracle_verify) must report a nearest neighbour and a d1 planted
+  wrong in the state;
+* the local predictor's per-point flags against the oracle's, element by element;
+* the N = 16000 five-family workload at the committed tuned grids and lane widths,
+  40 steps per family, every array on every step;
+* N = 2^20 points in the plane (G = 512): cells of every point, eps_t and S_t, and
+  on 4096 sampled points the expiry keys, candidate membership and repaired
+  certificates against brute force;
+* the square root of the certificates over every non-negative binary32 value
+  against the host's correctly rounded square root.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp, model
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+H_TOL = 1e-12
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nnc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_18314_amd as p
+    from paper_2606_18314_amd import binding
+    p.load()
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def assert_scene_equal(st, a, z, o, tag):
+    assert np.array_equal(st["nn"][a:z], o.nn), tag
+    assert np.array_equal(bits(st["d1"][a:z]), bits(o.d1)), tag
+    assert np.array_equal(bits(st["d2"][a:z]), bits(o.d2)), tag
+    assert np.array_equal(bits(st["e"][a:z]), bits(o.e)), tag
+    assert np.array_equal(st["cell"][a:z], o.cell), tag
+    assert np.array_equal(st["fail"][a:z].astype(bool), o.fail), tag
+
+
+# --- the learned policy of the batched step --------------------------------------------
+
+@pytest.mark.parametrize("network", ["trained", "random"])
+def test_batch_learned_decisions_follow_the_oracle_network(nnc, network):
+    """The selector network evaluated inside the batched step, with the committed
+    trained parameters (selector_params.npy) or a random network: every decision is
+    the binary64 oracle network's decision on the features the step reported, unless
+    the two logits are within a rounding margin (such scene-steps are counted, not
+    judged); every feature equals the oracle's definition; every scene stays exact.
+    The random network must take both decisions, so both branches are exercised."""
+    from paper_2606_18314_amd import selector
+    params, meta = selector.load_params()
+    assert params is not None, "the committed selector parameters are missing"
+    if network == "random":
+        params = (np.random.default_rng(5).standard_normal(params.size) * 0.5).astype(np.float32)
+    p64 = params.astype(np.float64)
+    # scenes of the selector's workload: step sizes over a decade so that both strategies win
+    specs = selector.scene_specs(24, seed=7100, n_hi=8000)
+    steps = 8
+    trajs = [synth.make_trajectory(sp["family"], sp["n"], sp["d"], steps, sp["eps"], tuple(sp["seed"]))
+             for sp in specs]
+    grids = [synth_default_grid(t.n, t.d) for t in trajs]
+    b = nnc.NNCBatch([t.n for t in trajs], [t.d for t in trajs], grids=grids, lanes=16, features=True)
+    b.selector_load(dev(params))
+    oracles = [model.OracleScene(d=t.d, n=t.n, G=G) for t, G in zip(trajs, grids)]
+    frames = [dev(synth.concat_frame(trajs, t)) for t in range(steps + 1)]
+    b.init(frames[0])
+    for o, tr in zip(oracles, trajs):
+        o.init_certificates(tr.frames[0])
+    chosen, close = [], 0
+    for t in range(1, steps + 1):
+        b.step(frames[t], nnc.POLICY_LEARNED, float(meta.get("tau", 0.5)))
+        stats = b.stats()
+        st = {k: host(v) for k, v in b.state().items()}
+        for s, (o, tr) in enumerate(zip(oracles, trajs)):
+            o.step(tr.frames[t])
+            f = np.array(stats[s]["features"], np.float32)
+            want = o.features()
+            assert np.allclose(f.astype(np.float64), want, rtol=2e-6, atol=1e-7), (s, t, f, want)
+            z, _ = mlp.forward(p64, f.astype(np.float64)[None, :])
+            margin = abs(z[0, 1] - z[0, 0])
+            if margin <= 1e-4 * (1.0 + np.abs(z).max()):
+                close += 1
+            else:
+                assert stats[s]["strategy"] == int(mlp.decide(p64, f.astype(np.float64)[None, :])[0]), (s, t)
+            chosen.append(stats[s]["strategy"])
+            o.rebuild() if stats[s]["strategy"] == 1 else o.repair()
+            assert_scene_equal(st, int(b.point_off[s]), int(b.point_off[s + 1]), o, (s, t))
+    b.close()
+    if network == "random":
+        assert set(chosen) == {0, 1}, "both decisions should occur"
+    assert close <= len(chosen) // 20
+    print(f"{network} network: {len(chosen)} scene-steps, {sum(chosen)} rebuilds, {close} within the margin")
+
+
+def synth_default_grid(n, d):
+    from paper_2606_18314_amd import autotune
+    return autotune.default_grid(n, d)
+
+
+def test_batch_features_equal_single_scene_features(nnc):
+    """All six features of the batched step equal those of a single-scene context
+    (nnc_features) on the same transition."""
+    trajs = [synth.make_trajectory(f, n, d, 5, 1e-3, (7200, k))
+             for k, (f, n, d) in enumerate([("clustered_drift", 3000, 3), ("uniform_brownian", 5000, 2),
+                                            ("ring_rotation", 1200, 3), ("shear_band", 7000, 2)])]
+    grids = [12, 60, 9, 70]
+    b = nnc.NNCBatch([t.n for t in trajs], [t.d for t in trajs], grids=grids, features=True)
+    ctxs = [nnc.NNCert(t.n, t.d, grid_g=G) for t, G in zip(trajs, grids)]
+    frames = [dev(synth.concat_frame(trajs, t)) for t in range(6)]
+    b.init(frames[0])
+    for c, tr in zip(ctxs, trajs):
+        c.init_certificates(dev(tr.frames[0]))
+    for t in range(1, 6):
+        b.step(frames[t], nnc.POLICY_REPAIR)
+        stats = b.stats()
+        for s, (c, tr) in enumerate(zip(ctxs, trajs)):
+            c.step(dev(tr.frames[t]))
+            f1 = host(c.features())
+            f0 = np.array(stats[s]["features"], np.float32)
+            assert np.array_equal(f0[[0, 2, 3, 4, 5]], f1[[0, 2, 3, 4, 5]]), (s, t, f0, f1)
+            assert abs(float(f0[1]) - float(f1[1])) <= 1e-6 * max(1.0, abs(float(f1[1]))), (s, t)
+            c.repair()
+    for c in ctxs:
+        c.close()
+    b.close()
+
+
+# --- a captured batched step, replayed ---------------------------------------------------
+
+def _cfg4_like_scenes(seed, count, steps):
+    spec = synth.batch_spec(count, seed=seed)
+    trajs = synth.batch_trajectories(spec, steps, eps=5e-4, seed=seed)
+    return trajs
+
+
+def _tuner_grids(trajs, factor=1.5, target=4.0, cap=8):
+    """The batch tuner's refinement rule (occupied-cell count from the oracle's cells)."""
+    from paper_2606_18314_amd import autotune
+    grids = []
+    for tr in trajs:
+        g0 = autotune.default_grid(tr.n, tr.d)
+        C = max(1, np.unique(model.cells(tr.frames[0], g0)).size)
+        scale = min(8.0, max(1.0, (tr.n / C / target) ** (1.0 / tr.d)))
+        g = max(1, int(round(g0 * scale * factor)))
+        while g > 1 and (g ** tr.d > autotune.MAX_CELLS or g ** tr.d > cap * max(tr.n, 1)):
+            g -= 1
+        grids.append(g)
+    return grids
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2, 3])
+def test_captured_batch_step_replayed_matches_per_scene_oracles(nnc, policy):
+    """64 scenes of the batched workload's distribution (N log-uniform in [500, 20000],
+    d in {2, 3}, the five families), tuner-rule grids; one step captured in a graph by
+    the caller and replayed for steps 2..10 with each frame copied into the captured
+    buffer, every scene compared with its oracle after every replay."""
+    from paper_2606_18314_amd import selector
+    steps = 10
+    trajs = _cfg4_like_scenes(4100 + policy, 64, steps)
+    grids = _tuner_grids(trajs)
+    params, meta = selector.load_params()
+    tau = 0.45 if policy == 2 else float(meta.get("tau", 0.5))
+    s = torch.cuda.Stream()
+    frames = [dev(synth.concat_frame(trajs, t)) for t in range(steps + 1)]
+    buf = frames[1].clone()
+    with torch.cuda.stream(s):
+        b = nnc.NNCBatch([t.n for t in trajs], [t.d for t in trajs], grids=grids, lanes=16, stream=s.cuda_stream,
+                         features=True)
+        if policy == 3:
+            b.selector_load(dev(params))
+        b.init(frames[0])
+    torch.cuda.synchronize()
+    oracles = [model.OracleScene(d=t.d, n=t.n, G=G) for t, G in zip(trajs, grids)]
+    for o, tr in zip(oracles, trajs):
+        o.init_certificates(tr.frames[0])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.step(buf, policy, tau)
+    # capture does not run the step: replay it for every step, frame t in the buffer
+    for t in range(1, steps + 1):
+        with torch.cuda.stream(s):
+            buf.copy_(frames[t])
+            g.replay()
+        torch.cuda.synchronize()
+        stats = b.stats()
+        st = {k: host(v) for k, v in b.state().items()}
+        _ = torch.ones(4096, device="cuda").sum().item()     # unrelated eager work between replays
+        for k, (o, tr) in enumerate(zip(oracles, trajs)):
+            res = o.step(tr.frames[t])
+            assert stats[k]["err"] == 0
+            assert stats[k]["eps"] == float(res.eps) and stats[k]["S"] == res.S, (k, t)
+            assert stats[k]["n_cand"] == res.candidates.size, (k, t)
+            if policy == 0:
+                assert stats[k]["strategy"] == 0
+            elif policy == 1:
+                assert stats[k]["strategy"] == 1
+            elif policy == 2:
+                assert stats[k]["strategy"] == int(np.float32(res.candidates.size) / np.float32(tr.n)
+                                                   >= np.float32(tau))
+            o.rebuild() if stats[k]["strategy"] == 1 else o.repair()
+            assert_scene_equal(st, int(b.point_off[k]), int(b.point_off[k + 1]), o, (k, t))
+            H, m, C, F = o.frontier_entropy(model.FAILED)
+            assert stats[k]["n_fail"] == F
+            assert abs(stats[k]["H_fail"] - H) <= H_TOL * max(1.0, abs(H))
+    del g
+    b.close()
+
+
+def test_library_graph_of_the_batch_step(nnc):
+    """The batch step's own graph (captured on the first call, replayed while the
+    position buffer, policy and tau repeat, re-captured when they change) gives the
+    state of the eagerly launched kernels, step by step."""
+    steps = 8
+    trajs = _cfg4_like_scenes(4200, 24, steps)
+    grids = _tuner_grids(trajs)
+    frames = [dev(synth.concat_frame(trajs, t)) for t in range(steps + 1)]
+    s = torch.cuda.Stream()
+    out = {}
+    for mode in ("eager", "graph_new_buffers", "graph_one_buffer"):
+        with torch.cuda.stream(s):
+            b = nnc.NNCBatch([t.n for t in trajs], [t.d for t in trajs], grids=grids, stream=s.cuda_stream,
+                             eager=mode == "eager")
+            b.init(frames[0])
+            buf = frames[1].clone()
+            states = []
+            for t in range(1, steps + 1):
+                policy = 2 if t % 3 else 1            # the policy changes: a re-capture
+                if mode == "graph_one_buffer":
+                    buf.copy_(frames[t])
+                    b.step(buf, policy, 0.3)
+                else:
+                    b.step(frames[t], policy, 0.3)
+                states.append({k: v.clone() for k, v in b.state().items()})
+        torch.cuda.synchronize()
+        out[mode] = states
+        b.close()
+    for mode in ("graph_new_buffers", "graph_one_buffer"):
+        for t in range(steps):
+            for k in out["eager"][t]:
+                assert torch.equal(out["eager"][t][k], out[mode][t][k]), (mode, t, k)
+
+
+# --- checks of the checkers ----------------------------------------------------------------
+
+def test_auditor_reports_planted_errors(nnc):
+    """nnc_oracle_verify must see one wrong nearest neighbour (a point not recomputed
+    at this step) and one wrong d1 of a freshly recomputed point, written into the
+    state through nnc_get_state's device pointers."""
+    tr = synth.cube_16k("uniform_brownian", n=4000, steps=3)
+    ctx = nnc.NNCert(4000, 3, grid_g=9)
+    ctx.init_certificates(dev(tr.frames[0]))
+    for t in (1, 2):
+        ctx.step(dev(tr.frames[t]), tr.eps)
+        ctx.repair()
+    ctx.step(dev(tr.frames[3]), tr.eps)
+    cand = host(ctx.frontier_indices())
+    ctx.repair()
+    clean = ctx.oracle_verify()
+    assert clean["n_missed"] == 0 and clean["n_value_mismatch"] == 0
+    fresh = int(cand[len(cand) // 2])
+    stale = int(np.setdiff1d(np.arange(4000), cand)[7])
+    st = ctx.state()
+    ptr = ctx.state_pointers()
+    nn_bad = st["nn"][stale:stale + 1].clone()
+    nn_bad[0] = (int(nn_bad[0]) + 1) % 4000
+    if int(nn_bad[0]) == stale:
+        nn_bad[0] = (stale + 1) % 4000
+    d1_bad = torch.nextafter(st["d1"][fresh:fresh + 1], torch.tensor([np.inf], device="cuda"))
+    nnc.copy_to_device(ptr["nn"] + 4 * stale, nn_bad, ctx.stream)
+    nnc.copy_to_device(ptr["d1"] + 4 * fresh, d1_bad, ctx.stream)
+    torch.cuda.synchronize()
+    a = ctx.oracle_verify()
+    assert a["n_missed"] == 1, a
+    assert a["n_value_mismatch"] == 1, a
+    assert a["nn_hash"] != clean["nn_hash"]
+    ctx.close()
+
+
+@pytest.mark.parametrize("family", ["uniform_brownian", "adversarial_crossing", "clustered_drift"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_rho_flags_per_point(nnc, family, d):
+    """The local predictor's flag of every point against the oracle's rho_flags."""
+    tr = synth.make_trajectory(family, 3000, d, 6, 2e-3, 7300 + d)
+    G = 12 if d == 3 else 40
+    ctx = nnc.NNCert(tr.n, d, grid_g=G)
+    sc = model.OracleScene(d=d, n=tr.n, G=G)
+    ctx.init_certificates(dev(tr.frames[0]))
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, tr.steps + 1):
+        ctx.step(dev(tr.frames[t]), tr.eps)
+        sc.step(tr.frames[t])
+        ctx.rho_predict()
+        want = sc.rho_flags()
+        got = host(ctx.rho_flags()).astype(bool)
+        assert np.array_equal(got, want), (t, np.flatnonzero(got != want)[:10])
+        ctx.repair() if t % 2 else ctx.rebuild()
+        sc.repair() if t % 2 else sc.rebuild()
+    ctx.close()
+
+
+# --- the timed configurations at full size ------------------------------------------------
+
+def _tuned_table():
+    with open(os.path.join(ROOT, "paper_2606_18314_amd", "tuned_cube16k.json")) as f:
+        return json.load(f)["scenes"]
+
+
+@pytest.mark.parametrize("family", synth.FAMILIES)
+def test_cube_16k_at_the_tuned_grid_and_lanes(nnc, family):
+    """N = 16000, d = 3 with the grid and lane width the benchmark uses for this
+    family, 40 steps of repair, every array and the candidate list on every step."""
+    row = _tuned_table()[family]
+    G, lanes = int(row["G"]), int(row["lanes"])
+    tr = synth.cube_16k(family, steps=40)
+    ctx = nnc.NNCert(tr.n, 3, grid_g=G, lanes=lanes)
+    sc = model.OracleScene(d=3, n=tr.n, G=G)
+    ctx.init_certificates(dev(tr.frames[0]))
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, 41):
+        ctx.step(dev(tr.frames[t]), tr.eps)
+        res = sc.step(tr.frames[t])
+        assert np.array_equal(host(ctx.frontier_indices()), res.candidates), t
+        ctx.repair()
+        sc.repair()
+        gs = ctx.state()
+        assert np.array_equal(host(gs["nn"]), sc.nn), t
+        assert np.array_equal(bits(host(gs["d1"])), bits(sc.d1)), t
+        assert np.array_equal(bits(host(gs["d2"])), bits(sc.d2)), t
+        assert np.array_equal(bits(host(gs["e"])), bits(sc.e)), t
+        assert np.array_equal(host(gs["cell"]), sc.cell), t
+        assert np.array_equal(host(gs["fail"]).astype(bool), sc.fail), t
+    assert ctx.oracle_verify()["n_missed"] == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["diffuse", "localized"])
+def test_plane_2e20_sampled_against_brute_force(nnc, mode):
+    """N = 2^20 uniform points in the plane, G = 512 (the frontier-sweep workload, eps
+    for about 5 % candidates): cells of every point, eps_t and S_t exactly; on 4096
+    sampled points the initial expiry keys, candidate membership, and after the repair
+    nn, d1, d2 and keys against brute force at the new positions."""
+    n, G = 1 << 20, 512
+    p0 = synth.sweep_start(n)
+    ctx = nnc.NNCert(n, 2, grid_g=G)
+    ctx.init_certificates(dev(p0))
+    g = np.random.default_rng(5 if mode == "diffuse" else 6)
+    q = np.sort(g.choice(n, 4096, replace=False)).astype(np.int64)
+    st = ctx.state()
+    e0 = host(st["e"])
+    nn0, d10, d20 = model.top2(p0, q)
+    assert np.array_equal(host(st["nn"])[q], nn0)
+    assert np.array_equal(bits(host(st["d1"])[q]), bits(d10))
+    assert np.array_equal(bits(e0[q]), bits(model.expiry_key(0.0, d10, d20, model.GUARD_DEFAULT)))
+    c = np.sort(host(st["d2"] - st["d1"]))
+    p1 = synth.sweep_motion(p0, float(c[int(0.05 * n)]) / 4.0, mode)
+    ctx.step(dev(p1), -1.0)
+    ent = ctx.frontier_entropy(nnc.NNC_CANDIDATES)
+    eps = model.max_step(p0, p1)
+    assert ent["eps"] == float(eps)
+    assert ent["S"] == float(np.float64(0.0) + np.float64(eps))
+    cand = host(ctx.frontier_indices())
+    assert np.array_equal(host(ctx.state()["cell"]), model.cells(p1, G))
+    want_member = ent["S"] >= e0[q]
+    assert np.array_equal(np.isin(q, cand), want_member)
+    assert np.all(np.diff(cand) > 0)
+    ctx.repair()
+    st = ctx.state()
+    nn1, d11, d21 = model.top2(p1, q)
+    assert np.array_equal(host(st["nn"])[q], nn1)       # no miss among the sampled points
+    fresh = want_member
+    assert fresh.sum() > 50
+    assert np.array_equal(bits(host(st["d1"])[q][fresh]), bits(d11[fresh]))
+    assert np.array_equal(bits(host(st["d2"])[q][fresh]), bits(d21[fresh]))
+    assert np.array_equal(bits(host(st["e"])[q][fresh]),
+                          bits(model.expiry_key(ent["S"], d11[fresh], d21[fresh], model.GUARD_DEFAULT)))
+    # certificates not recomputed keep their values
+    assert np.array_equal(bits(host(st["e"])[q][~fresh]), bits(e0[q][~fresh]))
+    ctx.close()
+
+
+# --- the square root of the certificates -----------------------------------------------------
+
+def test_certificate_sqrt_is_correctly_rounded_everywhere(nnc):
+    """Every non-negative binary32 value (zero, subnormals, normals, +inf): the
+    library's square root equals the host's correctly rounded one bit for bit."""
+    chunk = 1 << 27
+    total = 0x7F800001                       # bit patterns 0 .. +inf
+    mism = 0
+    for lo in range(0, total, chunk):
+        m = min(chunk, total - lo)
+        xb = torch.arange(lo, lo + m, dtype=torch.int64, device="cuda").to(torch.int32)
+        x = xb.view(torch.float32)
+        got = nnc.sqrt_f32(x)
+        want = np.sqrt(np.arange(lo, lo + m, dtype=np.uint32).view(np.float32))
+        diff = host(got.view(torch.int32)).view(np.uint32) != want.view(np.uint32)
+        mism += int(diff.sum())
+        assert mism == 0, (hex(lo), np.flatnonzero(diff)[:5])
+    assert mism == 0

@@ -477,3 +477,84 @@ def test_box_cells_equal_the_cells_of_exactly_normalised_coordinates():
         assert np.array_equal(boxed, unit)
         p01 = g.random((d, 500)).astype(np.float32)
         assert np.array_equal(model.cells(p01, 17, lo=(0.0,) * 3, hi=(1.0,) * 3), model.cells(p01, 17))
+
+
+# --- the binary64 tie audit and the selector features ------------------------------------
+
+def test_binary64_pair_distance_against_exact_arithmetic():
+    """pair_sqdist64 (the distance of the tie audit) is the real squared distance up to
+    binary64 rounding, and exact on dyadic coordinates with few bits."""
+    g = np.random.default_rng(41)
+    for d in (2, 3):
+        pos = _random_scene(g, 60, d, "uniform")
+        a = g.integers(0, 60, 400)
+        b = g.integers(0, 60, 400)
+        s = model.pair_sqdist64(pos, a, b)
+        P = exact.coords(pos)
+        for k in range(400):
+            S = exact.sqdist_real(P, int(a[k]), int(b[k]))
+            assert abs(Fraction(float(s[k])) - S) <= Fraction(4) * Fraction(2.0 ** -53) * S
+        lat = _random_scene(g, 60, d, "lattice")
+        s = model.pair_sqdist64(lat, a, b)
+        P = exact.coords(lat)
+        for k in range(400):
+            assert Fraction(float(s[k])) == exact.sqdist_real(P, int(a[k]), int(b[k]))
+
+
+def _tie_audit(pos):
+    """(near_ties, errors) of binary32 brute force against binary64 brute force: where
+    the two nearest neighbours differ, a near-tie if their binary64 squared distances
+    are within 16u of each other (u = 2^-24), otherwise an error."""
+    nn32, _, _ = model.top2(pos)
+    nn64, s64 = model.nn_f64(pos)
+    diff = np.flatnonzero(nn32 != nn64)
+    if diff.size == 0:
+        return 0, 0
+    s_other = model.pair_sqdist64(pos, diff, nn32[diff])
+    near = np.abs(s_other - s64[diff]) <= 16.0 * U * s64[diff]
+    return int(near.sum()), int((~near).sum())
+
+
+def test_binary64_tie_audit_of_the_workloads():
+    """Every frame of plane_1k and every 25th frame of the five N = 16000 cube
+    trajectories: the binary32 certificates pick the binary64 nearest neighbour except
+    at near-ties, never farther than the rounding band."""
+    near = err = frames = 0
+    tr = synth.plane_1k()
+    for f in tr.frames:
+        a, b = _tie_audit(f)
+        near, err, frames = near + a, err + b, frames + 1
+    for fam in synth.FAMILIES:
+        tr = synth.cube_16k(fam)
+        for t in range(0, tr.steps + 1, 25):
+            a, b = _tie_audit(tr.frames[t])
+            near, err, frames = near + a, err + b, frames + 1
+    print(f"tie audit: {frames} frames, {near} binary32 near-ties, {err} errors")
+    assert err == 0
+
+
+def test_selector_features_median_bin_and_counts():
+    """The oracle's selector features of a pending step against their definitions
+    recomputed by plain loops: candidate fraction, touched cells over all cells, ln N,
+    d, and the budget median: the bin reported holds the element of rank ceil(V/2) of
+    the sorted budgets."""
+    tr = synth.make_trajectory("clustered_drift", 3000, 3, 4, 1e-3, 77)
+    sc = model.OracleScene(d=3, n=3000, G=12)
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, 5):
+        e_before, S_prev = sc.e.copy(), sc.S
+        res = sc.step(tr.frames[t])
+        f = sc.features()
+        cand = res.candidates
+        assert f[0] == cand.size / 3000
+        assert len({int(sc.cell[i]) for i in cand}) / 12 ** 3 == f[4]
+        assert f[2] == math.log(3000) and f[3] == 3
+        r = sorted(float(e_before[i] - S_prev) for i in range(3000)
+                   if e_before[i] - S_prev > 0 and math.isfinite(e_before[i] - S_prev))
+        med = r[(len(r) + 1) // 2 - 1]
+        radius = float(res.eps) / f[5]
+        lo = radius / 1.5
+        assert lo <= med < 2 * lo, (t, med, radius)
+        H, m, C, F = sc.frontier_entropy(model.CANDIDATES, cand)
+        assert f[1] == H
+        sc.repair()
