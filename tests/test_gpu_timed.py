@@ -79,7 +79,7 @@ def test_batch_learned_decisions_follow_the_oracle_network(nnc, network):
     params, meta = selector.load_params()
     assert params is not None, "the committed selector parameters are missing"
     if network == "random":
-        params = (np.random.default_rng(5).standard_normal(params.size) * 0.5).astype(np.float32)
+        params = _split_network(params.size)
     p64 = params.astype(np.float64)
     # scenes of the selector's workload: step sizes over a decade so that both strategies win
     specs = selector.scene_specs(24, seed=7100, n_hi=8000)
@@ -118,6 +118,26 @@ def test_batch_learned_decisions_follow_the_oracle_network(nnc, network):
         assert set(chosen) == {0, 1}, "both decisions should occur"
     assert close <= len(chosen) // 20
     print(f"{network} network: {len(chosen)} scene-steps, {sum(chosen)} rebuilds, {close} within the margin")
+
+
+def _split_network(size):
+    """Small random weights plus one path that makes the decision follow d (rebuild
+    in the cube, repair in the plane), so that both branches of the in-step decision
+    run; the oracle still judges every decision on the reported features."""
+    p = np.random.default_rng(5).standard_normal(size) * 0.05
+    W1, b1 = 0, 64 * 6                      # layout: W1 [64x6], b1, W2 [64x64], b2, W3 [2x64], b3
+    W2 = b1 + 64
+    b2 = W2 + 64 * 64
+    W3 = b2 + 64
+    b3 = W3 + 2 * 64
+    p[W1 + 0 * 6 + 3] = 10.0                # unit 0 of layer 1: relu(10 d - 25), 0 or 5
+    p[b1 + 0] = -25.0
+    p[W2 + 0 * 64 + 0] = 10.0               # unit 0 of layer 2: about 0 or 50
+    p[b2 + 0] = 0.0
+    p[W3 + 0 * 64 + 0] = -1.0
+    p[W3 + 1 * 64 + 0] = 1.0
+    p[b3 + 0], p[b3 + 1] = 25.0, -25.0       # logit difference about -50 (plane) or +50 (cube)
+    return p.astype(np.float32)
 
 
 def synth_default_grid(n, d):
