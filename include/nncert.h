@@ -361,6 +361,19 @@ size_t nnc_mlp_workspace_bytes(int B);
 int nnc_mlp_grad(const float *params, const float *X, const int32_t *y, const float *w, int B, void *workspace,
                  float *grad, float *loss, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): nnc_mlp_grad without a
+ * workspace argument.  The workspace is a fixed device array inside the library
+ * (4 MiB per device for NNC_MLP_STATIC_MAX_B samples, held until the process
+ * ends); the call allocates nothing.  B above NNC_MLP_STATIC_MAX_B gives
+ * NNC_E_INVAL.  Every call on one device shares that array: calls that overlap
+ * on one device (on different streams) race and must be serialised by the
+ * caller.  The stream's device (the current device for NULL) is used.  Results
+ * equal nnc_mlp_grad's bit for bit.  Asynchronous. */
+#define NNC_MLP_STATIC_MAX_B 4096
+int nnc_mlp_grad_static(const float *params, const float *X, const int32_t *y, const float *w, int B, float *grad,
+                        float *loss, void *stream);
+
 /* One Adam step (step = 1, 2, ...) on params with moments m, v. */
 int nnc_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr, float beta1,
                  float beta2, float eps, void *stream);

@@ -42,7 +42,7 @@ EXPORTS = (
     "nnc_batch_create", "nnc_batch_destroy", "nnc_batch_offsets", "nnc_batch_init", "nnc_batch_step",
     "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
     "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
-    "nnc_sqrt_f32",
+    "nnc_sqrt_f32", "nnc_mlp_grad_static",
 )
 
 POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
@@ -152,6 +152,7 @@ def load():
     lib.nnc_mlp_workspace_bytes.argtypes = [ctypes.c_int]
     lib.nnc_mlp_workspace_bytes.restype = ctypes.c_size_t
     lib.nnc_mlp_grad.argtypes = [P, P, P, P, ctypes.c_int, P, P, P, P]
+    lib.nnc_mlp_grad_static.argtypes = [P, P, P, P, ctypes.c_int, P, P, P]
     lib.nnc_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, P]
     lib.nnc_mlp_forward.argtypes = [P, P, ctypes.c_int, P, P]
@@ -474,6 +475,20 @@ def mlp_grad(params: torch.Tensor, X: torch.Tensor, y: torch.Tensor, w: torch.Te
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
     check(_lib.nnc_mlp_grad(_ptr(params), _ptr(X), _ptr(y), _ptr(w), B, _ptr(workspace), _ptr(g), _ptr(loss),
                             _stream()), "nnc_mlp_grad")
+    return loss, g
+
+
+MLP_STATIC_MAX_B = 4096
+
+
+def mlp_grad_static(params: torch.Tensor, X: torch.Tensor, y: torch.Tensor, w: torch.Tensor):
+    """(loss, grad) like mlp_grad, through the entry point that allocates nothing
+    (its workspace is the library's fixed per-device array; B <= MLP_STATIC_MAX_B)."""
+    B = X.shape[0]
+    g = torch.empty(SELECTOR_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    check(load().nnc_mlp_grad_static(_ptr(params), _ptr(X), _ptr(y), _ptr(w), B, _ptr(g), _ptr(loss), _stream()),
+          "nnc_mlp_grad_static")
     return loss, g
 
 

@@ -13,6 +13,8 @@
 // Parameter layout: W1 [64x6], b1 [64], W2 [64x64], b2 [64], W3 [2x64], b3 [2].
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace nnc {
@@ -170,6 +172,41 @@ inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP
 
 }  // namespace
 
+// Workspace of nnc_mlp_grad_static: H1, H2, D1, D2 [64][B], D3 [2][B], L [B] for
+// B <= NNC_MLP_STATIC_MAX_B, one copy per device for the life of the process.
+constexpr size_t kStaticFloats = (size_t)(4 * NH + NO + 1) * NNC_MLP_STATIC_MAX_B;
+static __device__ __align__(256) float scratch[kStaticFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices];  // device address of scratch, per device
+
+// The device address of this device's copy of scratch (looked up once per device,
+// with that device current).  Null on failure.
+float *scratch_on(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 }  // namespace nnc
 
 extern "C" {
@@ -185,6 +222,24 @@ int nnc_mlp_grad(const float *params, const float *X, const int32_t *y, const fl
                        B, (float *)workspace);
     hipLaunchKernelGGL(nnc::k_mlp_wgrad, dim3((nnc::NP + 1 + nnc::kT - 1) / nnc::kT), dim3(nnc::kT), 0, s, X, B,
                        (const float *)workspace, grad, loss);
+    return nnc::check();
+}
+
+int nnc_mlp_grad_static(const float *params, const float *X, const int32_t *y, const float *w, int B, float *grad,
+                        float *loss, void *stream)
+{
+    if (!params || !X || !y || !w || !grad || !loss || B <= 0 || B > NNC_MLP_STATIC_MAX_B) return NNC_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = -1;
+    if (s ? hipStreamGetDevice(s, &dev) != hipSuccess : hipGetDevice(&dev) != hipSuccess) return NNC_E_HIP;
+    float *ws = nnc::scratch_on(dev);
+    if (!ws) return NNC_E_HIP;
+    // every workspace entry the gradient kernel reads is written by the first kernel
+    // for this B: nothing needs clearing between calls
+    hipLaunchKernelGGL(nnc::k_mlp_fwd_bwd, dim3((B + nnc::kT - 1) / nnc::kT), dim3(nnc::kT), 0, s, params, X, y, w,
+                       B, ws);
+    hipLaunchKernelGGL(nnc::k_mlp_wgrad, dim3((nnc::NP + 1 + nnc::kT - 1) / nnc::kT), dim3(nnc::kT), 0, s, X, B,
+                       (const float *)ws, grad, loss);
     return nnc::check();
 }
 
