@@ -142,26 +142,32 @@ typedef struct {
     int32_t count;    /* |set| */
 } nnc_entropy;
 
-/* Create a context for cfg->n points in cfg->d dimensions; allocates all state.
+/* Create a context for cfg->n points in cfg->d dimensions (Section 2: the moving
+ * point set, its per-point records and the uniform grid sized for a constant mean
+ * occupancy); allocates all state.
  * Errors: NNC_E_INVAL (d not 2/3, n out of range, G^d over 2^24), NNC_E_NOMEM. */
 int nnc_create(nnc_ctx **out, const nnc_config *cfg);
 
-/* Release every buffer of the context (after draining its stream). */
+/* Release every buffer of the context created by nnc_create (Section 2's state),
+ * after draining its stream.  NULL is ignored. */
 void nnc_destroy(nnc_ctx *ctx);
 
-/* Certificates of every point at positions pos (device, float32 [d][n]) by a full
- * grid build and 2-NN query; clock S = 0.  pos is borrowed: it must stay
+/* Certificates (Definition 1) of every point at positions pos (device, float32
+ * [d][n]) by a full grid build and 2-NN query; clock S = 0.  pos is borrowed: it must stay
  * unchanged until the next nnc_step returns (or is copied with
  * NNC_COPY_POSITIONS).  Asynchronous. */
 int nnc_init_certificates(nnc_ctx *ctx, const float *pos);
 
 /* One step of Algorithm 1 up to its repair loop: measure eps_t against the
- * previous frame, advance the clock, bring every cell id up to date, and
- * compact the candidates S_t >= e_i into an ascending list (out).
+ * previous frame, advance the clock (appendix, per-step cost), bring every cell
+ * id up to date, and compact the candidates S_t >= e_i (Lemma 1, Theorem 2) into
+ * an ascending list (out).
  * pos_new (device, float32 [d][n]) is borrowed like in init.  eps_declared < 0:
  * no check; else a measured eps_t > eps_declared * (1 + 2^-16) + 2^-20 (the
- * slack covers rounding of coordinates to binary32) is reported as NNC_E_EPS;
- * the step still uses the measured eps_t, so certificates stay exact.  The
+ * slack covers rounding of coordinates to binary32) is reported as NNC_E_EPS by
+ * the next synchronising call, and the step still runs with the measured eps_t, so
+ * certificates stay exact: the state IS advanced (the check runs on the device,
+ * and holding the state back would need a synchronisation every step).  The
  * declared bound also paces the refresh of the grid index.  Asynchronous unless NNC_SYNC.  A step must be followed by exactly
  * one nnc_repair or nnc_rebuild before the next step (NNC_E_STATE otherwise). */
 int nnc_step(nnc_ctx *ctx, const float *pos_new, float eps_declared, nnc_frontier *out);
@@ -174,13 +180,15 @@ int nnc_step(nnc_ctx *ctx, const float *pos_new, float eps_declared, nnc_frontie
  * by nnc_frontier_entropy.  Asynchronous. */
 int nnc_repair(nnc_ctx *ctx, const nnc_frontier *f);
 
-/* The competitor: rebin all n points and recompute every certificate
- * (O(N) grid rebuild), in place of nnc_repair for the pending step.  Asynchronous. */
+/* The competitor (Section 3's GPU grid rebuild; Theorem 3's Theta(N) side): rebin
+ * all n points and recompute every certificate, in place of nnc_repair for the
+ * pending step.  Asynchronous. */
 int nnc_rebuild(nnc_ctx *ctx);
 
-/* Exact tiled all-pairs top-2 of the current positions on the GPU, compared with
- * the state: nn of every point, d1/d2 bitwise of points certified at the last
- * step.  Synchronises. */
+/* The exact frontier oracle (Section 3; the no-miss audit of Section 4 and
+ * Corollary 1): tiled all-pairs top-2 of the current positions on the GPU,
+ * compared with the state: nn of every point, d1/d2 bitwise of points certified
+ * at the last step.  Synchronises. */
 int nnc_oracle_verify(nnc_ctx *ctx, nnc_audit *out);
 
 /* The local failure predictor the paper reports beside the safety rule (Section 4,
@@ -195,27 +203,35 @@ int nnc_oracle_verify(nnc_ctx *ctx, nnc_audit *out);
 int nnc_rho_predict(nnc_ctx *ctx);
 
 /* Normalised entropy (Definition 2) of the failed set or of the last step's
- * candidates, over the current cells.  Synchronises. */
+ * candidates, over the current cells, with m and C (Theorem 4: m >= C^H), in one
+ * struct with eps_t, S_t and the set's size.  Synchronises. */
 int nnc_frontier_entropy(nnc_ctx *ctx, int which, nnc_entropy *out);
 
 /* The six selector features of the pending step (after nnc_step, before
- * nnc_repair/nnc_rebuild), written to out (device float32 [NNC_FEATURES]):
+ * nnc_repair/nnc_rebuild); the selector predicts Section 3's best-strategy label
+ * (the fastest strategy of the transition) from them, written to out (device float32 [NNC_FEATURES]):
  * |F|/N, H of the candidates, ln N, d, cells met by the candidates / G^d, and
  * eps_t / the median remaining motion budget e_i - S_{t-1} (median from a
  * power-of-two histogram).  Asynchronous. */
 int nnc_features(nnc_ctx *ctx, float *out);
 
-/* Read-only device views of the state arrays.  Does not synchronise. */
+/* Read-only device views of the state arrays: the per-point record of Section 2
+ * (certificate of Definition 1, expiry key of the appendix, cell of Algorithm 1,
+ * failure flag of Definition 2).  Does not synchronise. */
 int nnc_get_state(nnc_ctx *ctx, nnc_state *v);
 
-/* Device-side copy of the whole state (for timing two strategies on one step). */
+/* Device-side copy of the whole state, so that both strategies can be timed on one
+ * transition (Section 3 labels each transition with its fastest strategy).
+ * Allocates the snapshot; restore copies it back (asynchronous); snap_free
+ * releases it (NULL ignored). */
 int nnc_snapshot(nnc_ctx *ctx, nnc_snap **out);
 int nnc_restore(nnc_ctx *ctx, const nnc_snap *snap);
 /* Overwrite an existing snapshot of this context with the current state (no allocation). */
 int nnc_snapshot_update(nnc_ctx *ctx, nnc_snap *snap);
 void nnc_snap_free(nnc_snap *snap);
 
-/* Standalone exact all-pairs top-2 (the brute-force competitor and ground truth):
+/* Standalone exact all-pairs top-2 (Section 3's full N x N pass and Table 2's brute
+ * force; the ground truth of Definition 1):
  * for every point of pos (device float32 [d][n]) -- or for the nq listed points
  * when qidx (device int32 [nq]) is not NULL -- write nn (int32), d1, d2 (float32)
  * to device arrays of length n (or nq).  stream: hipStream_t or NULL.
@@ -245,7 +261,7 @@ typedef struct {
 } nnc_profile;
 
 /* Enable (1) or disable (0) HIP-event timing of every kernel the context
- * launches, per class.  Events are recorded on the context's stream around each
+ * launches, per class (the per-strategy times of Section 3's cost comparison).  Events are recorded on the context's stream around each
  * launch; enabling adds an event pair per launch, so use it for measurement
  * passes only.  Not for use under stream capture. */
 int nnc_profile_enable(nnc_ctx *ctx, int enable);
@@ -305,7 +321,8 @@ typedef struct {
     float   features[NNC_FEATURES];
 } nnc_scene_stats;
 
-/* Create a batch; allocates every buffer.  Scene s's coordinates occupy a
+/* Create a batch of independent scenes, each the point set of Section 2; allocates
+ * every buffer.  Scene s's coordinates occupy a
  * float32 [d_s][n_s] block at offset coord_off[s] of the concatenated position
  * arrays, and its per-point state the range [point_off[s], point_off[s] + n_s)
  * of the concatenated state arrays (offsets from nnc_batch_offsets).
@@ -313,11 +330,12 @@ typedef struct {
 int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg);
 void nnc_batch_destroy(nnc_batch *b);
 
-/* Host arrays of scenes+1 entries each (the last entry is the total). */
+/* Where each scene's points and coordinates sit in the concatenated arrays: host
+ * arrays of scenes+1 entries each (the last entry is the total). */
 int nnc_batch_offsets(const nnc_batch *b, int64_t *point_off, int64_t *coord_off);
 
-/* Certificates of every point of every scene (device, concatenated positions;
- * borrowed like nnc_init_certificates).  Asynchronous. */
+/* Certificates (Definition 1) of every point of every scene (device, concatenated
+ * positions, read during the call).  Asynchronous. */
 int nnc_batch_init(nnc_batch *b, const float *pos);
 
 /* One maintenance step of every scene (Algorithm 1 per scene, with the clock of
@@ -338,19 +356,23 @@ int nnc_batch_init(nnc_batch *b, const float *pos);
  * synchronisation happens inside a step. */
 int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau);
 
-/* Load the selector's parameters (device float32 [NNC_SELECTOR_PARAMS]); copied. */
+/* Load the selector's parameters (device float32 [NNC_SELECTOR_PARAMS]); copied.
+ * The network predicts Section 3's best-strategy label for NNC_POLICY_LEARNED. */
 int nnc_batch_selector_load(nnc_batch *b, const float *params);
 
-/* Per-scene results of the last step (host array [scenes]).  Synchronises. */
+/* Per-scene results of the last step (host array [scenes]): eps_t and S_t
+ * (appendix clock), sizes and entropies of the failed and candidate sets
+ * (Definition 2), the features and the chosen strategy.  Synchronises. */
 int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out);
 
-/* Device views of the concatenated state arrays (n = total points, d = 0,
- * grid_g = 0).  Does not synchronise. */
+/* Device views of the concatenated per-point records (Section 2; n = total
+ * points, d = 0, grid_g = 0, rho = NULL).  Does not synchronise. */
 int nnc_batch_get_state(nnc_batch *b, nnc_state *v);
 
 /* ---- selector network: training and inference kernels ----------------------- */
-/* A 6-64-64-2 ReLU network in FP32 (layout as NNC_SELECTOR_PARAMS above).  All
- * pointers are device pointers; all calls are asynchronous on stream. */
+/* A 6-64-64-2 ReLU network in FP32 (layout as NNC_SELECTOR_PARAMS above) that
+ * predicts Section 3's best-strategy label (repair or rebuild) from the features.
+ * All pointers are device pointers; all calls are asynchronous on stream. */
 
 /* Bytes of workspace nnc_mlp_grad needs for a batch of B samples. */
 size_t nnc_mlp_workspace_bytes(int B);
@@ -381,7 +403,7 @@ int nnc_mlp_adam(float *params, float *m, float *v, const float *grad, int step,
 /* Logits [B][2] of a batch of feature rows X [B][6]. */
 int nnc_mlp_forward(const float *params, const float *X, int B, float *logits, void *stream);
 
-/* Human-readable text of an error code. */
+/* Human-readable text of an error code (a static string; never NULL). */
 const char *nnc_strerror(int code);
 
 #ifdef __cplusplus

@@ -33,6 +33,19 @@ routine for the certificates themselves:
 The literal reading of Algorithm 1 across many steps (a point is a candidate
 when its possibly stale clearance is at most 4 * eps_t of this step alone) is
 kept as ``rule="literal"`` so that a test can show it misses failures.
+
+``rule="budget"`` is the tighter per-point safe set the Limitations section
+asks for (a per-point motion budget in place of the global step bound): a
+point whose key has expired is re-tested against its kept certificate
+(nn = j, d2, made at clock S_i).  Every point has moved at most
+D = S_t - S_i since, so every k != j is at least d2 - 2 D from i now, while j
+is at its current distance r = |p_i - p_j| (binary32 formula, sqrtf).  If
+r < d2 - 2 D, j is still the strict nearest neighbour: the certificate is
+kept and its key is moved to S_t + (d2 - 2 D - r) / 4 (the gap closes by at
+most 4 per unit of clock: r grows by 2 and d2 - 2 D falls by 2); otherwise
+the point is a candidate.  With the guard g: the test uses
+thr = d2 (1 - g) - 2 (D (1 + g)), gap = thr - r, kept iff gap > 0, new key
+S_t + gap * K; all in binary64 in that order.
 """
 from __future__ import annotations
 
@@ -256,6 +269,7 @@ class OracleScene:
     cell: np.ndarray = None
     fail: np.ndarray = None
     S: float = 0.0
+    Si: np.ndarray = None             # clock at which each certificate was computed
     pending: StepResult = None
     last_eps: np.float32 = field(default_factory=lambda: np.float32(0))
 
@@ -266,6 +280,7 @@ class OracleScene:
         self.d1[idx] = d1
         self.d2[idx] = d2
         self.e[idx] = expiry_key(self.S, d1, d2, self.guard)
+        self.Si[idx] = self.S
         self.fail[:] = False
         self.fail[idx] = nn != old
 
@@ -276,6 +291,7 @@ class OracleScene:
         self.d1 = np.full(n, np.inf, np.float32)
         self.d2 = np.full(n, np.inf, np.float32)
         self.e = np.full(n, np.inf, np.float64)
+        self.Si = np.zeros(n, np.float64)
         self.fail = np.zeros(n, bool)
         self.S = 0.0
         self.cell = cells(self.pos, self.G, self.lo, self.hi)
@@ -294,6 +310,8 @@ class OracleScene:
         self.last_eps = eps
         if self.rule == "clock":
             cand = np.flatnonzero(self.S >= self.e)
+        elif self.rule == "budget":
+            cand = self._budget_test(np.flatnonzero(self.S >= self.e))
         elif self.rule == "literal":
             c = clearance(self.d1, self.d2).astype(np.float64)
             cand = np.flatnonzero(c <= 4.0 * np.float64(eps))
@@ -301,6 +319,23 @@ class OracleScene:
             raise ValueError(self.rule)
         self.pending = StepResult(eps, self.S, cand.astype(np.int64))
         return self.pending
+
+    def _budget_test(self, expired: np.ndarray) -> np.ndarray:
+        """The per-point budget test of the expired points (module docstring); moves
+        the keys of those whose kept neighbour is provably still nearest and returns
+        the others, the candidates."""
+        if expired.size == 0:
+            return expired
+        g = self.guard
+        j = self.nn[expired].astype(np.int64)
+        r = np.sqrt(pair_sqdist32(self.pos, expired, j))                 # binary32
+        D = np.float64(self.S) - self.Si[expired]
+        thr = self.d2[expired].astype(np.float64) * (1.0 - g) - 2.0 * (D * (1.0 + g))
+        gap = thr - r.astype(np.float64)
+        keep = gap > 0.0
+        K = np.float64(1.0) / (np.float64(4.0) + np.float64(4.0) * np.float64(g))
+        self.e[expired[keep]] = np.float64(self.S) + gap[keep] * K
+        return expired[~keep]
 
     def rho_flags(self) -> np.ndarray:
         """The local predictor the paper reports beside the safety rule (Section 4,

@@ -558,3 +558,116 @@ def test_selector_features_median_bin_and_counts():
         H, m, C, F = sc.frontier_entropy(model.CANDIDATES, cand)
         assert f[1] == H
         sc.repair()
+
+
+# --- the per-point motion budget (rule "budget") -------------------------------------------
+
+def _line_scene_moves(eta, order, d1, eps, d, moves):
+    p0, p1, ia, ik = _line_scene(eta, order, d1, eps, d)
+    if moves == "k":                       # only k moves (toward i); i and a stay
+        p1 = p0.copy()
+        p1[0, ik] = np.float32(float(p0[0, ik]) + eps)
+    return p0, p1, ia, ik
+
+
+@pytest.mark.parametrize("guard", [0.0, model.GUARD_DEFAULT])
+@pytest.mark.parametrize("d", [2, 3])
+def test_budget_rule_line_constructions(guard, d):
+    """The per-point test on Theorem 2's line: as tight as the clock rule when i and
+    its neighbour move apart (the theorem's worst case), strictly tighter when they
+    stand still; the key of a kept point moves to S_t + gap/4; never a missed failure."""
+    fx = _golden("budget_tightness.json")
+    eps = fx["eps"]
+    for case in fx["cases"]:
+        p0, p1, ia, ik = _line_scene_moves(case["eta"], case["order"], fx["d1"], eps, d, case["moves"])
+        for rule in ("budget", "clock"):
+            sc = model.OracleScene(d=d, n=3, G=4, guard=guard, rule=rule)
+            sc.init_certificates(p0)
+            assert sc.nn[0] == ia and float(sc.d2[0]) - float(sc.d1[0]) == case["eta"] * eps
+            res = sc.step(p1)
+            assert float(res.eps) == eps
+            want = case["candidate"] if rule == "budget" else case["clock_candidate"]
+            assert (0 in set(res.candidates.tolist())) == want, (case, rule)
+            if rule == "budget" and guard == 0.0 and case["key_over_eps"] is not None:
+                assert sc.e[0] == case["key_over_eps"] * eps, case
+            sc.repair()
+            assert bool(sc.fail[0]) == case["nn_changes"]
+            assert sc.audit().size == 0
+
+
+def test_budget_rule_lattice_enumeration_no_miss_and_subset():
+    """All 504 x 125 lattice configurations: the per-point rule's candidates are a
+    subset of the clock rule's, contain every failure, and the enumeration reaches
+    the rule's boundary (|p_i - p_nn| = d2 - 2 eps exactly)."""
+    n_cases = n_strict = n_boundary = 0
+    for p0, p1 in _lattice_cases_2d():
+        a = model.OracleScene(d=2, n=3, G=2, guard=0.0, rule="budget")
+        b = model.OracleScene(d=2, n=3, G=2, guard=0.0)
+        a.init_certificates(p0)
+        b.init_certificates(p0)
+        nn_before = a.nn.copy()
+        r = np.sqrt(model.pair_sqdist32(p1, np.arange(3), nn_before.astype(np.int64))).astype(np.float64)
+        thr = a.d2.astype(np.float64)
+        ra, rb = a.step(p1), b.step(p1)
+        ca, cb = set(ra.candidates.tolist()), set(rb.candidates.tolist())
+        thr = thr - 2.0 * float(ra.eps)
+        nn_after, _, _ = model.top2(p1)
+        failed = set(np.flatnonzero(nn_after != nn_before).tolist())
+        assert failed <= ca <= cb
+        a.repair()
+        assert np.array_equal(a.nn, nn_after)
+        n_cases += 1
+        n_strict += len(cb - ca)
+        n_boundary += int(np.sum(r == thr))
+    assert n_cases == 504 * 125
+    assert n_strict > 1000 and n_boundary > 1000
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_budget_rule_multistep_lattice_walks_no_miss(d):
+    """Random walks of 40 points on a fine dyadic lattice (exact arithmetic, ties
+    everywhere), 30 steps each, with repairs and an occasional rebuild: refreshed keys
+    carried over many steps never hide a failure."""
+    g = np.random.default_rng(500 + d)
+    for walk in range(12):
+        p = (g.integers(0, 16, (d, 40)) / 16.0).astype(np.float64)
+        sc = model.OracleScene(d=d, n=40, G=4, guard=0.0 if walk % 2 else model.GUARD_DEFAULT, rule="budget")
+        sc.init_certificates(p.astype(np.float32))
+        for t in range(30):
+            mv = np.zeros_like(p)
+            who = g.random(40) < 0.3
+            ax = g.integers(0, d, 40)
+            mv[ax, np.arange(40)] = np.where(who, g.choice([-1.0, 1.0], 40) / 64.0, 0.0)
+            p = p + mv
+            nn_before = sc.nn.copy()
+            res = sc.step(p.astype(np.float32))
+            nn_after, _, _ = model.top2(p.astype(np.float32))
+            assert set(np.flatnonzero(nn_after != nn_before).tolist()) <= set(res.candidates.tolist())
+            sc.rebuild() if t % 11 == 10 else sc.repair()
+            assert np.array_equal(sc.nn, nn_after), (walk, t)
+
+
+@pytest.mark.parametrize("family", ["uniform_brownian", "ring_rotation", "adversarial_crossing", "clustered_drift",
+                                    "shear_band"])
+def test_budget_rule_no_miss_on_the_workload_families(family):
+    """Reduced cube trajectories (N = 3000, 25 steps): every step the per-point rule
+    misses nothing, its failure set is the true change, and over the run it flags
+    fewer points than the clock rule."""
+    tr = synth.make_trajectory(family, 3000, 3, 25, 5e-4, 2000 + synth.FAMILIES.index(family))
+    a = model.OracleScene(d=3, n=3000, G=9, rule="budget")
+    b = model.OracleScene(d=3, n=3000, G=9)
+    a.init_certificates(tr.frames[0])
+    b.init_certificates(tr.frames[0])
+    prev = a.nn.copy()
+    na = nb = 0
+    for t in range(1, 26):
+        ra, rb = a.step(tr.frames[t]), b.step(tr.frames[t])
+        a.repair()
+        b.repair()
+        now = model.top2(tr.frames[t])[0]
+        assert np.array_equal(a.nn, now) and np.array_equal(b.nn, now)
+        assert set(np.flatnonzero(a.fail)) == set(np.flatnonzero(now != prev))
+        prev = now
+        na += ra.candidates.size
+        nb += rb.candidates.size
+    assert na < nb
