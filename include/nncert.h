@@ -67,6 +67,15 @@ extern "C" {
  * N = 2^17 (d = 2) or 2^19 (d = 3) on for a rebuild, pointwise below; these force one. */
 #define NNC_QUERY_TILED     4u
 #define NNC_QUERY_POINTWISE 8u
+/* Per-point motion budget (the Limitations section's tighter safe set): each step,
+ * a point whose key S_i + c_i/4 has expired is re-tested against its kept
+ * certificate (nn = j, d2, made at clock S_i).  Every point has moved at most
+ * D = S_t - S_i since, so j is still the strict nearest neighbour while its current
+ * distance r (binary32 formula) is below d2 - 2 D; then the certificate is kept and
+ * its key moves to S_t + gap * K, gap = (d2 (1 - g) - 2 (D (1 + g))) - r in
+ * binary64 (g the guard, K = 1/(4 + 4g)); otherwise the point is a candidate.
+ * The candidates are a subset of the clock rule's; no failure is missed. */
+#define NNC_BUDGET          16u
 
 /* nnc_frontier_entropy: which set */
 #define NNC_FAILED     0      /* certificates whose nearest neighbour changed (Definition 2) */
@@ -83,7 +92,8 @@ typedef struct {
     double   refresh;     /* loose-grid refresh when accumulated motion since the last
                              index build exceeds refresh * cell width; <= 0 = 0.25 */
     void    *stream;      /* hipStream_t to order work on; NULL = the null stream */
-    uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC | NNC_QUERY_TILED | NNC_QUERY_POINTWISE */
+    uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC | NNC_QUERY_TILED | NNC_QUERY_POINTWISE |
+                             NNC_BUDGET */
     int32_t  block;       /* lanes that share one 2-NN query: 1 (one thread per query,
                              for large N), 16, 32 or 64; 0 = 32 for d = 3 and 16 for d = 2 */
     /* Domain box of the grid: axis k is cut into grid_g equal cells over
@@ -118,6 +128,8 @@ typedef struct {
     int32_t d, grid_g;
     const uint8_t *rho;   /* device [n], flags of the local predictor (nnc_rho_predict) of
                              the last step; meaningful only after that call, NULL in a batch */
+    const double *Si;     /* device [n], clock S_i at which each certificate was computed
+                             (NULL in a batch) */
 } nnc_state;
 
 typedef struct {

@@ -31,6 +31,7 @@ NNC_COPY_POSITIONS = 1
 NNC_SYNC = 2
 NNC_QUERY_TILED = 4
 NNC_QUERY_POINTWISE = 8
+NNC_BUDGET = 16
 
 NNC_FAILED = 0
 NNC_CANDIDATES = 1
@@ -75,7 +76,7 @@ class State(ctypes.Structure):
     _fields_ = [("nn", ctypes.c_void_p), ("d1", ctypes.c_void_p), ("d2", ctypes.c_void_p),
                 ("e", ctypes.c_void_p), ("cell", ctypes.c_void_p), ("fail", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("grid_g", ctypes.c_int32),
-                ("rho", ctypes.c_void_p)]
+                ("rho", ctypes.c_void_p), ("Si", ctypes.c_void_p)]
 
 
 class Audit(ctypes.Structure):
@@ -249,11 +250,12 @@ class NNCert:
 
     def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
                  copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0,
-                 all_query: str = "auto", box=None):
+                 all_query: str = "auto", box=None, budget: bool = False):
         """all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
         query every point (under "auto" tiled by cells from N = 65536 on at
         initialisation, from 2^17 (d = 2) or 2^19 (d = 3) on at a rebuild).
-        box: (lo, hi), per-axis bounds of the grid's domain (default the unit box)."""
+        box: (lo, hi), per-axis bounds of the grid's domain (default the unit box).
+        budget: the per-point motion budget (NNC_BUDGET) tightens the candidate set."""
         if all_query not in ("auto", "tiled", "pointwise"):
             raise ValueError("all_query: 'auto', 'tiled' or 'pointwise'")
         lib = load()
@@ -263,7 +265,8 @@ class NNCert:
                      stream=self.stream,
                      flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0)
                      | (NNC_QUERY_TILED if all_query == "tiled" else 0)
-                     | (NNC_QUERY_POINTWISE if all_query == "pointwise" else 0),
+                     | (NNC_QUERY_POINTWISE if all_query == "pointwise" else 0)
+                     | (NNC_BUDGET if budget else 0),
                      block=int(lanes))
         if box is not None:
             lo, hi = box
@@ -339,7 +342,8 @@ class NNCert:
         """Copies of the state arrays as CUDA tensors."""
         st, n = self._state, self.n
         spec = [("nn", torch.int32, 4), ("d1", torch.float32, 4), ("d2", torch.float32, 4),
-                ("e", torch.float64, 8), ("cell", torch.int32, 4), ("fail", torch.uint8, 1)]
+                ("e", torch.float64, 8), ("cell", torch.int32, 4), ("fail", torch.uint8, 1),
+                ("Si", torch.float64, 8)]
         out = {}
         for name, dt, sz in spec:
             t = torch.empty(n, dtype=dt, device="cuda")

@@ -46,6 +46,7 @@ size_t carve(nnc_ctx *c, char *base)
     c->d1 = k.take<float>(n);
     c->d2 = k.take<float>(n);
     c->e = k.take<double>(n);
+    c->Si = k.take<double>(n);
     c->fail = k.take<uint8_t>(n);
     c->frontier = k.take<int32_t>(n);
     c->grid.counts = k.take<int>(nc);
@@ -280,6 +281,8 @@ int nnc_step(nnc_ctx *c, const float *pos_new, float eps_declared, nnc_frontier 
     c->pos_prev = c->pos_cur;
     c->pos_cur = adopt_positions(c, pos_new);
     int rc = timed(c, NNC_K_INGEST, [&] { return nnc::launch_ingest(c, c->pos_prev, c->pos_cur); });
+    if (rc == NNC_OK && (c->flags & NNC_BUDGET))
+        rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_budget(c); });
     if (rc == NNC_OK) rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_filter(c, eps_declared); });
     if (rc != NNC_OK) return rc;
     c->grid_fresh = 0;
@@ -416,6 +419,7 @@ int nnc_get_state(nnc_ctx *c, nnc_state *v)
     v->d = c->d;
     v->grid_g = c->G;
     v->rho = c->rho;
+    v->Si = c->Si;
     return NNC_OK;
 }
 

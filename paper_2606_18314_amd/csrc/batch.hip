@@ -371,6 +371,7 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     q.d1 = a.d1 + sd.poff;
     q.d2 = a.d2 + sd.poff;
     q.e = a.e + sd.poff;
+    q.Si = nullptr;
     q.fail = a.fail + sd.poff;
     q.sc = &a.sc[s];
     q.guard = a.guard;
@@ -838,6 +839,7 @@ int nnc_batch_get_state(nnc_batch *b, nnc_state *v)
     v->d = 0;
     v->grid_g = 0;
     v->rho = nullptr;
+    v->Si = nullptr;
     return NNC_OK;
 }
 

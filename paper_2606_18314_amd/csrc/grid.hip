@@ -663,7 +663,7 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
             // whose blocks hold few points: the whole block; measured)
             double T = __builtin_inf(), glo[3] = {0.0, 0.0, 0.0}, ghi[3] = {0.0, 0.0, 0.0};
             if (D == 3 && !a.init) {
-                T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
+                T = point_cutoff(a, i, St, margin);
                 cell_gaps<D, UNIT>(a, x, y, z, cx, cy, cz, glo, ghi);
             }
             const double T2 = T < __builtin_inf() ? T * T : __builtin_inf();
@@ -827,6 +827,40 @@ __global__ void __launch_bounds__(kB) k_audit(int n, const int *__restrict__ nn,
         atomicAdd(&sc->audit[3], (unsigned long long)fresh);
         atomicAdd(&sc->audit[4], h);
         if (hit) atomicAdd(&sc->audit[7], (unsigned long long)hit);
+    }
+}
+
+// Per-point motion budget (the Limitations section's tighter safe set; Theorem 2
+// applied to the kept certificate).  Every point has moved at most
+// D = S_t - S_i since point i's certificate (nn = j, d2) was made, so every other
+// point is at least d2 - 2 D from i now, while j is at its current distance r.
+// For each point whose key has expired: if r < d2 - 2 D (with the guard g:
+// gap = (d2 (1 - g) - 2 (D (1 + g))) - r > 0) the certificate is kept and its key
+// moves to S_t + gap * K -- the gap closes by at most 4 per unit of clock --
+// otherwise the point stays expired and the filter makes it a candidate.  S_t is
+// computed as the filter will (from the same ingest maxima), read-only.
+template <int D>
+__global__ void __launch_bounds__(kB) k_budget(const float *__restrict__ pos, int n, const int *__restrict__ nn,
+                                               const float *__restrict__ d2, const double *__restrict__ Si,
+                                               double *__restrict__ e, const DevScalars *__restrict__ sc, int parity,
+                                               double guard, double K)
+{
+    const int lane = (int)lane_id();
+    const float m = fmaxf(wave_max(__uint_as_float(sc->dmax_part[parity][lane])), __uint_as_float(sc->dmax[parity]));
+    const double St = sc->S[parity ^ 1] + (double)cert_sqrt(m);
+    const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
+    for (int i = blockIdx.x * kB + (int)threadIdx.x; i < n; i += gridDim.x * kB) {
+        const double ei = e[i];
+        if (!(St >= ei)) continue;
+        const int j = nn[i];
+        if (j < 0 || j >= n) continue;
+        const float s = sqdist<D>(pos[i], pos[n1 + i], D == 3 ? pos[n2 + i] : 0.0f, pos[j], pos[n1 + j],
+                                  D == 3 ? pos[n2 + j] : 0.0f);
+        const float r = cert_sqrt(s);
+        const double dS = St - Si[i];
+        const double thr = (double)d2[i] * (1.0 - guard) - 2.0 * (dS * (1.0 + guard));
+        const double gap = thr - (double)r;
+        if (gap > 0.0) e[i] = St + gap * K;
     }
 }
 
@@ -1020,6 +1054,7 @@ QueryArgs query_args(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, 
     a.d1 = c->d1;
     a.d2 = c->d2;
     a.e = c->e;
+    a.Si = c->Si;
     a.fail = c->fail;
     a.sc = c->sc;
     a.guard = c->guard;
@@ -1142,6 +1177,21 @@ int launch_audit(nnc_ctx *c)
                        (const uint8_t *)(c->rho_step == c->t ? c->rho : nullptr), c->sc);
     hipLaunchKernelGGL(k_audit_cand, dim3(blocks < 4096 ? blocks : 4096), dim3(kB), 0, c->stream, c->frontier,
                        c->fail, c->sc);
+    return check();
+}
+
+int launch_budget(nnc_ctx *c)
+{
+    if (c->n == 0) return NNC_OK;
+    const int parity = (int)(c->t & 1);
+    const int b = blocks_for(c->n, kB);
+    const int blocks = b < 4096 ? b : 4096;
+    if (c->d == 2)
+        hipLaunchKernelGGL(k_budget<2>, dim3(blocks), dim3(kB), 0, c->stream, c->pos_cur, (int)c->n, c->nn, c->d2,
+                           c->Si, c->e, c->sc, parity, c->guard, c->K);
+    else
+        hipLaunchKernelGGL(k_budget<3>, dim3(blocks), dim3(kB), 0, c->stream, c->pos_cur, (int)c->n, c->nn, c->d2,
+                           c->Si, c->e, c->sc, parity, c->guard, c->K);
     return check();
 }
 

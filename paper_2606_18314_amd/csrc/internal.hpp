@@ -96,6 +96,7 @@ struct nnc_ctx {
     int32_t *nn, *cell, *stamp;
     float *d1, *d2;
     double *e;
+    double *Si;                   // clock at which each certificate was computed
     uint8_t *fail;
     // grid index
     nnc::Grid grid;
@@ -159,6 +160,7 @@ int launch_entropy(nnc_ctx *c, int which);
 int launch_cand_hist(nnc_ctx *c);
 int launch_audit(nnc_ctx *c);
 int launch_rho(nnc_ctx *c);
+int launch_budget(nnc_ctx *c);
 int launch_features(nnc_ctx *c, float *out);
 int launch_fill(void *p, int value, size_t count, hipStream_t s);
 

@@ -293,6 +293,7 @@ struct QueryArgs {
                                // null for a single scene, whose entropy scans hist
     float *d1, *d2;
     double *e;
+    double *Si;                // clock of each certificate (a single scene; null in a batch)
     uint8_t *fail;
     DevScalars *sc;
     double guard, K;
@@ -773,6 +774,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
     a.d1[i] = d1;
     a.d2[i] = d2;
     a.e[i] = expiry(St, d1, d2, a.guard, a.K);
+    if (a.Si) a.Si[i] = St;
     a.stamp[i] = a.t;
     const bool f = !a.init && t.nn != old;
     a.fail[i] = f ? 1 : 0;
@@ -813,6 +815,19 @@ __device__ __forceinline__ double repair_cutoff(float d1, float d2, double e, do
     return ((double)d2 + 2.0 * dS) * (1.0 + kCutSlack) + margin;
 }
 
+// The cut-off of point i: from its stored certificate clock when the scene keeps
+// one (its key may have been moved by the per-point budget), else from the key.
+__device__ __forceinline__ double point_cutoff(const QueryArgs &a, int i, double St, double margin)
+{
+    if (a.Si) {
+        const float d2 = a.d2[i];
+        if (!(d2 < kInf)) return __builtin_inf();
+        const double dS = fmax(St - a.Si[i], 0.0);
+        return ((double)d2 + 2.0 * dS) * (1.0 + kCutSlack) + margin;
+    }
+    return repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
+}
+
 // Query q of a scene (the q-th candidate, or the q-th slot when recomputing all
 // points) by the L lanes of one group; lane 0 writes the new certificate, its
 // expiry key, stamp and failure flag, and counts a failure in the histogram.
@@ -838,7 +853,7 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     }
     const int old = lane == 0 ? a.nn[i] : 0;  // fetched early, used at the end
     double T = __builtin_inf();
-    if (!a.init) T = repair_cutoff(a.d1[i], a.d2[i], a.e[i], St, a.guard, a.K, margin);
+    if (!a.init) T = point_cutoff(a, i, St, margin);
     Top2 t;
     t.init();
     const int cell = group_search<D, L, UNIT>(a, x, y, z, i, margin, T, lane, t);

@@ -45,6 +45,8 @@ def assert_state_equal(gs, sc, tag):
     assert np.array_equal(bits(host(gs["e"])), bits(sc.e)), tag
     assert np.array_equal(host(gs["cell"]), sc.cell), tag
     assert np.array_equal(host(gs["fail"]).astype(bool), sc.fail), tag
+    if "Si" in gs:
+        assert np.array_equal(bits(host(gs["Si"])), bits(sc.Si)), tag
 
 
 # --- all-pairs top-2 ---------------------------------------------------------------
@@ -100,13 +102,14 @@ def test_allpairs_cube_16k_size(nnc):
 # --- the state machine ---------------------------------------------------------------
 
 def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0, all_query="auto",
-               box=None):
+               box=None, budget=False):
     d, n = traj.d, traj.n
     frames = [dev(f) for f in traj.frames]
-    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query, box=box)
+    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query, box=box, budget=budget)
     assert ctx.grid_g == G
     sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard,
-                           lo=None if box is None else box[0], hi=None if box is None else box[1])
+                           lo=None if box is None else box[0], hi=None if box is None else box[1],
+                           rule="budget" if budget else "clock")
     ctx.init_certificates(frames[0])
     sc.init_certificates(traj.frames[0])
     assert_state_equal(ctx.state(), sc, "init")
@@ -276,6 +279,29 @@ def test_unit_box_given_explicitly_is_the_default(nnc):
 def test_invalid_domain_box_is_rejected(nnc):
     with pytest.raises(nnc.NNCError):
         nnc.NNCert(100, 2, box=((0.0, 1.0), (1.0, 1.0)))   # hi = lo on y
+
+
+@pytest.mark.parametrize("family", synth.FAMILIES)
+def test_budget_rule_cube_families(nnc, family):
+    """The per-point motion budget (NNC_BUDGET): candidates, refreshed keys, S_i and
+    every certificate against the oracle's budget rule on every step, with repairs
+    and a rebuild every fourth step."""
+    tr = synth.make_trajectory(family, 6000, 3, 30, 5e-4, 2000 + synth.FAMILIES.index(family))
+    run_parity(nnc, tr, G=12, strategy="alternate", budget=True)
+
+
+@pytest.mark.parametrize("guard", [0.0, -1.0])
+@pytest.mark.parametrize("lanes", [1, 16])
+def test_budget_rule_plane(nnc, guard, lanes):
+    run_parity(nnc, synth.plane_1k(), G=15, guard=guard, lanes=lanes, budget=True)
+    tr = synth.make_trajectory("uniform_brownian", 70000, 2, 6, 1e-3, 4545)
+    run_parity(nnc, tr, G=130, guard=guard, lanes=lanes, budget=True, strategy="alternate")
+
+
+def test_budget_rule_full_size_cube(nnc):
+    """N = 16000 at the default grid, 20 steps of repair in budget mode."""
+    tr = synth.cube_16k("uniform_brownian", steps=20)
+    run_parity(nnc, tr, G=15, budget=True)
 
 
 def test_guard_zero_literal_key(nnc):
