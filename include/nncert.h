@@ -219,6 +219,13 @@ int nnc_rho_predict(nnc_ctx *ctx);
  * struct with eps_t, S_t and the set's size.  Synchronises. */
 int nnc_frontier_entropy(nnc_ctx *ctx, int which, nnc_entropy *out);
 
+/* Spatial spread of the failed set (Definition 2's F_t) or of the last step's
+ * candidates at the current positions: its radius of gyration
+ * sqrt(mean |p_i - centroid|^2) and centroid (centroid[3] may be NULL; z = 0 in
+ * the plane), in binary64; 0 for an empty set.  The gyration descriptor of the
+ * dataset (Section 6).  Synchronises. */
+int nnc_frontier_gyration(nnc_ctx *ctx, int which, double *gyration, double *centroid);
+
 /* The six selector features of the pending step (after nnc_step, before
  * nnc_repair/nnc_rebuild); the selector predicts Section 3's best-strategy label
  * (the fastest strategy of the transition) from them, written to out (device float32 [NNC_FEATURES]):

@@ -244,6 +244,22 @@ def entropy(members: np.ndarray, cell: np.ndarray):
     return H, m, C, F
 
 
+def gyration(pos: np.ndarray, members: np.ndarray):
+    """Radius of gyration sqrt(mean |p_i - c|^2) of the member points (boolean mask or
+    indices) about their centroid c, and c (z = 0 in the plane), in binary64 by the
+    plain two-pass definition: the dataset's spatial-spread descriptor of a frontier
+    (Section 6 names it; its definition is this reading).  (0, 0) for no members."""
+    pos = _soa(pos).astype(np.float64)
+    idx = np.flatnonzero(members) if np.asarray(members).dtype == bool else np.asarray(members, np.int64)
+    cen = np.zeros(3)
+    if idx.size == 0:
+        return 0.0, cen
+    P = np.zeros((3, idx.size))
+    P[:pos.shape[0]] = pos[:, idx]
+    cen = P.mean(axis=1)
+    return float(np.sqrt(np.mean(np.sum((P - cen[:, None]) ** 2, axis=0)))), cen
+
+
 @dataclass
 class StepResult:
     eps: np.float32

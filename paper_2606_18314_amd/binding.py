@@ -43,7 +43,7 @@ EXPORTS = (
     "nnc_batch_create", "nnc_batch_destroy", "nnc_batch_offsets", "nnc_batch_init", "nnc_batch_step",
     "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
     "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
-    "nnc_sqrt_f32", "nnc_mlp_grad_static",
+    "nnc_sqrt_f32", "nnc_mlp_grad_static", "nnc_frontier_gyration",
 )
 
 POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
@@ -158,6 +158,8 @@ def load():
                                  ctypes.c_float, P]
     lib.nnc_mlp_forward.argtypes = [P, P, ctypes.c_int, P, P]
     lib.nnc_sqrt_f32.argtypes = [P, P, ctypes.c_int64, P]
+    lib.nnc_frontier_gyration.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]
     lib.nnc_strerror.argtypes = [ctypes.c_int]
     lib.nnc_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -326,6 +328,13 @@ class NNCert:
         e = Entropy()
         check(_lib.nnc_frontier_entropy(self.h, which, ctypes.byref(e)), "nnc_frontier_entropy")
         return {k: getattr(e, k) for k, _ in Entropy._fields_}
+
+    def frontier_gyration(self, which: int = NNC_FAILED):
+        """(radius of gyration, centroid (x, y, z)) of the failed set or the candidates."""
+        g = ctypes.c_double()
+        cen = (ctypes.c_double * 3)()
+        check(_lib.nnc_frontier_gyration(self.h, which, ctypes.byref(g), cen), "nnc_frontier_gyration")
+        return g.value, tuple(cen)
 
     def frontier_indices(self) -> torch.Tensor:
         """The last step's candidate list as a CUDA int32 tensor (synchronises)."""

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -69,6 +70,7 @@ size_t carve(nnc_ctx *c, char *base)
     c->ntcount = (int)((n + 4095) / 4096 + 1);
     c->tcount = k.take<int32_t>((size_t)c->ntcount);
     c->ent_part = k.take<double>(3 * nnc::kEntropyParts);
+    c->shape_part = k.take<double>(4 * nnc::kShapeParts + 4);
     c->a_nn = k.take<int32_t>(n);
     c->a_d1 = k.take<float>(n);
     c->a_d2 = k.take<float>(n);
@@ -394,6 +396,43 @@ int nnc_frontier_entropy(nnc_ctx *c, int which, nnc_entropy *out)
     out->C = h.Cres[which];
     out->count = h.F[which];
     return take_error(c, h);
+}
+
+int nnc_frontier_gyration(nnc_ctx *c, int which, double *gyration, double *centroid)
+{
+    if (!c || !gyration || (which != NNC_FAILED && which != NNC_CANDIDATES)) return NNC_E_INVAL;
+    if (!c->inited) return NNC_E_STATE;
+    std::vector<double> part(4 * nnc::kShapeParts);
+    double sums[4] = {0.0, 0.0, 0.0, 0.0}, cen[4] = {0.0, 0.0, 0.0, 0.0};
+    const size_t pbytes = part.size() * sizeof(double);
+    int rc = c->n > 0 ? nnc::launch_shape(c, which, nullptr) : NNC_OK;
+    if (rc == NNC_OK && c->n > 0) {
+        if (hipMemcpyAsync(part.data(), c->shape_part, pbytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return NNC_E_HIP;
+        for (int b = 0; b < nnc::kShapeParts; ++b)
+            for (int k = 0; k < 4; ++k) sums[k] += part[4 * b + k];
+    }
+    if (rc != NNC_OK) return rc;
+    double g = 0.0;
+    if (sums[3] > 0.0) {
+        for (int k = 0; k < 3; ++k) cen[k] = sums[k] / sums[3];
+        double *cen_dev = c->shape_part + 4 * nnc::kShapeParts;
+        if (hipMemcpyAsync(cen_dev, cen, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return NNC_E_HIP;
+        rc = nnc::launch_shape(c, which, cen_dev);
+        if (rc != NNC_OK) return rc;
+        if (hipMemcpyAsync(part.data(), c->shape_part, pbytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return NNC_E_HIP;
+        double ss = 0.0;
+        for (int b = 0; b < nnc::kShapeParts; ++b) ss += part[4 * b];
+        g = sqrt(ss / sums[3]);
+    }
+    *gyration = g;
+    if (centroid)
+        for (int k = 0; k < 3; ++k) centroid[k] = cen[k];
+    return NNC_OK;
 }
 
 int nnc_features(nnc_ctx *c, float *out)

@@ -864,6 +864,53 @@ __global__ void __launch_bounds__(kB) k_budget(const float *__restrict__ pos, in
     }
 }
 
+// Spatial spread of a frontier (the dataset's gyration descriptor): per workgroup,
+// sums over the members -- the failed points (list == nullptr: fail[i] set) or the
+// listed candidates -- of (x, y, z, 1) when cen is null, else of the squared
+// distance to the centroid cen; binary64.  part[4 * blockIdx + k] receives them.
+template <int D>
+__global__ void __launch_bounds__(kB) k_shape(const float *__restrict__ pos, int n, const uint8_t *__restrict__ fail,
+                                              const int *__restrict__ list, const int *__restrict__ count,
+                                              const double *__restrict__ cen, double *__restrict__ part)
+{
+    constexpr int NW = kB / 64;
+    __shared__ double s_v[4][NW];
+    const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
+    const int items = list ? *count : n;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = blockIdx.x * kB + (int)threadIdx.x; q < items; q += gridDim.x * kB) {
+        int i = q;
+        if (list) {
+            i = list[q];
+            if (i < 0 || i >= n) continue;
+        } else if (!fail[i]) {
+            continue;
+        }
+        const double x = pos[i], y = pos[n1 + i], z = D == 3 ? (double)pos[n2 + i] : 0.0;
+        if (!cen) {
+            v[0] += x;
+            v[1] += y;
+            v[2] += z;
+            v[3] += 1.0;
+        } else {
+            const double dx = x - cen[0], dy = y - cen[1], dz = z - cen[2];
+            v[0] += dx * dx + dy * dy + dz * dz;
+        }
+    }
+    const int w = (int)(threadIdx.x >> 6);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = wave_sum(v[k]);
+        if (lane_id() == 0) s_v[k][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int k = 0; k < NW; ++k) t += s_v[threadIdx.x][k];
+        part[4 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
 // The local failure predictor of the audit (Section 4, Table 1): point i is flagged
 // when twice its last-step motion plus its kept neighbour's exceeds the kept
 // certificate's clearance, 2 (|dp_i| + |dp_j|) > d2 - d1, all in binary32.
@@ -1177,6 +1224,19 @@ int launch_audit(nnc_ctx *c)
                        (const uint8_t *)(c->rho_step == c->t ? c->rho : nullptr), c->sc);
     hipLaunchKernelGGL(k_audit_cand, dim3(blocks < 4096 ? blocks : 4096), dim3(kB), 0, c->stream, c->frontier,
                        c->fail, c->sc);
+    return check();
+}
+
+int launch_shape(nnc_ctx *c, int which, const double *cen)
+{
+    const int *list = which == 1 ? c->frontier : nullptr;
+    const int *count = which == 1 ? &c->sc->nfront : nullptr;
+    if (c->d == 2)
+        hipLaunchKernelGGL(k_shape<2>, dim3(kShapeParts), dim3(kB), 0, c->stream, c->pos_cur, (int)c->n, c->fail, list,
+                           count, cen, c->shape_part);
+    else
+        hipLaunchKernelGGL(k_shape<3>, dim3(kShapeParts), dim3(kB), 0, c->stream, c->pos_cur, (int)c->n, c->fail, list,
+                           count, cen, c->shape_part);
     return check();
 }
 

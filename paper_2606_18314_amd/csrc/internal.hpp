@@ -13,6 +13,7 @@ namespace nnc {
 enum : unsigned { kErrNonFinite = 1u, kErrEps = 2u, kErrSpin = 4u, kErrOverflow = 8u };
 
 constexpr int kEntropyParts = 256;  // workgroups of the split entropy reduction
+constexpr int kShapeParts = 256;    // workgroups of the frontier gyration sums
 
 // Scalars that live on the device so that a step never waits for the host.
 // The clock and the displacement maximum are double-buffered by step parity:
@@ -115,6 +116,7 @@ struct nnc_ctx {
     int32_t *tcount;
     int ntcount;
     double *ent_part;             // partial sums of the split entropy reduction
+    double *shape_part;           // partial sums of the gyration (4 per workgroup), then the centroid
     // audit scratch
     int32_t *a_nn;
     float *a_d1, *a_d2;
@@ -161,6 +163,9 @@ int launch_cand_hist(nnc_ctx *c);
 int launch_audit(nnc_ctx *c);
 int launch_rho(nnc_ctx *c);
 int launch_budget(nnc_ctx *c);
+// which = 0: failed points, 1: candidates; cen: null for the first pass (sums of
+// coordinates and count), else the centroid (sum of squared distances)
+int launch_shape(nnc_ctx *c, int which, const double *cen);
 int launch_features(nnc_ctx *c, float *out);
 int launch_fill(void *p, int value, size_t count, hipStream_t s);
 

@@ -671,3 +671,21 @@ def test_budget_rule_no_miss_on_the_workload_families(family):
         na += ra.candidates.size
         nb += rb.candidates.size
     assert na < nb
+
+
+def test_gyration_closed_forms():
+    """Radius of gyration of a frontier: two points 2a apart -> a; the 2^d corners of a
+    cube of side 2a -> a sqrt(d); one point or none -> 0; invariant under translation."""
+    for d in (2, 3):
+        p = np.zeros((d, 2), np.float32)
+        p[0, 1] = 0.5
+        g, c = model.gyration(p, np.array([True, True]))
+        assert g == 0.25 and c[0] == 0.25
+        corners = np.array(list(itertools.product((0.25, 0.75), repeat=d)), np.float32).T
+        g, c = model.gyration(corners, np.ones(2 ** d, bool))
+        assert abs(g - 0.25 * math.sqrt(d)) < 1e-15 and np.allclose(c[:d], 0.5)
+        g, _ = model.gyration(corners, np.array([3]))
+        assert g == 0.0
+        assert model.gyration(corners, np.zeros(2 ** d, bool))[0] == 0.0
+        shifted = (corners + np.float32(0.125)).astype(np.float32)
+        assert model.gyration(shifted, np.ones(2 ** d, bool))[0] == model.gyration(corners, np.ones(2 ** d, bool))[0]
