@@ -54,6 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # FP32 VALU issue rate without FMA and without packed FP32:
 # 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 operations/s.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+FP32_PUBLISHED_TFLOPS = 157.3
 
 
 def parse():
@@ -63,10 +64,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling,audit")
     ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5, help="timed replays per leg (the median is reported)")
     ap.add_argument("--scaling-exps", default="16,18,20,22,24,26",
                     help="log2 N of the scaling leg's scenes")
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-tune", type=int, default=1,
+                    help="1: time the batch tuner's choices; 0: use its usual choice without timing")
     ap.add_argument("--regret-scenes", type=int, default=100)
     ap.add_argument("--regret-steps", type=int, default=110)
     ap.add_argument("--grid", default="table",
@@ -79,6 +83,18 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def progress(msg):
@@ -127,7 +143,11 @@ def batched_leg(args, nnc, synth, autotune, torch):
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     s = torch.cuda.Stream()
-    grids, lanes, table = autotune.tune_batch(frames, ns, ds, eps_steps=8, stream=s)
+    if args.batch_tune:
+        grids, lanes, table = autotune.tune_batch(frames, ns, ds, eps_steps=8, stream=s)
+    else:   # the tuner's usual choice, without its timing sweep
+        lanes, table = 16, {}
+        grids = autotune.batch_grids(frames[0], ns, ds, lanes=16, factor=1.5, cells_per_point=8)
     params, meta = selector.load_params()
     tau = float(meta.get("tau", 0.5)) if meta else 0.5
     total = sum(ns)
@@ -163,10 +183,14 @@ def batched_leg(args, nnc, synth, autotune, torch):
         ms = e0.elapsed_time(e1)
         st = b.stats()
         rebuilt = sum(x["strategy"] for x in st) / len(st)
-        progress(f"batched {name}: {ms / steps:.4f} ms/step")
+        nbytes = batched_step_bytes(ns, ds, grids, st)
+        gbs = nbytes / (ms / steps * 1e-3) / 1e9
+        progress(f"batched {name}: {ms / steps:.4f} ms/step, {gbs:.0f} GB/s algorithmic")
         res[name] = {"value": total * steps / (ms / 1e3), "ms_per_step": ms / steps,
                      "last_step_rebuild_fraction": rebuilt,
-                     "errors": sum(1 for x in st if x["err"] != 0)}
+                     "errors": sum(1 for x in st if x["err"] != 0),
+                     "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes}}
         del g
         b.close()
     # the same scenes, one context per scene, advanced one after another (graph-captured)
@@ -195,10 +219,50 @@ def batched_leg(args, nnc, synth, autotune, torch):
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    res["per_scene_loop"] = {"value": total * per / (ms / 1e3), "ms_per_step": ms / per, "steps": per}
+    res["per_scene_loop"] = {"value": total * per / (ms / 1e3), "ms_per_step": ms / per, "steps": per,
+                             "form": "one context per scene, one stream, one graph"}
     del g
     for c in ctxs:
         c.close()
+    # the fairer per-scene baseline: the contexts spread over several streams that run as
+    # parallel branches of one graph (as the headline runs its five scenes)
+    nstreams = 8
+    bstreams = [torch.cuda.Stream() for _ in range(nstreams)]
+    ctxs = []
+    for k, tr in enumerate(trajs):
+        st_k = bstreams[k % nstreams]
+        with torch.cuda.stream(st_k):
+            c = nnc.NNCert(ns[k], ds[k], grid_g=grids[k], stream=st_k.cuda_stream, lanes=lanes)
+            c.init_certificates(tr_frames[k][0])
+            c.step(tr_frames[k][1], 5e-4)
+            c.repair()
+            ctxs.append(c)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for st_k in bstreams:
+            st_k.wait_stream(s)
+        for t in range(2, per + 2):
+            for k, c in enumerate(ctxs):
+                with torch.cuda.stream(bstreams[k % nstreams]):
+                    c.step(tr_frames[k][t], 5e-4)
+                    c.repair()
+        for st_k in bstreams:
+            s.wait_stream(st_k)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(s)
+    with torch.cuda.stream(s):
+        g.replay()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    res["per_scene_branches"] = {"value": total * per / (ms / 1e3), "ms_per_step": ms / per, "steps": per,
+                                 "form": f"one context per scene on {nstreams} streams, parallel branches of one graph"}
+    del g
+    for c in ctxs:
+        c.close()
+    res["speedup_batched_repair_over_branches"] = res["repair"]["value"] / res["per_scene_branches"]["value"]
     res["speedup_batched_repair_over_loop"] = res["repair"]["value"] / res["per_scene_loop"]["value"]
     if "learned" in res:
         res["speedup_learned_over_loop"] = res["learned"]["value"] / res["per_scene_loop"]["value"]
@@ -217,6 +281,23 @@ def batched_leg(args, nnc, synth, autotune, torch):
             "training": meta,
         }
     return res
+
+
+def batched_step_bytes(ns, ds, grids, stats):
+    """Algorithmic bytes of one batched step from the last step's per-scene counts:
+    ingest (new coordinates, rank, the slot record read and rewritten, cell), filter
+    (key, fail flag; candidate list), queries (each query's coordinates and list entry,
+    its certificate written; every slot record of the scene read once; the cell-start
+    table), and for a rebuilt scene its grid build (counts, scan, scatter)."""
+    tot = 0
+    for n, d, G, st in zip(ns, ds, grids, stats):
+        cells = G ** d
+        q = n if st["strategy"] == 1 else st["n_cand"]
+        tot += n * (4 * d + 4 + 16 + 16 + 4) + n * 9 + 4 * st["n_cand"]
+        tot += q * (4 * d + 4 + 25) + 16 * n + 4 * (cells + 1)
+        if st["strategy"] == 1:
+            tot += 12 * cells + n * (8 * d + 12)
+    return tot
 
 
 def sweep_leg(args, nnc, synth, torch):
@@ -337,6 +418,48 @@ def sweep_leg(args, nnc, synth, torch):
         rows.append({"target_fraction": f, "mode": "forced", "count": k, "forced_localized_ms": out["localized"],
                      "forced_diffuse_ms": out["diffuse"]})
         del snap
+    # the per-point motion budget: the candidate set now depends on where the points
+    # moved (stationary points need twice the clearance of moving ones), so localized
+    # and diffuse motion of the same size give different frontiers
+    with torch.cuda.stream(s):
+        bctx = nnc.NNCert(n, d, grid_g=G, stream=s.cuda_stream, lanes=lanes, budget=True)
+        bctx.init_certificates(P0)
+    torch.cuda.synchronize()
+    bfresh = bctx.snapshot()
+    budget_rows = []
+    gq = torch.Generator(device="cuda")
+    gq.manual_seed(3500)
+    qidx = torch.sort(torch.randperm(n, generator=gq, device="cuda")[:4096]).values.to(torch.int32)
+    for f in (0.001, 0.01, 0.05, 0.2, 0.5):
+        k = max(1, int(math.ceil(f * n)))
+        eps = float(c[k - 1]) / 4.0
+        for mode in ("localized", "diffuse"):
+            P1 = torch.from_numpy(synth.sweep_motion(p0, eps, mode)).cuda()
+            with torch.cuda.stream(s):
+                bctx.restore(bfresh)
+                bctx.step(P1, -1.0)
+            bsnap = bctx.snapshot()
+            hc = bctx.frontier_entropy(nnc.NNC_CANDIDATES)
+            best = math.inf
+            for _ in range(reps):
+                e0, e1 = ev(), ev()
+                with torch.cuda.stream(s):
+                    bctx.restore(bsnap)
+                    e0.record(s)
+                    bctx.repair()
+                    e1.record(s)
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            hf = bctx.frontier_entropy(nnc.NNC_FAILED)
+            nn_s, _, _ = nnc.allpairs_top2(P1, qidx)
+            bad = int((bctx.state()["nn"][qidx.long()] != nn_s).sum())
+            budget_rows.append({"target_fraction": f, "mode": mode, "eps": eps, "candidates": hc["count"],
+                                "candidate_fraction": hc["count"] / n, "H_candidates": hc["H"],
+                                "m_candidates": hc["m"], "failures": hf["count"], "H_fail": hf["H"],
+                                "repair_ms": best, "sampled_missed": bad})
+            del bsnap
+    del bfresh
+    bctx.close()
     # HBM roofline of the rebuild's all-point query at this size
     reb = [r for r in rows if r.get("mode") == "diffuse"]
     q_us = sum(r["rebuild_query_us"] for r in reb) / len(reb)
@@ -346,6 +469,7 @@ def sweep_leg(args, nnc, synth, torch):
     rbytes = rep50["candidates"] * (4 * d + 4 + 25) + n * (4 * d + 4) + 4 * (rep50["C"] + 1)
     ctx.close()
     return {"n": n, "d": d, "G": G, "lanes": lanes, "lanes_table_ms": lanes_table, "rows": rows,
+            "budget_rows": budget_rows,
             "roofline_rebuild_query": {"bound": "hbm", "achieved": qbytes / (q_us * 1e-6) / 1e9,
                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": qbytes / (q_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
@@ -591,6 +715,7 @@ def main():
     # kernel timing, certification ------------------------------------------------------
     kernel_avg = {}
     audits = {}
+    end_hash = {}
     for strategy in ("repair", "rebuild"):
         if strategy not in legs_req:
             continue
@@ -625,10 +750,20 @@ def main():
             def replay():
                 with torch.cuda.stream(stream):
                     g.replay()
-            graph_ms = timed(replay)
+            # several replays of the same K steps from the same state; the median is reported
+            runs = []
+            for r in range(args.repeats):
+                if r:
+                    for f in fams:
+                        ctxs[f][0].restore(snaps[f])
+                    torch.cuda.synchronize()
+                runs.append(timed(replay))
+            graph_ms = sorted(runs)[len(runs) // 2]
             end_audit = {f: ctxs[f][0].oracle_verify() for f in fams}
-            progress(f"{strategy} {mode}: {graph_ms / K:.4f} ms/step")
+            end_hash[(strategy, mode)] = {f: end_audit[f]["nn_hash"] for f in fams}
+            progress(f"{strategy} {mode}: {graph_ms / K:.4f} ms/step (median of {len(runs)})")
             leg[mode] = {"value": pts_per_step * K / (graph_ms / 1e3), "ms_per_step": graph_ms / K,
+                         "replay_ms": [round(v, 4) for v in runs],
                          "eager_value": pts_per_step * K / (eager_ms / 1e3), "eager_ms_per_step": eager_ms / K,
                          "end_state_missed": sum(a["n_missed"] for a in end_audit.values()),
                          "end_state_value_mismatch": sum(a["n_value_mismatch"] for a in end_audit.values())}
@@ -660,6 +795,7 @@ def main():
                         ctxs[f][0].restore(snaps[f])
                     tot = {"steps": 0, "n_missed": 0, "n_value_mismatch": 0, "n_detect": 0, "n_true_fail": 0,
                            "H_fail_sum": 0.0, "H_cand_sum": 0.0, "C_sum": 0}
+                    last_hash = {}
                     for t in range(W + 1, T + 1):
                         for f in fams:
                             c, st = ctxs[f]
@@ -678,13 +814,17 @@ def main():
                             tot["H_fail_sum"] += hf["H"]
                             tot["H_cand_sum"] += hc["H"]
                             tot["C_sum"] += hf["C"]
+                            last_hash[f] = a["nn_hash"]
                     cert = {"scene_steps": tot["steps"], "n_missed": tot["n_missed"],
                             "n_value_mismatch": tot["n_value_mismatch"],
                             "candidate_fraction": tot["n_detect"] / (tot["steps"] * N),
                             "failure_fraction": tot["n_true_fail"] / (tot["steps"] * N),
                             "mean_H_fail": tot["H_fail_sum"] / tot["steps"],
                             "mean_H_candidates": tot["H_cand_sum"] / tot["steps"],
-                            "mean_occupied_cells": tot["C_sum"] / tot["steps"]}
+                            "mean_occupied_cells": tot["C_sum"] / tot["steps"],
+                            # the audited run and the timed graph replays end in the same state
+                            "end_hash_equals_timed_runs": all(end_hash[(strategy, m)] == last_hash
+                                                              for m in ("streams", "serial"))}
                 progress(f"{strategy} certification done")
                 audits[strategy] = cert
                 leg["certification"] = cert
@@ -713,6 +853,7 @@ def main():
         ms = e0.elapsed_time(e1)
         launch_us = ms * 1e3 / (ksteps * len(fams))
         ops = (3 * D) * N * (N - 1)           # 3d-1 distance operations + 1 comparison per pair
+        dist_ops = (3 * D - 1) * N * (N - 1)
         progress(f"allpairs: {ms / ksteps:.4f} ms/step")
         legs["allpairs"] = {"value": pts_per_step * ksteps / (ms / 1e3), "ms_per_step": ms / ksteps,
                             "steps": ksteps, "pairs_per_s": N * (N - 1) * ksteps * len(fams) / (ms / 1e3),
@@ -720,7 +861,12 @@ def main():
                             "roofline": {"bound": "alu", "achieved": ops / (launch_us * 1e-6) / 1e12,
                                          "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
                                          "frac": ops / (launch_us * 1e-6) / 1e12 / VALU_PEAK_TOPS,
-                                         "traffic": None}}
+                                         "traffic": None,
+                                         # the same work against the published FP32 vector peak (packed
+                                         # FMA counted as four operations), distance operations only
+                                         "published_peak": FP32_PUBLISHED_TFLOPS,
+                                         "frac_of_published": dist_ops / (launch_us * 1e-6) / 1e12
+                                         / FP32_PUBLISHED_TFLOPS}}
 
     # ---- frontier-fraction sweep at N = 2^20 -----------------------------------------------
     if "sweep" in legs_req:
@@ -773,8 +919,8 @@ def main():
 
     if "repair" in legs and audits.get("repair"):
         a = audits["repair"]
-        out["certified"] = (a["n_missed"] == 0 and a["n_value_mismatch"] == 0 and
-                            all(legs["repair"][m]["end_state_missed"] == 0 for m in ("streams", "serial")))
+        out["certified"] = (a["n_missed"] == 0 and a["n_value_mismatch"] == 0 and a["end_hash_equals_timed_runs"]
+                            and all(legs["repair"][m]["end_state_missed"] == 0 for m in ("streams", "serial")))
 
     # ---- counter calibration copy ----------------------------------------------------------
     if args.copy_mib:
@@ -790,31 +936,40 @@ def main():
     # ---- CPU oracle baseline -------------------------------------------------------------
     if not args.no_cpu_baseline:
         from oracle import model
-        done = 0
-        spent = 0.0
-        per_fam_steps = {}
-        scenes = {}
-        for f in fams:
-            sc = model.OracleScene(d=D, n=N, G=grids[f])
-            sc.init_certificates(trajs[f].frames[0])
-            scenes[f] = sc
-            per_fam_steps[f] = 0
-        t = 1
-        while spent < args.cpu_seconds and t <= T:
-            for f in fams:     # the same step of every family, round robin
-                t0 = time.perf_counter()
-                scenes[f].step(trajs[f].frames[t])
-                scenes[f].repair()
-                spent += time.perf_counter() - t0
-                done += 1
-                per_fam_steps[f] = t
-            t += 1
-        progress(f"cpu baseline: {done} scene-steps in {spent:.1f} s")
-        out["cpu_baseline"] = {"value": done * N / spent, "unit": "point-steps/s", "cores": model.threads(),
-                               "kind": "oracle",
+
+        def oracle_run(seconds):
+            done, spent, last = 0, 0.0, 0
+            scenes = {}
+            for f in fams:
+                sc = model.OracleScene(d=D, n=N, G=grids[f])
+                sc.init_certificates(trajs[f].frames[0])
+                scenes[f] = sc
+            t = 1
+            while spent < seconds and t <= T:
+                for f in fams:     # the same step of every family, round robin
+                    t0 = time.perf_counter()
+                    scenes[f].step(trajs[f].frames[t])
+                    scenes[f].repair()
+                    spent += time.perf_counter() - t0
+                    done += 1
+                last = t
+                t += 1
+            return done, spent, last
+
+        all_cores = model.threads()
+        done, spent, last = oracle_run(args.cpu_seconds)
+        progress(f"cpu baseline ({all_cores} threads): {done} scene-steps in {spent:.1f} s")
+        model.set_threads(1)
+        done1, spent1, last1 = oracle_run(args.cpu_seconds / 3)
+        model.set_threads(all_cores)
+        progress(f"cpu baseline (1 thread): {done1} scene-steps in {spent1:.1f} s")
+        out["cpu_baseline"] = {"value": done * N / spent, "unit": "point-steps/s", "cores": all_cores,
+                               "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+                               "single_thread_value": done1 * N / spent1,
                                "sample": f"oracle step + repair (brute-force certificates of the candidates) of the "
-                                         f"first {min(per_fam_steps.values())} steps of each of the five "
-                                         f"N=16000 five-family scenes, {spent:.1f} s of CPU time"}
+                                         f"first {last} steps of each of the five N=16000 five-family scenes, "
+                                         f"{spent:.1f} s of CPU time on {all_cores} threads; single thread: first "
+                                         f"{last1} steps, {spent1:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

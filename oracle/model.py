@@ -46,10 +46,23 @@ most 4 per unit of clock: r grows by 2 and d2 - 2 D falls by 2); otherwise
 the point is a candidate.  With the guard g: the test uses
 thr = d2 (1 - g) - 2 (D (1 + g)), gap = thr - r, kept iff gap > 0, new key
 S_t + gap * K; all in binary64 in that order.
+
+Before that test the budget rule applies the block-local half of the budget:
+every step, the cells a moving point leaves and enters are stamped with the step
+number (last_move).  An expired point i whose 3^d block of cells (around its
+current cell) holds no stamp later than the step of i's certificate has not moved,
+nor has any point that was inside the block; a point outside the block is at least
+B - fuzz from i (B: distance from p_i to the outside of the block; fuzz: the cell
+boundaries' rounding allowance) and has moved at most D since, so if
+(d2 + D)(1 + 2^-20) + fuzz < B no point can have come within d2 of i: the
+certificate is still exact, the point is not a candidate and its key is left as
+it is (it is tested again next step).  Motion confined to one region therefore
+only makes candidates of points near that region.
 """
 from __future__ import annotations
 
 import ctypes
+import itertools
 import math
 import os
 import subprocess
@@ -95,9 +108,15 @@ def lib():
         _lib.orc_pair_sqdist64.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, i64p,
                                            ctypes.c_int64, f64p]
         _lib.orc_threads.restype = ctypes.c_int
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib.orc_pair_sqdist32.argtypes = [f32p, ctypes.c_int64, ctypes.c_int, i64p, i64p,
                                            ctypes.c_int64, f32p]
     return _lib
+
+
+def set_threads(k: int) -> None:
+    """Thread count of the C part's parallel loops from now on."""
+    lib().orc_set_threads(int(k))
 
 
 def threads() -> int:
@@ -286,6 +305,9 @@ class OracleScene:
     fail: np.ndarray = None
     S: float = 0.0
     Si: np.ndarray = None             # clock at which each certificate was computed
+    stamp: np.ndarray = None          # step at which each certificate was computed
+    last_move: np.ndarray = None      # per cell: last step a moving point left or entered it
+    t: int = 0
     pending: StepResult = None
     last_eps: np.float32 = field(default_factory=lambda: np.float32(0))
 
@@ -297,6 +319,7 @@ class OracleScene:
         self.d2[idx] = d2
         self.e[idx] = expiry_key(self.S, d1, d2, self.guard)
         self.Si[idx] = self.S
+        self.stamp[idx] = self.t
         self.fail[:] = False
         self.fail[idx] = nn != old
 
@@ -308,6 +331,9 @@ class OracleScene:
         self.d2 = np.full(n, np.inf, np.float32)
         self.e = np.full(n, np.inf, np.float64)
         self.Si = np.zeros(n, np.float64)
+        self.stamp = np.zeros(n, np.int64)
+        self.last_move = np.zeros(self.G ** self.d, np.int64)
+        self.t = 0
         self.fail = np.zeros(n, bool)
         self.S = 0.0
         self.cell = cells(self.pos, self.G, self.lo, self.hi)
@@ -318,7 +344,12 @@ class OracleScene:
     def step(self, pos_new: np.ndarray) -> StepResult:
         pos_new = _soa(pos_new)
         eps = max_step(self.pos, pos_new)
+        self.t += 1
+        old_cell = self.cell
         self.cell = cells(pos_new, self.G, self.lo, self.hi)  # every cell current (Algorithm 1)
+        moved = np.any(pos_new != self.pos, axis=0)
+        self.last_move[old_cell[moved]] = self.t
+        self.last_move[self.cell[moved]] = self.t
         self.pos_prev = self.pos
         self.pos = pos_new.copy()
         self.S_prev = self.S
@@ -342,6 +373,9 @@ class OracleScene:
         the others, the candidates."""
         if expired.size == 0:
             return expired
+        expired = expired[~self._block_still(expired)]
+        if expired.size == 0:
+            return expired
         g = self.guard
         j = self.nn[expired].astype(np.int64)
         r = np.sqrt(pair_sqdist32(self.pos, expired, j))                 # binary32
@@ -352,6 +386,42 @@ class OracleScene:
         K = np.float64(1.0) / (np.float64(4.0) + np.float64(4.0) * np.float64(g))
         self.e[expired[keep]] = np.float64(self.S) + gap[keep] * K
         return expired[~keep]
+
+    def _block_still(self, idx: np.ndarray) -> np.ndarray:
+        """The block-local test (module docstring) of the points idx: True where no
+        cell of the point's 3^d block was stamped after its certificate and no point
+        from outside the block can have come within d2."""
+        d, G = self.d, self.G
+        gid = self.cell[idx].astype(np.int64)
+        gc = []
+        for _ in range(d):                          # per-axis cell coordinates, x first
+            gc.append(gid % G)
+            gid = gid // G
+        quiet = np.ones(idx.size, bool)
+        for offs in itertools.product((-1, 0, 1), repeat=d):
+            nb = np.zeros(idx.size, np.int64)
+            inside = np.ones(idx.size, bool)
+            for k in range(d - 1, -1, -1):
+                gk = gc[k] + offs[k]
+                inside &= (gk >= 0) & (gk < G)
+                nb = nb * G + np.clip(gk, 0, G - 1)
+            quiet &= ~inside | (self.last_move[nb] <= self.stamp[idx])
+        # distance from p_i to the outside of its block (sides at the grid edge open)
+        lo = np.zeros(3) if self.lo is None else np.asarray(self.lo, np.float32).astype(np.float64)
+        hi = np.ones(3) if self.hi is None else np.asarray(self.hi, np.float32).astype(np.float64)
+        B = np.full(idx.size, np.inf)
+        for k in range(d):
+            w = (hi[k] - lo[k]) / np.float64(G)
+            x = self.pos[k, idx].astype(np.float64)
+            low_side = gc[k] - 1 > 0
+            B = np.where(low_side, np.minimum(B, x - (lo[k] + (gc[k] - 1).astype(np.float64) * w)), B)
+            high_side = gc[k] + 1 < G - 1
+            B = np.where(high_side, np.minimum(B, (lo[k] + (gc[k] + 2).astype(np.float64) * w) - x), B)
+        mag = 1.0 if self.lo is None else max(1.0, *np.abs(lo[:d]), *np.abs(hi[:d]))
+        fuzz = 2.0 ** -20 * mag
+        D = np.float64(self.S) - self.Si[idx]
+        need = (self.d2[idx].astype(np.float64) + D) * (1.0 + 2.0 ** -20) + fuzz
+        return quiet & (need < B)
 
     def rho_flags(self) -> np.ndarray:
         """The local predictor the paper reports beside the safety rule (Section 4,

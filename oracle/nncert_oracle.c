@@ -42,6 +42,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Set the thread count of the parallel loops (k < 1: leave it unchanged). */
+void orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 static float sqdist32(const float *pos, int64_t n, int d, int64_t i, int64_t j)
 {
     float dx = pos[j] - pos[i];

@@ -689,3 +689,74 @@ def test_gyration_closed_forms():
         assert model.gyration(corners, np.zeros(2 ** d, bool))[0] == 0.0
         shifted = (corners + np.float32(0.125)).astype(np.float32)
         assert model.gyration(shifted, np.ones(2 ** d, bool))[0] == model.gyration(corners, np.ones(2 ** d, bool))[0]
+
+
+def _block_scene(k_from, k_to, q_move=0.0):
+    """Unit square, G = 4 (cells of 1/4): i = (0.625, 0.625) with j at distance 1/64 and
+    m at 1/32 (all in cell (2, 2), whose block spans cells 1..3 on each axis: the
+    distance from i to the block's outside is 0.375, the high sides being open); k
+    moves on the line y = 0.625 from x = k_from to k_to; q, inside i's block at
+    (0.875, 0.375) (cell (3, 1)), moves by q_move along y.  Values are dyadic."""
+    p0 = np.array([[0.625, 0.625 + 1 / 64, 0.625, k_from, 0.875],
+                   [0.625, 0.625, 0.625 + 1 / 32, 0.625, 0.375]])
+    p1 = p0.copy()
+    p1[0, 3] = k_to
+    p1[1, 4] += q_move
+    return p0.astype(np.float32), p1.astype(np.float32)
+
+
+def test_budget_block_rule_constructions():
+    """The block-local half of the budget: a quiet block with no reachable outsider
+    keeps i's certificate although the clock rule flags it; a jump from outside the
+    block that could reach within d2 makes i a candidate (and the failure is caught);
+    a mover inside the block hands i over to the distance test."""
+    cases = [  # (k_from, k_to, q_move, budget candidate, clock candidate, nn changes)
+        (0.09375, 0.15625, 0.0, False, True, False),    # k moves 1/16 inside cell 0: quiet block
+        (0.09375, 0.6171875, 0.0, True, True, True),    # k jumps next to i: 0.523 > B - d2
+        (0.09375, 0.15625, 1 / 64, True, True, False),  # q moves inside the block, eps = 1/16
+    ]
+    for k_from, k_to, q_move, want_budget, want_clock, changes in cases:
+        p0, p1 = _block_scene(k_from, k_to, q_move)
+        for rule, want in (("budget", want_budget), ("clock", want_clock)):
+            sc = model.OracleScene(d=2, n=5, G=4, guard=0.0, rule=rule)
+            sc.init_certificates(p0)
+            assert sc.nn[0] == 1 and float(sc.d2[0]) == 1 / 32
+            res = sc.step(p1)
+            assert (0 in set(res.candidates.tolist())) == want, (k_from, k_to, q_move, rule)
+            sc.repair()
+            assert bool(sc.fail[0]) == changes
+            assert sc.audit().size == 0
+
+
+def test_budget_rule_localized_motion_localizes_the_candidates():
+    """Motion confined to one disc: under the budget rule every candidate lies within a
+    block of a cell some moving point left or entered, the candidates are a strict
+    subset of the clock rule's, and nothing is missed; motion of the same number of
+    points spread uniformly makes many more candidates."""
+    g = np.random.default_rng(77)
+    n, G = 20000, 70
+    p0 = g.random((2, n))
+    centre = np.array([[0.3], [0.6]])
+    inside = np.flatnonzero(np.hypot(*(p0 - centre)) < 0.08)
+    spread = g.choice(n, inside.size, replace=False)
+    counts = {}
+    for name, movers in (("localized", inside), ("diffuse", spread)):
+        p1 = p0.copy()
+        step = g.standard_normal((2, movers.size))
+        p1[:, movers] += 2e-4 * step / np.linalg.norm(step, axis=0)
+        a = model.OracleScene(d=2, n=n, G=G, rule="budget")
+        b = model.OracleScene(d=2, n=n, G=G)
+        a.init_certificates(p0.astype(np.float32))
+        b.init_certificates(p0.astype(np.float32))
+        ca = set(a.step(p1.astype(np.float32)).candidates.tolist())
+        cb = set(b.step(p1.astype(np.float32)).candidates.tolist())
+        assert ca < cb
+        stamped = np.flatnonzero(a.last_move == 1)
+        sx, sy = stamped % G, stamped // G
+        for i in ca:
+            gx, gy = a.cell[i] % G, a.cell[i] // G
+            assert np.any((np.abs(sx - gx) <= 1) & (np.abs(sy - gy) <= 1)), i
+        a.repair()
+        assert a.audit().size == 0
+        counts[name] = len(ca)
+    assert counts["diffuse"] > 3 * counts["localized"]
