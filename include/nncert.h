@@ -69,12 +69,19 @@ extern "C" {
 #define NNC_QUERY_POINTWISE 8u
 /* Per-point motion budget (the Limitations section's tighter safe set): each step,
  * a point whose key S_i + c_i/4 has expired is re-tested against its kept
- * certificate (nn = j, d2, made at clock S_i).  Every point has moved at most
- * D = S_t - S_i since, so j is still the strict nearest neighbour while its current
- * distance r (binary32 formula) is below d2 - 2 D; then the certificate is kept and
- * its key moves to S_t + gap * K, gap = (d2 (1 - g) - 2 (D (1 + g))) - r in
- * binary64 (g the guard, K = 1/(4 + 4g)); otherwise the point is a candidate.
- * The candidates are a subset of the clock rule's; no failure is missed. */
+ * certificate (nn = j, d2, made at clock S_i and step t_i), D = S_t - S_i:
+ *  (1) block-local: if no cell of its 3^d block was left or entered by a moving
+ *      point after step t_i and (d2 + D)(1 + 2^-20) + fuzz < B (B: distance to the
+ *      outside of the block, fuzz the cell-boundary allowance 2^-20 max(1, |lo|, |hi|)),
+ *      no point can have come within d2: kept, key = the next binary64 value
+ *      above S_t (tested again at the next step in which anything moves);
+ *  (2) distance: j is still the strict nearest neighbour while its current
+ *      distance r (binary32 formula) is below d2 - 2 D; then the certificate is
+ *      kept and its key moves to S_t + gap * K, gap = (d2 (1 - g) - 2 (D (1 + g))) - r
+ *      in binary64 (g the guard, K = 1/(4 + 4g));
+ * otherwise the point is a candidate.  The candidates are a subset of the clock
+ * rule's, and motion confined to one region makes candidates only near it; no
+ * failure is missed.  Costs a per-cell step stamp in the ingest. */
 #define NNC_BUDGET          16u
 
 /* nnc_frontier_entropy: which set */

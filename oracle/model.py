@@ -55,9 +55,10 @@ nor has any point that was inside the block; a point outside the block is at lea
 B - fuzz from i (B: distance from p_i to the outside of the block; fuzz: the cell
 boundaries' rounding allowance) and has moved at most D since, so if
 (d2 + D)(1 + 2^-20) + fuzz < B no point can have come within d2 of i: the
-certificate is still exact, the point is not a candidate and its key is left as
-it is (it is tested again next step).  Motion confined to one region therefore
-only makes candidates of points near that region.
+certificate is still exact, the point is not a candidate and its key becomes
+the smallest binary64 value above S_t (it is tested again at the next step in
+which anything moves).  Motion confined to one region therefore only makes
+candidates of points near that region.
 """
 from __future__ import annotations
 
@@ -373,7 +374,9 @@ class OracleScene:
         the others, the candidates."""
         if expired.size == 0:
             return expired
-        expired = expired[~self._block_still(expired)]
+        still = self._block_still(expired)
+        self.e[expired[still]] = np.nextafter(np.float64(self.S), np.inf)
+        expired = expired[~still]
         if expired.size == 0:
             return expired
         g = self.guard

@@ -57,6 +57,7 @@ size_t carve(nnc_ctx *c, char *base)
     // histograms padded to whole int4 groups (the entropy scans them four cells at a time)
     c->hist_fail = k.take<int32_t>((nc + 3) / 4 * 4);
     c->hist_cand = k.take<int32_t>((nc + 3) / 4 * 4);
+    c->last_move = k.take<int32_t>(nc);
     c->state_bytes = k.off;
     c->sync = k.take<nnc::DevSync>(1);
     c->grid.cursor = k.take<int>(nc);

@@ -171,10 +171,11 @@ template <int D>
 __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, const float *__restrict__ pnew,
                                                int n, int G, Box box, int *__restrict__ cell, int *__restrict__ counts,
                                                const int *__restrict__ rank, float4 *__restrict__ slots,
-                                               DevScalars *sc, int parity)
+                                               DevScalars *sc, int parity, int *__restrict__ last_move, int t)
 {
     // grid-stride over at most kIngestBlocks workgroups, each adding its maximum and
-    // cell-count change into one of the spread slots
+    // cell-count change into one of the spread slots; with last_move (the per-point
+    // budget), the cells a moving point leaves and enters are stamped with step t
     float s = 0.0f;
     int dC = 0;
     const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
@@ -190,6 +191,10 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
                 cell[i] = c;
                 dC -= atomicSub(&counts[old], 1) == 1;
                 dC += atomicAdd(&counts[c], 1) == 0;
+            }
+            if (last_move && (x1 != x0 || y1 != y0 || z1 != z0)) {
+                last_move[old] = t;  // every writer stores the same value
+                last_move[c] = t;
             }
         } else {
             atomicOr(&sc->err, kErrNonFinite);
@@ -831,19 +836,28 @@ __global__ void __launch_bounds__(kB) k_audit(int n, const int *__restrict__ nn,
 }
 
 // Per-point motion budget (the Limitations section's tighter safe set; Theorem 2
-// applied to the kept certificate).  Every point has moved at most
-// D = S_t - S_i since point i's certificate (nn = j, d2) was made, so every other
-// point is at least d2 - 2 D from i now, while j is at its current distance r.
-// For each point whose key has expired: if r < d2 - 2 D (with the guard g:
-// gap = (d2 (1 - g) - 2 (D (1 + g))) - r > 0) the certificate is kept and its key
-// moves to S_t + gap * K -- the gap closes by at most 4 per unit of clock --
+// applied to the kept certificate), for each point whose key has expired:
+//  1. block-local: if no cell of the point's 3^d block was stamped (a moving point
+//     left or entered it) after the point's certificate, neither the point nor any
+//     point that was inside the block has moved; a point from outside is at least
+//     B - fuzz away (B: distance to the outside of the block) and has moved at most
+//     D = S_t - S_i, so if (d2 + D)(1 + 2^-20) + fuzz < B none can have come within
+//     d2: the certificate is exact, the point is no candidate, and its key becomes
+//     the next binary64 value above S_t (tested again once anything moves);
+//  2. distance: every point has moved at most D since the certificate (nn = j, d2),
+//     so every other point is at least d2 - 2 D from i now, while j is at its
+//     current distance r; if r < d2 - 2 D (with the guard g:
+//     gap = (d2 (1 - g) - 2 (D (1 + g))) - r > 0) the certificate is kept and its key
+//     moves to S_t + gap * K -- the gap closes by at most 4 per unit of clock;
 // otherwise the point stays expired and the filter makes it a candidate.  S_t is
 // computed as the filter will (from the same ingest maxima), read-only.
 template <int D>
 __global__ void __launch_bounds__(kB) k_budget(const float *__restrict__ pos, int n, const int *__restrict__ nn,
                                                const float *__restrict__ d2, const double *__restrict__ Si,
                                                double *__restrict__ e, const DevScalars *__restrict__ sc, int parity,
-                                               double guard, double K)
+                                               double guard, double K, const int *__restrict__ cell,
+                                               const int *__restrict__ stamp, const int *__restrict__ last_move,
+                                               int G, Box box, double fuzz)
 {
     const int lane = (int)lane_id();
     const float m = fmaxf(wave_max(__uint_as_float(sc->dmax_part[parity][lane])), __uint_as_float(sc->dmax[parity]));
@@ -854,10 +868,46 @@ __global__ void __launch_bounds__(kB) k_budget(const float *__restrict__ pos, in
         if (!(St >= ei)) continue;
         const int j = nn[i];
         if (j < 0 || j >= n) continue;
+        const double dS = St - Si[i];
+        {
+            const int id = cell[i], si = stamp[i];
+            const int gc[3] = {id % G, (id / G) % G, D == 3 ? id / (G * G) : 0};
+            bool quiet = true;
+            for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0) && quiet; ++oz) {
+                const int z = gc[2] + oz;
+                if (z < 0 || z >= G) continue;
+                for (int oy = -1; oy <= 1 && quiet; ++oy) {
+                    const int y = gc[1] + oy;
+                    if (y < 0 || y >= G) continue;
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int x = gc[0] + ox;
+                        if (x < 0 || x >= G) continue;
+                        if (last_move[x + G * (y + G * z)] > si) {
+                            quiet = false;
+                            break;
+                        }
+                    }
+                }
+            }
+            if (quiet) {
+                double B = __builtin_inf();
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double w = box.w[k], lo = (double)box.lo[k], x = (double)pos[(size_t)k * n1 + i];
+                    if (gc[k] - 1 > 0) B = fmin(B, x - (lo + (double)(gc[k] - 1) * w));
+                    if (gc[k] + 1 < G - 1) B = fmin(B, (lo + (double)(gc[k] + 2) * w) - x);
+                }
+                const double need = ((double)d2[i] + dS) * (1.0 + 0x1p-20) + fuzz;
+                if (need < B) {
+                    // the next binary64 value above the clock (S_t >= 0): tested again once anything moves
+                    e[i] = __longlong_as_double(__double_as_longlong(St) + 1);
+                    continue;
+                }
+            }
+        }
         const float s = sqdist<D>(pos[i], pos[n1 + i], D == 3 ? pos[n2 + i] : 0.0f, pos[j], pos[n1 + j],
                                   D == 3 ? pos[n2 + j] : 0.0f);
         const float r = cert_sqrt(s);
-        const double dS = St - Si[i];
         const double thr = (double)d2[i] * (1.0 - guard) - 2.0 * (dS * (1.0 + guard));
         const double gap = thr - (double)r;
         if (gap > 0.0) e[i] = St + gap * K;
@@ -999,12 +1049,13 @@ int launch_ingest(nnc_ctx *c, const float *pold, const float *pnew)
     if (c->n == 0) return NNC_OK;
     const int parity = (int)(c->t & 1);
     const int blocks = blocks_for(c->n, kB) < kIngestBlocks ? blocks_for(c->n, kB) : kIngestBlocks;
+    int *lm = (c->flags & NNC_BUDGET) ? c->last_move : nullptr;
     if (c->d == 2)
         hipLaunchKernelGGL(k_ingest<2>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->box, c->cell,
-                           c->grid.counts, c->grid.rank, c->grid.slots, c->sc, parity);
+                           c->grid.counts, c->grid.rank, c->grid.slots, c->sc, parity, lm, (int)c->t);
     else
         hipLaunchKernelGGL(k_ingest<3>, dim3(blocks), dim3(kB), 0, c->stream, pold, pnew, (int)c->n, c->G, c->box, c->cell,
-                           c->grid.counts, c->grid.rank, c->grid.slots, c->sc, parity);
+                           c->grid.counts, c->grid.rank, c->grid.slots, c->sc, parity, lm, (int)c->t);
     return check();
 }
 
@@ -1248,10 +1299,12 @@ int launch_budget(nnc_ctx *c)
     const int blocks = b < 4096 ? b : 4096;
     if (c->d == 2)
         hipLaunchKernelGGL(k_budget<2>, dim3(blocks), dim3(kB), 0, c->stream, c->pos_cur, (int)c->n, c->nn, c->d2,
-                           c->Si, c->e, c->sc, parity, c->guard, c->K);
+                           c->Si, c->e, c->sc, parity, c->guard, c->K, c->cell, c->stamp, c->last_move, c->G, c->box,
+                           c->fuzz);
     else
         hipLaunchKernelGGL(k_budget<3>, dim3(blocks), dim3(kB), 0, c->stream, c->pos_cur, (int)c->n, c->nn, c->d2,
-                           c->Si, c->e, c->sc, parity, c->guard, c->K);
+                           c->Si, c->e, c->sc, parity, c->guard, c->K, c->cell, c->stamp, c->last_move, c->G, c->box,
+                           c->fuzz);
     return check();
 }
 

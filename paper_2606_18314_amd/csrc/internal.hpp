@@ -104,6 +104,7 @@ struct nnc_ctx {
     // frontier and histograms
     int32_t *frontier;
     int32_t *hist_fail, *hist_cand;   // per-cell counts of failures / candidates
+    int32_t *last_move;           // per cell: last step a moving point left or entered it
     unsigned long long *status;   // look-back tile descriptors
     int nstatus;
     nnc::DevScalars *sc;

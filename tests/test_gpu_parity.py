@@ -298,6 +298,28 @@ def test_budget_rule_plane(nnc, guard, lanes):
     run_parity(nnc, tr, G=130, guard=guard, lanes=lanes, budget=True, strategy="alternate")
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_budget_rule_localized_motion(nnc, d):
+    """Motion confined to one ball (the rest of the scene still), then spreading to
+    a second ball: the block-local budget keeps the certificates of quiet blocks;
+    candidates, keys and certificates against the oracle on every step."""
+    g = np.random.default_rng(900 + d)
+    n = 40000 if d == 2 else 30000
+    p = g.random((d, n))
+    c1 = np.full((d, 1), 0.3)
+    c2 = np.full((d, 1), 0.7)
+    frames = [p.copy()]
+    for t in range(10):
+        movers = np.linalg.norm(p - c1, axis=0) < 0.1
+        if t >= 5:
+            movers |= np.linalg.norm(p - c2, axis=0) < 0.05
+        step = g.standard_normal((d, n)) * 3e-4
+        p = p + np.where(movers, step, 0.0)
+        frames.append(p.copy())
+    tr = synth.Trajectory("custom", d, n, -1.0, np.array(frames, dtype=np.float32))
+    run_parity(nnc, tr, G=150 if d == 2 else 25, budget=True, strategy="alternate")
+
+
 def test_budget_rule_full_size_cube(nnc):
     """N = 16000 at the default grid, 20 steps of repair in budget mode."""
     tr = synth.cube_16k("uniform_brownian", steps=20)
