@@ -26,6 +26,8 @@ Legs (--legs):
             (d = 2 and 3, three step scales, N = 16000): failure fraction,
             misses of the safety rule and its over-flagging, and the local
             predictor rho's recall and false flags;
+  queue     candidate detection by the expiry calendar against the scan of
+            all keys, N = 2^20 to 2^24 at low pressure;
 plus a certification pass (every timed step of the repair and rebuild legs
 audited by the GPU all-pairs oracle: zero missed failures and bitwise-equal
 fresh certificates), HBM traffic of the dominant kernel from committed
@@ -62,7 +64,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling,audit")
+    ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling,audit,queue")
+    ap.add_argument("--queue-exps", default="20,22,24", help="log2 N of the queue leg's scenes")
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--repeats", type=int, default=5, help="timed replays per leg (the median is reported)")
     ap.add_argument("--scaling-exps", default="16,18,20,22,24,26",
@@ -521,6 +524,59 @@ def audit_leg(args, nnc, synth, torch):
     return {"n": n, "steps_per_run": steps, "eps": [5e-4, 2e-3, 8e-3], "d": [2, 3], "families": table}
 
 
+def queue_leg(args, nnc, synth, torch):
+    """Candidate detection by the expiry calendar (NNC_QUEUE) against the scan of all
+    keys, at low pressure (eps for about 0.1 % and 1 % of the points per step) and
+    N = 2^20 to 2^24 in the plane: per step the detection kernels' time (the scan, or
+    the calendar's pop plus the filing of the repaired keys) and the calendar's
+    entries read, from HIP events; both runs' candidate sets are compared."""
+    rows = []
+    d = 2
+    for e in [int(v) for v in args.queue_exps.split(",") if v]:
+        n = 1 << e
+        for frac in (0.001, 0.01):
+            p0 = synth.device_uniform(n, d, seed=8000 + e)
+            ctxs = {"scan": nnc.NNCert(n, d, lanes=16), "queue": nnc.NNCert(n, d, lanes=16, queue=True)}
+            for c in ctxs.values():
+                c.init_certificates(p0)
+            st = ctxs["scan"].state()
+            cs = (st["d2"] - st["d1"]).float()
+            eps = float(torch.kthvalue(cs, max(1, int(frac * n))).values) / 4.0
+            del st, cs
+            frames = [p0]
+            for t in range(1, 9):
+                frames.append(synth.device_brownian_step(frames[-1], eps, seed=8100 + 10 * e + t))
+            res = {}
+            same = True
+            for t in range(1, 9):
+                lists = {}
+                for name, c in ctxs.items():
+                    if t == 3:
+                        c.profile_enable(True)
+                    c.step(frames[t], -1.0)
+                    lists[name] = c.frontier_indices()
+                    c.repair()
+                same = same and torch.equal(torch.sort(lists["queue"]).values, lists["scan"])
+                cand = lists["scan"].numel()
+            for name, c in ctxs.items():
+                prof = c.profile_read()
+                ms, cnt = prof["filter"]
+                res[name] = ms / 6 * 1e3          # six profiled steps
+            qs = ctxs["queue"].queue_stats()
+            for c in ctxs.values():
+                c.close()
+            row = {"n": n, "target_fraction": frac, "eps": eps, "candidates_last_step": cand,
+                   "scan_detect_us_per_step": round(res["scan"], 2), "queue_detect_us_per_step": round(res["queue"], 2),
+                   "queue_entries_read_per_pop": round(qs["entries_read"] / max(qs["pops"], 1), 1),
+                   "queue_counters": qs, "same_candidate_sets": bool(same)}
+            progress(f"queue N=2^{e} f={frac}: scan {row['scan_detect_us_per_step']} us, queue "
+                     f"{row['queue_detect_us_per_step']} us, read {row['queue_entries_read_per_pop']}")
+            rows.append(row)
+            del frames
+            torch.cuda.empty_cache()
+    return {"d": d, "rows": rows}
+
+
 def scaling_leg(args, nnc, synth, torch):
     """The step, repair and rebuild kernels from N = 2^16 to 2^26 (d = 2, uniform,
     Brownian steps, eps set so that about 5 % of the points are candidates): mean
@@ -876,6 +932,8 @@ def main():
         legs["scaling"] = scaling_leg(args, nnc, synth, torch)
     if "audit" in legs_req:
         legs["audit"] = audit_leg(args, nnc, synth, torch)
+    if "queue" in legs_req:
+        legs["queue"] = queue_leg(args, nnc, synth, torch)
 
     # ---- batched scenes (512 scenes, log-uniform N, mixed d and families) ------------------
     if "batched" in legs_req:

@@ -83,6 +83,13 @@ extern "C" {
  * rule's, and motion confined to one region makes candidates only near it; no
  * failure is missed.  Costs a per-cell step stamp in the ingest. */
 #define NNC_BUDGET          16u
+/* Expiry calendar queue (appendix, per-step cost; Theorem 3): the keys are filed
+ * in a ring of buckets of the clock, so a step reads only the buckets the clock
+ * reached and files the repaired points' new keys, instead of scanning all N keys;
+ * the calendar is rebuilt (O(N)) after init, a rebuild, a restore, a caller's
+ * repair list, or when its pool fills.  The candidate SET is the same; the list
+ * comes in bucket order, not ascending.  Not with NNC_BUDGET; n < 2^28. */
+#define NNC_QUEUE           32u
 
 /* nnc_frontier_entropy: which set */
 #define NNC_FAILED     0      /* certificates whose nearest neighbour changed (Definition 2) */
@@ -100,7 +107,7 @@ typedef struct {
                              index build exceeds refresh * cell width; <= 0 = 0.25 */
     void    *stream;      /* hipStream_t to order work on; NULL = the null stream */
     uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC | NNC_QUERY_TILED | NNC_QUERY_POINTWISE |
-                             NNC_BUDGET */
+                             NNC_BUDGET | NNC_QUEUE */
     int32_t  block;       /* lanes that share one 2-NN query: 1 (one thread per query,
                              for large N), 16, 32 or 64; 0 = 32 for d = 3 and 16 for d = 2 */
     /* Domain box of the grid: axis k is cut into grid_g equal cells over
@@ -117,8 +124,8 @@ typedef struct {
  * G = max(1, floor(1/w)), a small constant mean occupancy (Section 2). */
 
 typedef struct {
-    const int32_t *idx_dev;    /* device: ascending candidate indices (library-owned,
-                                  valid until the next step/repair/rebuild) */
+    const int32_t *idx_dev;    /* device: ascending candidate indices (in bucket order with
+                                  NNC_QUEUE; library-owned, valid until the next step) */
     const int32_t *count_dev;  /* device: number of candidates */
     int32_t count_host;        /* filled when NNC_SYNC is set, else -1 */
     int32_t step;              /* step number t (1 = first step after init) */
@@ -225,6 +232,13 @@ int nnc_rho_predict(nnc_ctx *ctx);
  * candidates, over the current cells, with m and C (Theorem 4: m >= C^H), in one
  * struct with eps_t, S_t and the set's size.  Synchronises. */
 int nnc_frontier_entropy(nnc_ctx *ctx, int which, nnc_entropy *out);
+
+/* Work counters of the expiry calendar (NNC_QUEUE; appendix, per-step cost), since
+ * creation: out[0] steps that popped buckets, out[1] steps that scanned every key
+ * (the clock outran the calendar), out[2] calendars filed anew, out[3] entries the
+ * pops read; out[4] pool entries in use, out[5] keys in the far set at the last
+ * filing.  Synchronises.  NNC_E_STATE without NNC_QUEUE. */
+int nnc_queue_stats(nnc_ctx *ctx, int64_t *out);
 
 /* Spatial spread of the failed set (Definition 2's F_t) or of the last step's
  * candidates at the current positions: its radius of gyration

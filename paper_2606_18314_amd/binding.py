@@ -32,6 +32,7 @@ NNC_SYNC = 2
 NNC_QUERY_TILED = 4
 NNC_QUERY_POINTWISE = 8
 NNC_BUDGET = 16
+NNC_QUEUE = 32
 
 NNC_FAILED = 0
 NNC_CANDIDATES = 1
@@ -43,7 +44,7 @@ EXPORTS = (
     "nnc_batch_create", "nnc_batch_destroy", "nnc_batch_offsets", "nnc_batch_init", "nnc_batch_step",
     "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
     "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
-    "nnc_sqrt_f32", "nnc_mlp_grad_static", "nnc_frontier_gyration",
+    "nnc_sqrt_f32", "nnc_mlp_grad_static", "nnc_frontier_gyration", "nnc_queue_stats",
 )
 
 POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
@@ -158,6 +159,7 @@ def load():
                                  ctypes.c_float, P]
     lib.nnc_mlp_forward.argtypes = [P, P, ctypes.c_int, P, P]
     lib.nnc_sqrt_f32.argtypes = [P, P, ctypes.c_int64, P]
+    lib.nnc_queue_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.nnc_frontier_gyration.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
     lib.nnc_strerror.argtypes = [ctypes.c_int]
@@ -252,12 +254,13 @@ class NNCert:
 
     def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
                  copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0,
-                 all_query: str = "auto", box=None, budget: bool = False):
+                 all_query: str = "auto", box=None, budget: bool = False, queue: bool = False):
         """all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
         query every point (under "auto" tiled by cells from N = 65536 on at
         initialisation, from 2^17 (d = 2) or 2^19 (d = 3) on at a rebuild).
         box: (lo, hi), per-axis bounds of the grid's domain (default the unit box).
-        budget: the per-point motion budget (NNC_BUDGET) tightens the candidate set."""
+        budget: the per-point motion budget (NNC_BUDGET) tightens the candidate set.
+        queue: the expiry calendar queue (NNC_QUEUE) replaces the filter's scan of all keys."""
         if all_query not in ("auto", "tiled", "pointwise"):
             raise ValueError("all_query: 'auto', 'tiled' or 'pointwise'")
         lib = load()
@@ -268,7 +271,7 @@ class NNCert:
                      flags=(NNC_COPY_POSITIONS if copy_positions else 0) | (NNC_SYNC if sync else 0)
                      | (NNC_QUERY_TILED if all_query == "tiled" else 0)
                      | (NNC_QUERY_POINTWISE if all_query == "pointwise" else 0)
-                     | (NNC_BUDGET if budget else 0),
+                     | (NNC_BUDGET if budget else 0) | (NNC_QUEUE if queue else 0),
                      block=int(lanes))
         if box is not None:
             lo, hi = box
@@ -328,6 +331,12 @@ class NNCert:
         e = Entropy()
         check(_lib.nnc_frontier_entropy(self.h, which, ctypes.byref(e)), "nnc_frontier_entropy")
         return {k: getattr(e, k) for k, _ in Entropy._fields_}
+
+    def queue_stats(self) -> dict:
+        """Work counters of the expiry calendar (NNC_QUEUE contexts)."""
+        v = (ctypes.c_int64 * 6)()
+        check(_lib.nnc_queue_stats(self.h, v), "nnc_queue_stats")
+        return dict(zip(("pops", "full_scans", "builds", "entries_read", "pool_used", "far_keys"), list(v)))
 
     def frontier_gyration(self, which: int = NNC_FAILED):
         """(radius of gyration, centroid (x, y, z)) of the failed set or the candidates."""

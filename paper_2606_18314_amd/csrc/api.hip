@@ -72,6 +72,18 @@ size_t carve(nnc_ctx *c, char *base)
     c->tcount = k.take<int32_t>((size_t)c->ntcount);
     c->ent_part = k.take<double>(3 * nnc::kEntropyParts);
     c->shape_part = k.take<double>(4 * nnc::kShapeParts + 4);
+    if (c->flags & NNC_QUEUE) {
+        c->q_cap = (int)(4 * n + 1024);
+        c->qh = k.take<nnc::QHead>(1);
+        c->q_pool = k.take<int32_t>((size_t)c->q_cap);
+        c->q_nruns = k.take<int32_t>(nnc::kQR);
+        c->q_run_start = k.take<int32_t>((size_t)nnc::kQR * nnc::kQRuns);
+        c->q_run_len = k.take<int32_t>((size_t)nnc::kQR * nnc::kQRuns);
+        c->q_bcnt = k.take<int32_t>(nnc::kQR);
+        c->q_cursor = k.take<int32_t>(nnc::kQR);
+        c->q_qa = k.take<int32_t>(n);
+        c->q_keep = k.take<int32_t>(n);
+    }
     c->a_nn = k.take<int32_t>(n);
     c->a_d1 = k.take<float>(n);
     c->a_d2 = k.take<float>(n);
@@ -185,6 +197,7 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
     *out = nullptr;
     if (cfg->d != 2 && cfg->d != 3) return NNC_E_INVAL;
     if (cfg->n < 0 || cfg->n >= (int64_t)1 << 31) return NNC_E_INVAL;
+    if ((cfg->flags & NNC_QUEUE) && ((cfg->flags & NNC_BUDGET) || cfg->n >= (int64_t)1 << 28)) return NNC_E_INVAL;
     const int G = cfg->grid_g > 0 ? cfg->grid_g : default_grid(cfg->n, cfg->d);
     const double cells = pow((double)G, (double)cfg->d);
     if (G < 1 || cells > (double)kMaxCells) return NNC_E_INVAL;
@@ -267,6 +280,7 @@ int nnc_init_certificates(nnc_ctx *c, const float *pos)
     c->t = 0;
     c->pending = 0;
     c->rho_step = -1;
+    c->queue_valid = 0;
     // everything but the status words (whose epochs keep increasing) starts at zero
     if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
     int rc = nnc::launch_cells_init(c, c->pos_cur);
@@ -286,7 +300,12 @@ int nnc_step(nnc_ctx *c, const float *pos_new, float eps_declared, nnc_frontier 
     int rc = timed(c, NNC_K_INGEST, [&] { return nnc::launch_ingest(c, c->pos_prev, c->pos_cur); });
     if (rc == NNC_OK && (c->flags & NNC_BUDGET))
         rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_budget(c); });
-    if (rc == NNC_OK) rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_filter(c, eps_declared); });
+    if (rc == NNC_OK) {
+        if ((c->flags & NNC_QUEUE) && c->queue_valid)
+            rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_queue_pop(c, eps_declared); });
+        else
+            rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_filter(c, eps_declared); });
+    }
     if (rc != NNC_OK) return rc;
     c->grid_fresh = 0;
     if (eps_declared >= 0.0f && c->drift_host >= 0.0)
@@ -323,6 +342,17 @@ int nnc_repair(nnc_ctx *c, const nnc_frontier *f)
             return nnc::launch_query(c, f ? f->idx_dev : c->frontier, f ? f->count_dev : &c->sc->nfront, 0, 0);
         });
     if (rc == NNC_OK) rc = timed(c, NNC_K_ENTROPY, [&] { return nnc::launch_entropy(c, 0); });
+    // the calendar files the new keys (anew when it was not valid); after a caller's
+    // list, whose points were not popped and whose fail flags the next pop would not
+    // clear, the next step scans every key and the calendar is filed anew
+    if (rc == NNC_OK && (c->flags & NNC_QUEUE)) {
+        if (f) {
+            c->queue_valid = 0;
+        } else {
+            rc = timed(c, NNC_K_FILTER, [&] { return nnc::launch_queue_file(c, !c->queue_valid); });
+            c->queue_valid = rc == NNC_OK;
+        }
+    }
     c->pending = 0;
     c->steps_since_grid += 1;
     return rc;
@@ -335,6 +365,9 @@ int nnc_rebuild(nnc_ctx *c)
     int rc = build_grid(c);
     if (rc == NNC_OK) rc = timed(c, NNC_K_QUERY, [&] { return nnc::launch_query_all(c, 0); });
     if (rc == NNC_OK) rc = timed(c, NNC_K_ENTROPY, [&] { return nnc::launch_entropy(c, 0); });
+    // every key and any fail flag changed: the next step scans all keys (clearing every
+    // flag) and its repair files the calendar anew
+    c->queue_valid = 0;
     c->pending = 0;
     return rc;
 }
@@ -397,6 +430,23 @@ int nnc_frontier_entropy(nnc_ctx *c, int which, nnc_entropy *out)
     out->C = h.Cres[which];
     out->count = h.F[which];
     return take_error(c, h);
+}
+
+int nnc_queue_stats(nnc_ctx *c, int64_t *out)
+{
+    if (!c || !out) return NNC_E_INVAL;
+    if (!(c->flags & NNC_QUEUE)) return NNC_E_STATE;
+    nnc::QHead h;
+    if (hipMemcpyAsync(&h, c->qh, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return NNC_E_HIP;
+    out[0] = (int64_t)h.n_pop;
+    out[1] = (int64_t)h.n_scan;
+    out[2] = (int64_t)h.n_build;
+    out[3] = (int64_t)h.n_read;
+    out[4] = (int64_t)h.pool_top;
+    out[5] = (int64_t)h.far_count;
+    return NNC_OK;
 }
 
 int nnc_frontier_gyration(nnc_ctx *c, int which, double *gyration, double *centroid)
@@ -518,6 +568,7 @@ int nnc_restore(nnc_ctx *c, const nnc_snap *s)
     c->pos_prev = s->pos_prev;
     c->steps_since_grid = s->steps_since_grid;
     c->rho_step = -1;
+    c->queue_valid = 0;  // the calendar is not part of a snapshot: the next step scans every key
     return NNC_OK;
 }
 

@@ -55,6 +55,33 @@ struct DevSync {
     unsigned tile_ctr;
 };
 
+// Expiry calendar queue (NNC_QUEUE): every finite expiry key is filed in a ring of
+// kQR buckets of width W (clock units) starting at bucket a_epoch, or, more than
+// kQAhead buckets past the clock, in a far set whose smallest key is kept.  A
+// bucket is a list of runs (start, length) in an append-only pool; each filing
+// adds at most one run per bucket.  See queue.hip.
+constexpr int kQR = 512;        // ring buckets
+constexpr int kQAhead = 256;    // buckets past the clock's bucket that the ring files
+constexpr int kQRuns = 512;     // runs per bucket
+
+struct QHead {
+    double W;                   // bucket width
+    long long a_epoch;          // absolute bucket floor(e / W) of relative bucket 0
+    unsigned long long far_min; // bits of the smallest key in the far set (keys >= 0)
+    int pool_top;               // entries used in the pool
+    int a_next;                 // first relative bucket not yet fully popped
+    int a_hi;                   // relative bucket of S_t at the last pop or build
+    int cnt[2];                 // entries popped as candidates, by step parity
+    int nkeep;                  // popped entries not yet due (filed again after the repair)
+    int build;                  // 1: the next filing rebuilds the whole calendar
+    int mode;                   // this filing: 0 appends, 1 rebuilds
+    int far_count;
+    int fallback;               // this step's pop scanned every key
+    // counters since creation: steps that popped buckets, steps that scanned every
+    // key, calendars filed anew, entries the pops read
+    unsigned long long n_pop, n_scan, n_build, n_read;
+};
+
 // Loose uniform grid: slots are grouped by the cell each point had when the grid
 // was last built; slot k holds one 16-byte record {x, y, z, point index} with the
 // point's CURRENT coordinates (z = 0 in the plane; ingest rewrites the record
@@ -105,6 +132,11 @@ struct nnc_ctx {
     int32_t *frontier;
     int32_t *hist_fail, *hist_cand;   // per-cell counts of failures / candidates
     int32_t *last_move;           // per cell: last step a moving point left or entered it
+    // expiry calendar queue (NNC_QUEUE)
+    nnc::QHead *qh;
+    int32_t *q_pool, *q_nruns, *q_run_start, *q_run_len, *q_bcnt, *q_cursor, *q_qa, *q_keep;
+    int q_cap;
+    int queue_valid;              // host: the calendar holds every current key
     unsigned long long *status;   // look-back tile descriptors
     int nstatus;
     nnc::DevScalars *sc;
@@ -164,6 +196,10 @@ int launch_cand_hist(nnc_ctx *c);
 int launch_audit(nnc_ctx *c);
 int launch_rho(nnc_ctx *c);
 int launch_budget(nnc_ctx *c);
+// queue.hip: the calendar's pop (in place of the filter) and its filing after a repair
+// or rebuild (rebuilding the whole calendar when build is set)
+int launch_queue_pop(nnc_ctx *c, float eps_declared);
+int launch_queue_file(nnc_ctx *c, int build);
 // which = 0: failed points, 1: candidates; cen: null for the first pass (sums of
 // coordinates and count), else the centroid (sum of squared distances)
 int launch_shape(nnc_ctx *c, int which, const double *cen);

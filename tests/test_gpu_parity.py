@@ -102,10 +102,11 @@ def test_allpairs_cube_16k_size(nnc):
 # --- the state machine ---------------------------------------------------------------
 
 def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_every=1, lanes=0, all_query="auto",
-               box=None, budget=False):
+               box=None, budget=False, queue=False):
     d, n = traj.d, traj.n
     frames = [dev(f) for f in traj.frames]
-    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query, box=box, budget=budget)
+    ctx = nnc.NNCert(n, d, grid_g=G, guard=guard, lanes=lanes, all_query=all_query, box=box, budget=budget,
+                     queue=queue)
     assert ctx.grid_g == G
     sc = model.OracleScene(d=d, n=n, G=G, guard=model.GUARD_DEFAULT if guard < 0 else guard,
                            lo=None if box is None else box[0], hi=None if box is None else box[1],
@@ -118,6 +119,9 @@ def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_ev
         ctx.step(frames[t], traj.eps)
         res = sc.step(traj.frames[t])
         cand = host(ctx.frontier_indices())
+        if queue:   # the calendar lists its candidates in bucket order
+            assert np.unique(cand).size == cand.size, f"duplicate candidates step {t}"
+            cand = np.sort(cand)
         assert np.array_equal(cand, res.candidates), f"candidates step {t}"
         ent_c = ctx.frontier_entropy(nnc.NNC_CANDIDATES)
         assert ent_c["eps"] == float(res.eps)
@@ -141,6 +145,8 @@ def run_parity(nnc, traj, G, steps=None, strategy="repair", guard=-1.0, check_ev
     audit = ctx.oracle_verify()
     assert audit["n_missed"] == 0
     assert audit["n_value_mismatch"] == 0
+    if queue:
+        audit["queue"] = ctx.queue_stats()
     ctx.close()
     return audit
 
@@ -324,6 +330,70 @@ def test_budget_rule_full_size_cube(nnc):
     """N = 16000 at the default grid, 20 steps of repair in budget mode."""
     tr = synth.cube_16k("uniform_brownian", steps=20)
     run_parity(nnc, tr, G=15, budget=True)
+
+
+@pytest.mark.parametrize("family", synth.FAMILIES)
+def test_queue_cube_families(nnc, family):
+    """The expiry calendar (NNC_QUEUE): the candidate set of every step equals the
+    oracle's (every key at or below the clock), and every certificate too, through
+    repairs and a rebuild every fourth step (the calendar is filed anew after it)."""
+    tr = synth.make_trajectory(family, 6000, 3, 30, 5e-4, 2000 + synth.FAMILIES.index(family))
+    q = run_parity(nnc, tr, G=12, strategy="alternate", queue=True)["queue"]
+    # steps after a rebuild scan every key; the others pop buckets
+    assert q["pops"] >= 20 and q["full_scans"] == 0, q
+
+
+@pytest.mark.parametrize("lanes", [1, 16])
+def test_queue_plane(nnc, lanes):
+    run_parity(nnc, synth.plane_1k(), G=15, lanes=lanes, queue=True)
+    tr = synth.make_trajectory("uniform_brownian", 70000, 2, 12, 1e-3, 4546)
+    q = run_parity(nnc, tr, G=130, lanes=lanes, queue=True)["queue"]
+    assert q["pops"] == 11 and q["builds"] >= 1, q
+
+
+def test_queue_step_sizes_that_outrun_the_ring(nnc):
+    """Steps that grow a hundredfold and shrink again: the clock runs past the ring's
+    window and reaches the far set (the pop scans every key and the calendar is filed
+    anew), then falls back to small steps; static frames (eps = 0) in between."""
+    g = np.random.default_rng(77)
+    n, d = 5000, 3
+    p = g.random((d, n))
+    frames = [p.copy()]
+    for t in range(24):
+        scale = 1e-4 if t < 6 else (2e-2 if t < 10 else (0.0 if t in (12, 13) else 3e-4))
+        p = p + scale * g.standard_normal((d, n))
+        frames.append(p.copy())
+    tr = synth.Trajectory("custom", d, n, -1.0, np.array(frames, dtype=np.float32))
+    q = run_parity(nnc, tr, G=10, queue=True)["queue"]
+    assert q["full_scans"] >= 1 and q["pops"] >= 10, q
+
+
+def test_queue_with_snapshots_and_forced_lists(nnc):
+    """A restore and a caller's repair list invalidate the calendar; the steps after
+    them still list exactly the due keys."""
+    tr = synth.cube_16k("adversarial_crossing", n=4000, steps=12)
+    ctx = nnc.NNCert(4000, 3, grid_g=9, queue=True)
+    sc = model.OracleScene(d=3, n=4000, G=9)
+    ctx.init_certificates(dev(tr.frames[0]))
+    sc.init_certificates(tr.frames[0])
+    for t in range(1, 13):
+        ctx.step(dev(tr.frames[t]), tr.eps)
+        res = sc.step(tr.frames[t])
+        assert np.array_equal(np.sort(host(ctx.frontier_indices())), res.candidates), t
+        if t == 5:
+            snap = ctx.snapshot()
+            ctx.rebuild()
+            ctx.restore(snap)
+        if t == 8:
+            forced = np.union1d(res.candidates, np.arange(0, 4000, 13)).astype(np.int32)
+            ctx.repair(dev(forced), dev(np.array([forced.size], np.int32)))
+            sc.repair(forced)
+        else:
+            ctx.repair()
+            sc.repair()
+        assert_state_equal(ctx.state(), sc, f"step {t}")
+    assert ctx.oracle_verify()["n_missed"] == 0
+    ctx.close()
 
 
 def test_guard_zero_literal_key(nnc):
