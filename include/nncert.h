@@ -64,7 +64,9 @@ extern "C" {
 #define NNC_SYNC           2u  /* nnc_step synchronises and fills count_host */
 /* All-point queries (initialisation, rebuild) run tiled by grid cells with the
  * neighbourhood staged in LDS from N = 65536 on for initialisation and from
- * N = 2^17 (d = 2) or 2^19 (d = 3) on for a rebuild, pointwise below; these force one. */
+ * N = 2^17 (d = 2) or 2^19 (d = 3) on for a rebuild, pointwise below; these force one.
+ * NNC_QUERY_TILED also sends repairs to the tiled query of the marked candidates
+ * (faster only when about half of the points are candidates). */
 #define NNC_QUERY_TILED     4u
 #define NNC_QUERY_POINTWISE 8u
 /* Per-point motion budget (the Limitations section's tighter safe set): each step,
@@ -338,7 +340,7 @@ typedef struct {
     double guard;            /* as in nnc_config */
     double refresh;          /* as in nnc_config */
     void *stream;            /* hipStream_t */
-    uint32_t flags;          /* NNC_BATCH_FEATURES | NNC_BATCH_EAGER */
+    uint32_t flags;          /* NNC_BATCH_FEATURES | NNC_BATCH_EAGER | NNC_BATCH_TIMING */
 } nnc_batch_config;
 
 /* Compute the candidate histogram, H of the candidates and the selector features
@@ -346,6 +348,11 @@ typedef struct {
 #define NNC_BATCH_FEATURES 1u
 /* Launch the step's kernels one by one instead of through the library's graph. */
 #define NNC_BATCH_EAGER    2u
+/* Per-scene cost accounting with the GPU's wall clock: the filter's and the grid
+ * build's workgroup time and the query waves' summed busy time of each scene
+ * (nnc_scene_stats.t_*_us), to label each scene-step with its cheaper strategy
+ * inside the batch (Section 3's best-strategy label). */
+#define NNC_BATCH_TIMING   4u
 
 typedef struct {
     double  eps;             /* eps_t of the last step */
@@ -359,6 +366,9 @@ typedef struct {
     int32_t strategy;        /* 0 repair, 1 rebuild */
     int32_t err;             /* NNC_OK or a negative code latched for this scene */
     float   features[NNC_FEATURES];
+    double  t_filter_us;     /* with NNC_BATCH_TIMING (else -1): the scene's filter workgroup time, */
+    double  t_grid_us;       /* its grid build's workgroup time (0 without a build), */
+    double  t_query_us;      /* and the summed time of the query waves that worked on it */
 } nnc_scene_stats;
 
 /* Create a batch of independent scenes, each the point set of Section 2; allocates
@@ -404,6 +414,16 @@ int nnc_batch_selector_load(nnc_batch *b, const float *params);
  * (appendix clock), sizes and entropies of the failed and candidate sets
  * (Definition 2), the features and the chosen strategy.  Synchronises. */
 int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out);
+
+/* Device-side copy of a batch's whole state, to time both strategies on one step
+ * of every scene (Section 3's label); allocates.  Restore copies it back
+ * (asynchronous); snap_free releases it (NULL ignored). */
+typedef struct nnc_batch_snap nnc_batch_snap;
+int nnc_batch_snapshot(nnc_batch *b, nnc_batch_snap **out);
+int nnc_batch_restore(nnc_batch *b, const nnc_batch_snap *snap);
+/* Overwrite an existing snapshot of this batch with the current state (no allocation). */
+int nnc_batch_snapshot_update(nnc_batch *b, nnc_batch_snap *snap);
+void nnc_batch_snap_free(nnc_batch_snap *snap);
 
 /* Device views of the concatenated per-point records (Section 2; n = total
  * points, d = 0, grid_g = 0, rho = NULL).  Does not synchronise. */

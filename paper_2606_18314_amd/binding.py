@@ -45,6 +45,7 @@ EXPORTS = (
     "nnc_batch_selector_load", "nnc_batch_scene_stats", "nnc_batch_get_state", "nnc_features",
     "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
     "nnc_sqrt_f32", "nnc_mlp_grad_static", "nnc_frontier_gyration", "nnc_queue_stats",
+    "nnc_batch_snapshot", "nnc_batch_restore", "nnc_batch_snap_free", "nnc_batch_snapshot_update",
 )
 
 POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
@@ -105,7 +106,8 @@ class SceneStats(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("S", ctypes.c_double), ("H_fail", ctypes.c_double),
                 ("H_cand", ctypes.c_double), ("n_cand", ctypes.c_int32), ("n_fail", ctypes.c_int32),
                 ("m_cand", ctypes.c_int32), ("C", ctypes.c_int32), ("strategy", ctypes.c_int32),
-                ("err", ctypes.c_int32), ("features", ctypes.c_float * 6)]
+                ("err", ctypes.c_int32), ("features", ctypes.c_float * 6),
+                ("t_filter_us", ctypes.c_double), ("t_grid_us", ctypes.c_double), ("t_query_us", ctypes.c_double)]
 
 
 _lib = None
@@ -160,6 +162,11 @@ def load():
     lib.nnc_mlp_forward.argtypes = [P, P, ctypes.c_int, P, P]
     lib.nnc_sqrt_f32.argtypes = [P, P, ctypes.c_int64, P]
     lib.nnc_queue_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.nnc_batch_snapshot.argtypes = [P, ctypes.POINTER(P)]
+    lib.nnc_batch_restore.argtypes = [P, P]
+    lib.nnc_batch_snapshot_update.argtypes = [P, P]
+    lib.nnc_batch_snap_free.argtypes = [P]
+    lib.nnc_batch_snap_free.restype = None
     lib.nnc_frontier_gyration.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
     lib.nnc_strerror.argtypes = [ctypes.c_int]
@@ -410,6 +417,16 @@ class NNCert:
         check(_lib.nnc_restore(self.h, snap.handle), "nnc_restore")
 
 
+class BatchSnapshot:
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.nnc_batch_snap_free(self.handle)
+            self.handle = 0
+
+
 class NNCBatch:
     """Many independent scenes advanced together (one launch per kernel for all scenes).
 
@@ -417,8 +434,9 @@ class NNCBatch:
     [d_s, n_s] block starting at ``coord_off[s]``."""
 
     def __init__(self, ns, ds, grids=None, lanes: int = 0, guard: float = -1.0, refresh: float = 0.0,
-                 stream: int | None = None, features: bool = False, eager: bool = False):
-        """eager: launch each step's kernels directly instead of through the library's graph."""
+                 stream: int | None = None, features: bool = False, eager: bool = False, timing: bool = False):
+        """eager: launch each step's kernels directly instead of through the library's graph;
+        timing: per-scene wall-clock cost accounting (stats' t_filter_us, t_grid_us, t_query_us)."""
         import numpy as np
         lib = load()
         self.S = len(ns)
@@ -429,7 +447,7 @@ class NNCBatch:
         cfg = BatchConfig(scenes=self.S, n=self._n.ctypes.data, d=self._d.ctypes.data,
                           grid_g=0 if self._g is None else self._g.ctypes.data, lanes=int(lanes),
                           guard=float(guard), refresh=float(refresh), stream=self.stream,
-                          flags=(1 if features else 0) | (2 if eager else 0))
+                          flags=(1 if features else 0) | (2 if eager else 0) | (4 if timing else 0))
         h = ctypes.c_void_p()
         check(lib.nnc_batch_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_batch_create")
         self.h = h.value
@@ -454,6 +472,18 @@ class NNCBatch:
     def step(self, pos: torch.Tensor, policy: int = POLICY_REPAIR, tau: float = 0.5) -> None:
         self._keep = (self._keep + [pos])[-2:]
         check(_lib.nnc_batch_step(self.h, _ptr(pos), int(policy), float(tau)), "nnc_batch_step")
+
+    def snapshot(self, into=None):
+        """A device copy of the whole batch state (BatchSnapshot; into: overwrite that one)."""
+        if into is not None:
+            check(_lib.nnc_batch_snapshot_update(self.h, into.handle), "nnc_batch_snapshot_update")
+            return into
+        h = ctypes.c_void_p()
+        check(_lib.nnc_batch_snapshot(self.h, ctypes.byref(h)), "nnc_batch_snapshot")
+        return BatchSnapshot(h.value)
+
+    def restore(self, snap) -> None:
+        check(_lib.nnc_batch_restore(self.h, snap.handle), "nnc_batch_restore")
 
     def selector_load(self, params: torch.Tensor) -> None:
         if params.numel() != SELECTOR_PARAMS or params.dtype != torch.float32:

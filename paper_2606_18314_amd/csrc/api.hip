@@ -68,20 +68,25 @@ size_t carve(nnc_ctx *c, char *base)
     c->status = k.take<unsigned long long>(tiles);
     c->wide = k.take<int32_t>(n);
     c->rec = k.take<int4>(n);
+    c->cmask = k.take<uint8_t>(n);
     c->ntcount = (int)((n + 4095) / 4096 + 1);
     c->tcount = k.take<int32_t>((size_t)c->ntcount);
+    c->nfmask = (long long)((n + 4095) / 4096 + 1) * 64;
+    c->fmask = k.take<unsigned long long>((size_t)c->nfmask);
     c->ent_part = k.take<double>(3 * nnc::kEntropyParts);
     c->shape_part = k.take<double>(4 * nnc::kShapeParts + 4);
     if (c->flags & NNC_QUEUE) {
         c->q_cap = (int)(4 * n + 1024);
         c->qh = k.take<nnc::QHead>(1);
         c->q_pool = k.take<int32_t>((size_t)c->q_cap);
+        c->q_pool_e = k.take<double>((size_t)c->q_cap);
+        c->q_keep_e = k.take<double>(n);
+        c->q_key = k.take<double>(n);
         c->q_nruns = k.take<int32_t>(nnc::kQR);
         c->q_run_start = k.take<int32_t>((size_t)nnc::kQR * nnc::kQRuns);
         c->q_run_len = k.take<int32_t>((size_t)nnc::kQR * nnc::kQRuns);
         c->q_bcnt = k.take<int32_t>(nnc::kQR);
         c->q_cursor = k.take<int32_t>(nnc::kQR);
-        c->q_qa = k.take<int32_t>(n);
         c->q_keep = k.take<int32_t>(n);
     }
     c->a_nn = k.take<int32_t>(n);
@@ -281,6 +286,7 @@ int nnc_init_certificates(nnc_ctx *c, const float *pos)
     c->pending = 0;
     c->rho_step = -1;
     c->queue_valid = 0;
+    c->fail_dirty = 1;
     // everything but the status words (whose epochs keep increasing) starts at zero
     if (hipMemsetAsync(c->arena, 0, c->state_bytes, c->stream) != hipSuccess) return NNC_E_HIP;
     int rc = nnc::launch_cells_init(c, c->pos_cur);
@@ -339,12 +345,14 @@ int nnc_repair(nnc_ctx *c, const nnc_frontier *f)
     if (refresh) rc = build_grid(c);
     if (rc == NNC_OK)
         rc = timed(c, NNC_K_QUERY, [&] {
-            return nnc::launch_query(c, f ? f->idx_dev : c->frontier, f ? f->count_dev : &c->sc->nfront, 0, 0);
+            return nnc::launch_query(c, f ? f->idx_dev : c->frontier, f ? f->count_dev : &c->sc->nfront, 0, 0,
+                                     (c->flags & NNC_QUEUE) && !f ? c->q_key : nullptr);
         });
     if (rc == NNC_OK) rc = timed(c, NNC_K_ENTROPY, [&] { return nnc::launch_entropy(c, 0); });
     // the calendar files the new keys (anew when it was not valid); after a caller's
     // list, whose points were not popped and whose fail flags the next pop would not
     // clear, the next step scans every key and the calendar is filed anew
+    if (f) c->fail_dirty = 1;  // the caller's list set fail flags outside the candidate list
     if (rc == NNC_OK && (c->flags & NNC_QUEUE)) {
         if (f) {
             c->queue_valid = 0;
@@ -368,6 +376,7 @@ int nnc_rebuild(nnc_ctx *c)
     // every key and any fail flag changed: the next step scans all keys (clearing every
     // flag) and its repair files the calendar anew
     c->queue_valid = 0;
+    c->fail_dirty = 1;
     c->pending = 0;
     return rc;
 }
@@ -569,6 +578,7 @@ int nnc_restore(nnc_ctx *c, const nnc_snap *s)
     c->steps_since_grid = s->steps_since_grid;
     c->rho_step = -1;
     c->queue_valid = 0;  // the calendar is not part of a snapshot: the next step scans every key
+    c->fail_dirty = 1;
     return NNC_OK;
 }
 

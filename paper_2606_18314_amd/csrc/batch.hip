@@ -57,6 +57,7 @@ struct BatchArgs {
     double guard, K;
     DevScalars *sc;
     int *tdev;                // [0] completed steps, [1] selector parameters loaded
+    unsigned long long *cost; // per scene [filter, grid, query] wall-clock ticks (NNC_BATCH_TIMING), or null
     const float *pos_cur;
     float4 *slots;  // slot records {x, y, z, point index}, indexed by poff + slot
     int *cell, *counts, *rank, *cell_start, *cursor;
@@ -177,10 +178,14 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
     __shared__ float s_h[kH];
     __shared__ int s_dec;
     const int s = blockIdx.x;
+    const long long t_start = a.cost ? wall_clock64() : 0;
     const SceneDesc sd = a.desc[s];
     DevScalars *sc = &a.sc[s];
     const int n = sd.n;
     const int parity = step_number(a) & 1;
+    // candidate histogram, entropy and the budget median only when a feature is wanted
+    // (the learned policy, or statistics requested)
+    const bool want = a.features_on || a.policy == NNC_POLICY_LEARNED;
     if (threadIdx.x < kVBins) s_vh[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_m = 0;
     const double Sprev = sc->S[parity ^ 1];
@@ -199,10 +204,22 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
         const int i = k * kFB + (int)threadIdx.x;
+        int bin = -1;
         if (i < n) {
             a.fail[sd.poff + i] = 0;
             const double r = ev[k] - Sprev;  // remaining motion budget of the certificate
-            if (r > 0.0 && r < __builtin_inf()) atomicAdd(&s_vh[validity_bin(r)], 1);
+            if (r > 0.0 && r < __builtin_inf()) bin = validity_bin(r);
+        }
+        if (want) {
+            // the budget histogram, one LDS add per distinct bin of the wave (most
+            // budgets of a row fall in a few neighbouring bins)
+            unsigned long long left = __ballot(bin >= 0);
+            while (left) {
+                const int b = __shfl(bin, __ffsll((long long)left) - 1, 64);
+                const unsigned long long same = __ballot(bin == b) & left;
+                if (lane == 0) atomicAdd(&s_vh[b], (int)__popcll(same));
+                left &= ~same;
+            }
         }
         masks[k] = __ballot(St >= ev[k]);
         if (lane == 0) s_cnt[k * NW + w] = __popcll(masks[k]);
@@ -234,16 +251,28 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
             if (at < n) front[at] = i;
         }
     }
-    // candidate cells: histogram, touched list, entropy (all within this workgroup);
-    // only when a feature is wanted (the learned policy, or statistics requested)
-    const bool want = a.features_on || a.policy == NNC_POLICY_LEARNED;
+    // candidate cells: histogram, touched list, entropy (all within this workgroup)
     const int *cell = a.cell + sd.poff;
     int *hist = a.hist_cand + sd.goff;
     int *touched = a.touched_cand + sd.poff;
     if (want) {
-        for (int q = (int)threadIdx.x; q < tot; q += kFB) {
-            const int c = cell[front[q]];
-            if (atomicAdd(&hist[c], 1) == 0) touched[atomicAdd(&s_m, 1)] = c;
+        // one LDS atomic per wave for the first touches of cells
+        for (int base = 0; base < tot; base += kFB) {
+            const int q = base + (int)threadIdx.x;
+            int c = 0;
+            bool first = false;
+            if (q < tot) {
+                c = cell[front[q]];
+                first = atomicAdd(&hist[c], 1) == 0;
+            }
+            const unsigned long long fm = __ballot(first);
+            if (fm) {
+                const int leader = __ffsll((long long)fm) - 1;
+                int at = 0;
+                if ((int)lane == leader) at = atomicAdd(&s_m, (int)__popcll(fm));
+                at = __shfl(at, leader, 64);
+                if (first) touched[at + rank_below(fm)] = c;
+            }
         }
     }
     __syncthreads();
@@ -293,6 +322,10 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
         a.strategy[s] = dec;
         a.need_grid[s] = dec == 1 || (St - sc->S_grid > sd.refresh_w);
         a.qcount[s] = dec == 1 ? n : tot;
+        if (a.cost) {
+            a.cost[3 * s] = (unsigned long long)(wall_clock64() - t_start);
+            a.cost[3 * s + 2] = 0;  // the query kernel adds into it
+        }
     }
 }
 
@@ -314,7 +347,11 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
         return;
     }
     const int s = blockIdx.x;
-    if (!a.need_grid[s]) return;
+    if (!a.need_grid[s]) {
+        if (a.cost && threadIdx.x == 0) a.cost[3 * s + 1] = 0;
+        return;
+    }
+    const long long t_start = a.cost ? wall_clock64() : 0;
     const SceneDesc sd = a.desc[s];
     int run = 0;
     for (int base = 0; base < sd.ncell; base += kFB) {
@@ -345,6 +382,10 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
         a.rank[sd.poff + i] = k;
         so[k] = make_float4(p[i], p[n1 + i], sd.d == 3 ? p[2 * n1 + i] : 0.0f, __int_as_float(i));
     }
+    if (a.cost) {
+        __syncthreads();
+        if (threadIdx.x == 0) a.cost[3 * s + 1] = (unsigned long long)(wall_clock64() - t_start);
+    }
 }
 
 // Per-scene view of the concatenated arrays for the shared query routine.
@@ -372,6 +413,9 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     q.d2 = a.d2 + sd.poff;
     q.e = a.e + sd.poff;
     q.Si = nullptr;
+    q.cmask = nullptr;
+    q.qkey = nullptr;
+    q.tiled_from = 0;
     q.fail = a.fail + sd.poff;
     q.sc = &a.sc[s];
     q.guard = a.guard;
@@ -421,6 +465,7 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
             const double St = a.sc[s].S[parity];
             const double margin = query_margin(St, a.sc[s].S_grid, kFuzz);
             const int end = min(next, q1);
+            const long long t_start = a.cost ? wall_clock64() : 0;
             for (; g < end; g += GPW) {
                 if (g + grp < end) {
                     if (sd.d == 3)
@@ -430,6 +475,8 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
                 }
             }
             g = end;
+            if (a.cost && (threadIdx.x & 63) == 0)
+                atomicAdd(&a.cost[3 * s + 2], (unsigned long long)(wall_clock64() - t_start));
         }
         ++s;
     }
@@ -479,7 +526,9 @@ struct nnc_batch {
     int ntiles;
     void *arena;
     nnc::BatchArgs a;       // device pointers, refreshed per call
+    size_t arena_bytes;
     int inited, features_on, eager;
+    double tick_us;         // microseconds per wall-clock tick (NNC_BATCH_TIMING)
     // the step as a graph: instantiated on the first call and replayed while
     // (positions, policy, tau) repeat; another key re-captures and updates it
     hipGraphExec_t exec;
@@ -589,7 +638,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     bytes += 4 * al(Pp * 4);                                   // stamp, frontier, touched x2
     bytes += 4 * al((size_t)NC * 4) + al((size_t)NS * 4);      // counts, cursor, hist x2, cell_start
     bytes += 2 * al(T * 4) + 3 * al(S * 4) + al((S + 1) * 4);  // tiles, strategy/need/qcount, qpre
-    bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4) + al(4 * 4);
+    bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4) + al(4 * 4) + al(S * 3 * 8);
     if (hipMalloc(&b->arena, bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete b;
@@ -636,7 +685,17 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     a.features = (float *)take(S * NNC_FEATURES * 4);
     a.params = (const float *)take(NNC_SELECTOR_PARAMS * 4);
     a.tdev = (int *)take(4 * 4);
+    unsigned long long *cost = (unsigned long long *)take(S * 3 * 8);
+    a.cost = (cfg->flags & NNC_BATCH_TIMING) ? cost : nullptr;
     a.scenes = b->S;
+    b->arena_bytes = bytes;
+    b->tick_us = 0.01;
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            b->tick_us = 1e3 / (double)khz;
+    }
     a.guard = b->guard;
     a.K = b->K;
     int rc = NNC_OK;
@@ -794,6 +853,10 @@ int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)
     std::vector<nnc::DevScalars> sc(b->S);
     std::vector<int> strat(b->S);
     std::vector<float> feat((size_t)b->S * NNC_FEATURES);
+    std::vector<unsigned long long> cost(b->a.cost ? (size_t)b->S * 3 : 0);
+    if (b->a.cost && hipMemcpyAsync(cost.data(), b->a.cost, cost.size() * 8, hipMemcpyDeviceToHost, b->stream) !=
+                         hipSuccess)
+        return NNC_E_HIP;
     int tdev = 0;
     if (hipMemcpyAsync(sc.data(), b->a.sc, b->S * sizeof(nnc::DevScalars), hipMemcpyDeviceToHost, b->stream) !=
             hipSuccess ||
@@ -822,8 +885,58 @@ int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)
                                                : NNC_E_DEVICE;
         if (o.err != NNC_OK && rc == NNC_OK) rc = o.err;
         for (int k = 0; k < NNC_FEATURES; ++k) o.features[k] = feat[(size_t)s * NNC_FEATURES + k];
+        o.t_filter_us = cost.empty() ? -1.0 : (double)cost[3 * (size_t)s] * b->tick_us;
+        o.t_grid_us = cost.empty() ? -1.0 : (double)cost[3 * (size_t)s + 1] * b->tick_us;
+        o.t_query_us = cost.empty() ? -1.0 : (double)cost[3 * (size_t)s + 2] * b->tick_us;
     }
     return rc;
+}
+
+struct nnc_batch_snap {
+    size_t bytes;
+    void *dev;
+};
+
+int nnc_batch_snapshot(nnc_batch *b, nnc_batch_snap **out)
+{
+    if (!b || !out) return NNC_E_INVAL;
+    *out = nullptr;
+    nnc_batch_snap *sn = new (std::nothrow) nnc_batch_snap();
+    if (!sn) return NNC_E_NOMEM;
+    sn->bytes = b->arena_bytes;
+    if (hipMalloc(&sn->dev, sn->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete sn;
+        return NNC_E_NOMEM;
+    }
+    if (hipMemcpyAsync(sn->dev, b->arena, sn->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess) {
+        (void)hipFree(sn->dev);
+        delete sn;
+        return NNC_E_HIP;
+    }
+    *out = sn;
+    return NNC_OK;
+}
+
+int nnc_batch_snapshot_update(nnc_batch *b, nnc_batch_snap *sn)
+{
+    if (!b || !sn || sn->bytes != b->arena_bytes) return NNC_E_INVAL;
+    return hipMemcpyAsync(sn->dev, b->arena, sn->bytes, hipMemcpyDeviceToDevice, b->stream) == hipSuccess ? NNC_OK
+                                                                                                        : NNC_E_HIP;
+}
+
+int nnc_batch_restore(nnc_batch *b, const nnc_batch_snap *sn)
+{
+    if (!b || !sn || sn->bytes != b->arena_bytes) return NNC_E_INVAL;
+    return hipMemcpyAsync(b->arena, sn->dev, sn->bytes, hipMemcpyDeviceToDevice, b->stream) == hipSuccess ? NNC_OK
+                                                                                                        : NNC_E_HIP;
+}
+
+void nnc_batch_snap_free(nnc_batch_snap *sn)
+{
+    if (!sn) return;
+    (void)hipFree(sn->dev);
+    delete sn;
 }
 
 int nnc_batch_get_state(nnc_batch *b, nnc_state *v)

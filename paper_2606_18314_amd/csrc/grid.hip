@@ -63,6 +63,11 @@ constexpr unsigned kSpinLimit = 1u << 24;
 // (measured); initialisation has no certificates and tiles from 2^16.
 constexpr long long kTiledMinN = 65536;
 constexpr long long kTiledMinNRebuild2 = 1 << 17, kTiledMinNRebuild3 = 1 << 19;
+// repairs go to the cell-tiled query of the marked candidates only under
+// NNC_QUERY_TILED: measured at N = 2^20 in the plane it beats the pointwise repair
+// only above about 40 % candidates (0.125 against 0.145 ms at 50 %) and loses below
+// (5 %: 0.090 against 0.026 ms; the staged neighbourhood serves a dozen candidates
+// per tile), and its launches cost about 18 us when the device-side gate skips it
 constexpr int kEntropyOneGroup4 = 1 << 15;  // histograms up to 2^17 cells: one-workgroup entropy
 constexpr int kIngestBlocks = 4096;  // at most 64 workgroups per spread slot
 
@@ -332,27 +337,44 @@ __global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restri
 }
 
 // Reduce-then-scan filter for large N (no chain between tiles): k_filter_count
-// advances the clock and counts each tile's candidates, k_filter_offsets scans
-// the counts in one workgroup, k_filter_write re-reads the keys and writes each
-// tile's candidates at its offset, in index order.
+// advances the clock, stores each tile's candidate ballots (one bit per point)
+// and counts them, k_filter_offsets scans the counts in one workgroup,
+// k_filter_write reads the ballots back (not the keys) and writes each tile's
+// candidates at its offset, in index order.  The fail flags are cleared over the
+// previous step's candidates (the only ones its repair could set) unless the host
+// asks for all of them (after a rebuild, a caller's list or a restore).
 constexpr int kFRows = 16;                // items per thread in the counting tiles
 constexpr int kFTile = kB * kFRows;       // 4096 items per tile
+constexpr int kFMasks = kFRows * (kB / 64);  // ballot words per tile
 
 __global__ void __launch_bounds__(kB) k_filter_count(const double *__restrict__ e, int n, DevScalars *sc, int parity,
                                                      float eps_decl, uint8_t *__restrict__ fail,
-                                                     int *__restrict__ tcount)
+                                                     int *__restrict__ tcount, unsigned long long *__restrict__ fmask,
+                                                     int clear_all, const int *__restrict__ prev_list)
 {
     __shared__ int s_w[kB / 64];
     const double St = advance_clock(sc, parity, eps_decl, blockIdx.x == 0 && threadIdx.x < 64);
     const long long base = (long long)blockIdx.x * kFTile;
+    const int w = (int)(threadIdx.x >> 6);
     int c = 0;
+    if (!clear_all) {
+        const int prev = min(sc->nfront, n);  // the count is rewritten only by the next kernel
+        for (int q = blockIdx.x * kB + (int)threadIdx.x; q < prev; q += gridDim.x * kB) {
+            const int i = prev_list[q];
+            if (i >= 0 && i < n) fail[i] = 0;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
         const long long i = base + (long long)k * kB + threadIdx.x;
+        bool cand = false;
         if (i < n) {
-            c += St >= e[i] ? 1 : 0;
-            fail[i] = 0;
+            cand = St >= e[i];
+            if (clear_all) fail[i] = 0;
         }
+        const unsigned long long m = __ballot(cand);
+        if (lane_id() == 0) fmask[(long long)blockIdx.x * kFMasks + k * (kB / 64) + w] = m;
+        c += cand ? 1 : 0;
     }
     c = wave_sum(c);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = c;
@@ -379,20 +401,18 @@ __global__ void __launch_bounds__(1024) k_filter_offsets(int *__restrict__ tcoun
     if (threadIdx.x == 0) sc->nfront = run;
 }
 
-__global__ void __launch_bounds__(kB) k_filter_write(const double *__restrict__ e, int n, const DevScalars *sc,
-                                                     int parity, const int *__restrict__ toff,
-                                                     int *__restrict__ frontier, unsigned *err)
+__global__ void __launch_bounds__(kB) k_filter_write(int n, const unsigned long long *__restrict__ fmask,
+                                                     const int *__restrict__ toff, int *__restrict__ frontier,
+                                                     unsigned *err)
 {
     __shared__ int s_cnt[kFRows][kB / 64];
-    const double St = sc->S[parity];
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
     const long long base = (long long)blockIdx.x * kFTile;
     unsigned long long masks[kFRows];
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
-        const long long i = base + (long long)k * kB + threadIdx.x;
-        masks[k] = __ballot(i < n && St >= e[i]);
+        masks[k] = fmask[(long long)blockIdx.x * kFMasks + k * (kB / 64) + w];
         if (lane == 0) s_cnt[k][w] = __popcll(masks[k]);
     }
     __syncthreads();
@@ -546,6 +566,7 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
     const bool pre = !a.all && q < a.list_cap;
     const int i_pre = pre ? a.list[q] : 0;
     const int count = a.all ? a.n : min(*a.count_dev, a.n);
+    if (a.tiled_from > 0 && count >= a.tiled_from) return;  // the tiled repair takes this list
     const double St = a.sc->S[a.parity];
     const double margin = query_margin(St, a.sc->S_grid, a.fuzz);
     for (bool first = true; q < count; q += gridDim.x * GPB, first = false)
@@ -582,6 +603,7 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                                                      int *__restrict__ wide, int4 *__restrict__ rec)
 {
     constexpr int RMAX = D == 3 ? 3 * (kTYMax + 2) : kTYMax + 2;
+    if (a.cmask && min(*a.count_dev, a.n) < a.tiled_from) return;  // a short list: the pointwise repair
     __shared__ float4 s_p[kNbMax];  // x, y, z (0 in the plane), point index bits
     __shared__ int s_cs[kCsMax];
     __shared__ int s_lo[RMAX], s_off[RMAX + 1], s_qoff[kTYMax + 1];
@@ -620,6 +642,23 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         s_qoff[ty] = q;
     }
     __syncthreads();
+    if (a.cmask) {
+        // repair of the marked candidates only: nothing to do in a tile without one
+        __shared__ int s_any;
+        if (threadIdx.x == 0) s_any = 0;
+        __syncthreads();
+        const int qt = s_qoff[ty];
+        int j0 = 0, any = 0;
+        for (int qq = (int)threadIdx.x; qq < qt; qq += kTB) {
+            while (s_qoff[j0 + 1] <= qq) ++j0;
+            const int kq = kbase + 1 + j0;
+            const int slot = s_cs[kq * w1 + gx0 - gl] + (qq - s_qoff[j0]);  // still slot numbers here
+            any |= a.cmask[slot];
+        }
+        if (any) s_any = 1;
+        __syncthreads();
+        if (!s_any) return;
+    }
     const int total = s_off[R];
     const bool staged = total <= kNbMax;
     // slot of LDS entry m of row k: s_lo[k] + (m - s_off[k]); cell starts become LDS positions
@@ -642,6 +681,10 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
         const int kq = kbase + 1 + j;
         const int q = s_cs[kq * w1 + gx0 - gl] + (qq - s_qoff[j]);  // LDS position
         const int slot = s_lo[kq] + (q - s_off[kq]);
+        if (a.cmask) {
+            if (!a.cmask[slot]) continue;
+            a.cmask[slot] = 0;
+        }
         float x, y, z = 0.0f;
         int i;
         if (staged) {
@@ -707,10 +750,27 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                 wide[at] = i;
             else
                 atomicOr(&a.sc->err, kErrOverflow);
-            rec[slot] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
+            if (!a.cmask) rec[slot] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
+        } else if (a.cmask) {
+            write_certificate(a, i, t, St, a.nn[i], -1);      // a repaired candidate, in place
         } else {
             rec[slot] = make_int4(t.nn, __float_as_int(t.s1), __float_as_int(t.s2), 1);
         }
+    }
+}
+
+// Candidates of a repair list marked in slot order for the tiled repair (when the
+// list is long enough for it); resets the widening count.
+__global__ void __launch_bounds__(kB) k_cand_mask(const int *__restrict__ list, const int *__restrict__ count_dev,
+                                                  int n, int tiled_from, const int *__restrict__ rank,
+                                                  uint8_t *__restrict__ cmask, DevScalars *sc)
+{
+    const int count = min(*count_dev, n);
+    if (count < tiled_from) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->nwide = 0;
+    for (int q = blockIdx.x * kB + (int)threadIdx.x; q < count; q += gridDim.x * kB) {
+        const int i = list[q];
+        if (i >= 0 && i < n) cmask[rank[i]] = 1;
     }
 }
 
@@ -1065,11 +1125,14 @@ int launch_filter(nnc_ctx *c, float eps_declared)
     if (c->n > (int64_t)kReduceScanMinN) {
         const int tiles = blocks_for(c->n, kFTile);
         if (tiles + 1 > c->ntcount) return NNC_E_INVAL;
+        if ((long long)tiles * kFMasks > c->nfmask) return NNC_E_INVAL;
         hipLaunchKernelGGL(k_filter_count, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n, c->sc, parity,
-                           eps_declared, c->fail, c->tcount);
+                           eps_declared, c->fail, c->tcount, c->fmask, c->fail_dirty ? 1 : 0,
+                           (const int *)c->frontier);
         hipLaunchKernelGGL(k_filter_offsets, dim3(1), dim3(1024), 0, c->stream, c->tcount, tiles, c->sc);
-        hipLaunchKernelGGL(k_filter_write, dim3(tiles), dim3(kB), 0, c->stream, c->e, (int)c->n,
-                           (const DevScalars *)c->sc, parity, (const int *)c->tcount, c->frontier, &c->sc->err);
+        hipLaunchKernelGGL(k_filter_write, dim3(tiles), dim3(kB), 0, c->stream, (int)c->n,
+                           (const unsigned long long *)c->fmask, (const int *)c->tcount, c->frontier, &c->sc->err);
+        c->fail_dirty = 0;
         return check();
     }
     // one workgroup only for small scenes: above two tiles the look-back version,
@@ -1153,6 +1216,9 @@ QueryArgs query_args(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, 
     a.d2 = c->d2;
     a.e = c->e;
     a.Si = c->Si;
+    a.cmask = nullptr;
+    a.qkey = nullptr;
+    a.tiled_from = 0;
     a.fail = c->fail;
     a.sc = c->sc;
     a.guard = c->guard;
@@ -1180,25 +1246,14 @@ void launch_pointwise(nnc_ctx *c, const QueryArgs &a)
 
 }  // namespace
 
-int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init)
-{
-    if (c->n == 0) return NNC_OK;
-    launch_pointwise(c, query_args(c, list, count_dev, all, init));
-    return check();
-}
+namespace {
 
-// All points, right after a grid build: tiled (then the widening pass over the
-// points it left), or pointwise.
-int launch_query_all(nnc_ctx *c, int init)
+// Tile shape of the cell-tiled queries: the most queries per staged neighbour at
+// the mean occupancy, within the LDS stage and the cell-start table.
+void tile_shape(const nnc_ctx *c, int &TX, int &TY)
 {
-    if (c->n == 0) return NNC_OK;
-    const long long from = init ? kTiledMinN : c->d == 3 ? kTiledMinNRebuild3 : kTiledMinNRebuild2;
-    const bool tiled = (c->flags & NNC_QUERY_TILED) || (!(c->flags & NNC_QUERY_POINTWISE) && c->n >= from);
-    if (!tiled) return launch_query(c, nullptr, nullptr, 1, init);
-    // tile shape: the most queries per staged neighbour at the mean occupancy,
-    // within the LDS stage and the cell-start table
     const double occ = (double)c->n / (double)c->ncell > 1.0 ? (double)c->n / (double)c->ncell : 1.0;
-    int TX = 1, TY = 1;
+    TX = TY = 1;
     double best = -1.0;
     for (int ty = 1; ty <= kTYMax && ty <= c->G; ty *= 2) {
         const int R = c->d == 3 ? 3 * (ty + 2) : ty + 2;
@@ -1214,10 +1269,10 @@ int launch_query_all(nnc_ctx *c, int init)
             TY = ty;
         }
     }
-    const long long nsx = (c->G + TX - 1) / TX, nsy = (c->G + TY - 1) / TY;
-    const long long tiles = nsx * nsy * (c->d == 3 ? c->G : 1);
-    if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
-    const QueryArgs a = query_args(c, nullptr, nullptr, 1, init);
+}
+
+void launch_tiled(nnc_ctx *c, const QueryArgs &a, int TX, int TY, long long nsx, long long nsy, long long tiles)
+{
     const dim3 grid((unsigned)tiles), block(kTB);
     if (c->d == 2 && c->unit_box)
         hipLaunchKernelGGL((k_query_tiled<2, true>), grid, block, 0, c->stream, a, TX, TY, (int)nsx, (int)nsy, c->wide,
@@ -1231,6 +1286,65 @@ int launch_query_all(nnc_ctx *c, int init)
     else
         hipLaunchKernelGGL((k_query_tiled<3, false>), grid, block, 0, c->stream, a, TX, TY, (int)nsx, (int)nsy, c->wide,
                            c->rec);
+}
+
+}  // namespace
+
+int tiled_repair_from(const nnc_ctx *c)
+{
+    return (c->flags & NNC_QUERY_TILED) && !(c->flags & NNC_QUERY_POINTWISE) ? 1 : 0;
+}
+
+int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init, double *qkey)
+{
+    if (c->n == 0) return NNC_OK;
+    // a long repair list of a large scene: the cell-tiled query of the marked candidates
+    // (the device picks it from the list's length: both launches check the count)
+    const bool split = !all && !init && list && tiled_repair_from(c) > 0;
+    if (!split) {
+        QueryArgs a = query_args(c, list, count_dev, all, init);
+        a.qkey = all ? nullptr : qkey;
+        launch_pointwise(c, a);
+        return check();
+    }
+    const int from = tiled_repair_from(c);
+    int TX, TY;
+    tile_shape(c, TX, TY);
+    const long long nsx = (c->G + TX - 1) / TX, nsy = (c->G + TY - 1) / TY;
+    const long long tiles = nsx * nsy * (c->d == 3 ? c->G : 1);
+    if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
+    const int mb = blocks_for(c->n, kB) < 4096 ? blocks_for(c->n, kB) : 4096;
+    hipLaunchKernelGGL(k_cand_mask, dim3(mb), dim3(kB), 0, c->stream, list, count_dev, (int)c->n, from, c->grid.rank,
+                       c->cmask, c->sc);
+    QueryArgs a = query_args(c, list, count_dev, 0, 0);
+    a.cmask = c->cmask;
+    a.tiled_from = from;
+    launch_tiled(c, a, TX, TY, nsx, nsy, tiles);
+    a.cmask = nullptr;
+    a.qkey = qkey;
+    launch_pointwise(c, a);   // the short lists
+    // points of the tiled repair whose search must widen (none when it did not run)
+    QueryArgs w = query_args(c, c->wide, &c->sc->nwide, 0, 0);
+    w.tiled_from = 0;
+    launch_pointwise(c, w);
+    return check();
+}
+
+// All points, right after a grid build: tiled (then the widening pass over the
+// points it left), or pointwise.
+int launch_query_all(nnc_ctx *c, int init)
+{
+    if (c->n == 0) return NNC_OK;
+    const long long from = init ? kTiledMinN : c->d == 3 ? kTiledMinNRebuild3 : kTiledMinNRebuild2;
+    const bool tiled = (c->flags & NNC_QUERY_TILED) || (!(c->flags & NNC_QUERY_POINTWISE) && c->n >= from);
+    if (!tiled) return launch_query(c, nullptr, nullptr, 1, init, nullptr);
+    int TX, TY;
+    tile_shape(c, TX, TY);
+    const long long nsx = (c->G + TX - 1) / TX, nsy = (c->G + TY - 1) / TY;
+    const long long tiles = nsx * nsy * (c->d == 3 ? c->G : 1);
+    if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
+    const QueryArgs a = query_args(c, nullptr, nullptr, 1, init);
+    launch_tiled(c, a, TX, TY, nsx, nsy, tiles);
     hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, a, c->grid.rank,
                        (const int4 *)c->rec);
     launch_pointwise(c, query_args(c, c->wide, &c->sc->nwide, 0, init));

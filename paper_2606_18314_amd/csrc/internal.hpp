@@ -134,7 +134,8 @@ struct nnc_ctx {
     int32_t *last_move;           // per cell: last step a moving point left or entered it
     // expiry calendar queue (NNC_QUEUE)
     nnc::QHead *qh;
-    int32_t *q_pool, *q_nruns, *q_run_start, *q_run_len, *q_bcnt, *q_cursor, *q_qa, *q_keep;
+    int32_t *q_pool, *q_nruns, *q_run_start, *q_run_len, *q_bcnt, *q_cursor, *q_keep;
+    double *q_pool_e, *q_keep_e, *q_key;  // keys beside the pool and keep entries; new keys in list order
     int q_cap;
     int queue_valid;              // host: the calendar holds every current key
     unsigned long long *status;   // look-back tile descriptors
@@ -145,9 +146,13 @@ struct nnc_ctx {
     // the tiled pass's results in slot order (nn, d1, d2 bits, done flag)
     int32_t *wide;
     int4 *rec;
+    uint8_t *cmask;               // tiled repair: candidates marked in slot order (all zero between repairs)
     // reduce-then-scan filter: candidates per tile, then their offsets
     int32_t *tcount;
     int ntcount;
+    unsigned long long *fmask;    // its candidate ballots, one bit per point
+    long long nfmask;
+    int fail_dirty;               // host: fail flags may be set outside the last candidate list
     double *ent_part;             // partial sums of the split entropy reduction
     double *shape_part;           // partial sums of the gyration (4 per workgroup), then the centroid
     // audit scratch
@@ -189,7 +194,11 @@ int launch_filter(nnc_ctx *c, float eps_declared);
 // from_slots: the slot records hold every point's current coordinates (any build
 // after the first), and the scatter reads them in their previous order
 int launch_grid_build(nnc_ctx *c, const float *pos, bool from_slots);
-int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init);
+// qkey: with a list, the new key of entry q is also written at qkey[q] (the expiry
+// calendar's filing), unless the tiled repair takes the list
+int launch_query(nnc_ctx *c, const int32_t *list, const int32_t *count_dev, int all, int init, double *qkey);
+// the list length from which a repair goes to the cell-tiled query (0: never)
+int tiled_repair_from(const nnc_ctx *c);
 int launch_query_all(nnc_ctx *c, int init);
 int launch_entropy(nnc_ctx *c, int which);
 int launch_cand_hist(nnc_ctx *c);

@@ -294,6 +294,10 @@ struct QueryArgs {
     float *d1, *d2;
     double *e;
     double *Si;                // clock of each certificate (a single scene; null in a batch)
+    uint8_t *cmask;            // tiled repair: candidates marked in slot order (cleared as read); else null
+    double *qkey;              // expiry calendar: new key of list entry q written at qkey[q]; else null
+    int tiled_from;            // > 0: candidate lists of at least this many entries go to the tiled
+                               // repair (the pointwise query then skips them); 0: no such split
     uint8_t *fail;
     DevScalars *sc;
     double guard, K;
@@ -766,14 +770,15 @@ __device__ __forceinline__ double query_margin(double St, double S_grid, double 
 // neighbour): distances, expiry key, stamp, failure flag, failure histogram (and,
 // for a batch scene, its failure count and touched-cell list).  cell: the point's
 // current cell id, or -1 to read it.
-__device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old,
-                                                 int cell)
+__device__ __forceinline__ double write_certificate(const QueryArgs &a, int i, const Top2 &t, double St, int old,
+                                                   int cell)
 {
     const float d1 = cert_sqrt(t.s1), d2 = cert_sqrt(t.s2);
+    const double key = expiry(St, d1, d2, a.guard, a.K);
     a.nn[i] = t.nn;
     a.d1[i] = d1;
     a.d2[i] = d2;
-    a.e[i] = expiry(St, d1, d2, a.guard, a.K);
+    a.e[i] = key;
     if (a.Si) a.Si[i] = St;
     a.stamp[i] = a.t;
     const bool f = !a.init && t.nn != old;
@@ -781,7 +786,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
     if (a.touched == nullptr) {
         // histogram only (the entropy scans it): no shared counters
         if (f) atomicAdd(&a.hist[cell >= 0 ? cell : a.cell[i]], 1);
-        return;
+        return key;
     }
     // failure count and first touch of each cell: one counter atomic per wave
     const unsigned long long fm = __ballot(f);
@@ -796,6 +801,7 @@ __device__ __forceinline__ void write_certificate(const QueryArgs &a, int i, con
         const int at = wave_append(&a.sc->ntouched, first);
         if (first) a.touched[at] = c;
     }
+    return key;
 }
 
 // First-pass cut-off of a query (repair or rebuild) from the point's previous certificate
@@ -857,7 +863,10 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
     Top2 t;
     t.init();
     const int cell = group_search<D, L, UNIT>(a, x, y, z, i, margin, T, lane, t);
-    if (lane == 0) write_certificate(a, i, t, St, old, cell);
+    if (lane == 0) {
+        const double key = write_certificate(a, i, t, St, old, cell);
+        if (a.qkey && !a.all) a.qkey[q] = key;
+    }
 }
 
 // Selector features of one scene-step (the same six numbers for a single scene

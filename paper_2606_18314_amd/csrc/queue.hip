@@ -26,10 +26,13 @@
 //                  smallest key;
 //   k_q_file_runs  one workgroup: each bucket's new run in the pool;
 //   k_q_file_put   the items written into their runs.
-// Candidates come out in bucket order, not in index order.  A bucket is emptied
-// when it is popped; an entry is valid only while the point's filed bucket (qa)
-// is that bucket, which guards against entries left by a forced repair (the host
-// rebuilds the calendar after one anyway).
+// Every entry carries its point's key, and the repair writes the new keys in
+// list order (beside the candidate list), so pops and filings read and write
+// contiguous runs and never gather keys by point index (except after a tiled
+// repair, whose keys are read from the state).  Candidates come out in bucket
+// order, not in index order.  A bucket is emptied when it is popped and every
+// point is filed exactly once between builds (the host rebuilds the calendar
+// after anything that changes keys of points that were not popped).
 #include <math.h>
 
 #include "device_common.hpp"
@@ -57,14 +60,51 @@ __device__ __forceinline__ int file_bucket(double e, double W, long long a_epoch
     return (int)a;
 }
 
-// Point of filing item q: every point for a rebuild (mode 1), else the candidates
-// then the kept entries.  -1 past the end.
-__device__ __forceinline__ int file_item(int q, int mode, int n, int nf, const int *frontier, int nk,
-                                         const int *keep)
+// Point and key of filing item q: every point for a rebuild (mode 1), else the
+// candidates (their new keys in list order, or from the state after a tiled
+// repair) then the kept entries.  Point -1 past the end.
+struct FileArgs {
+    int mode, n, nf, nk;
+    bool keys_in_list;
+    const int *frontier, *keep;
+    const double *e, *qkey, *keep_e;
+};
+
+__device__ __forceinline__ int file_item(int q, const FileArgs &f, double &key)
 {
-    if (mode) return q < n ? q : -1;
-    if (q < nf) return frontier[q];
-    return q - nf < nk ? keep[q - nf] : -1;
+    if (f.mode) {
+        if (q >= f.n) return -1;
+        key = f.e[q];
+        return q;
+    }
+    if (q < f.nf) {
+        const int i = f.frontier[q];
+        key = f.keys_in_list ? f.qkey[q] : (i >= 0 && i < f.n ? f.e[i] : 0.0);
+        return i;
+    }
+    if (q - f.nf < f.nk) {
+        key = f.keep_e[q - f.nf];
+        return f.keep[q - f.nf];
+    }
+    return -1;
+}
+
+__device__ __forceinline__ FileArgs file_args(const QHead *qh, const DevScalars *sc, int n, int tiled_from,
+                                              const int *frontier, const int *keep, const double *e,
+                                              const double *qkey, const double *keep_e)
+{
+    FileArgs f;
+    f.mode = qh->mode;
+    f.n = n;
+    f.nf = sc->nfront;
+    f.nk = qh->nkeep;
+    f.keys_in_list = !(tiled_from > 0 && min(f.nf, n) >= tiled_from);
+    f.frontier = frontier;
+    f.keep = keep;
+    f.e = e;
+    f.qkey = qkey;
+    f.keep_e = keep_e;
+    return f;
 }
 
 __global__ void __launch_bounds__(kQB) k_q_clear(const int *__restrict__ frontier, const int *__restrict__ count,
@@ -84,9 +124,9 @@ __global__ void __launch_bounds__(kQB) k_q_clear(const int *__restrict__ frontie
 
 // One chunk of up to kQB entries (i < 0: none) through the workgroup: due entries
 // appended to the candidates, kept ones to the keep list, one atomic each.
-__device__ __forceinline__ void append_chunk(int i, bool due, bool kp, int n, QHead *qh, int parity,
-                                             int *__restrict__ frontier, int *__restrict__ keep, DevScalars *sc,
-                                             int *s_w, int *s_base)
+__device__ __forceinline__ void append_chunk(int i, double key, bool due, bool kp, int n, QHead *qh, int parity,
+                                             int *__restrict__ frontier, int *__restrict__ keep,
+                                             double *__restrict__ keep_e, DevScalars *sc, int *s_w, int *s_base)
 {
     int tot;
     const int ex = block_excl_scan<kQB>((due ? 1 : 0) + (kp ? 0x10000 : 0), s_w, tot);
@@ -102,17 +142,22 @@ __device__ __forceinline__ void append_chunk(int i, bool due, bool kp, int n, QH
     }
     if (kp) {
         const int at = s_base[1] + (ex >> 16);
-        if (at < n) keep[at] = i;
-        else atomicOr(&sc->err, kErrOverflow);
+        if (at < n) {
+            keep[at] = i;
+            keep_e[at] = key;
+        } else {
+            atomicOr(&sc->err, kErrOverflow);
+        }
     }
     __syncthreads();
 }
 
 __global__ void __launch_bounds__(kQB) k_q_pop(const double *__restrict__ e, int n, DevScalars *sc, int parity,
                                                float eps_decl, QHead *qh, const int *__restrict__ pool,
-                                               const int *__restrict__ nruns, const int *__restrict__ run_start,
-                                               const int *__restrict__ run_len, const int *__restrict__ qa,
-                                               int *__restrict__ frontier, int *__restrict__ keep)
+                                               const double *__restrict__ pool_e, const int *__restrict__ nruns,
+                                               const int *__restrict__ run_start, const int *__restrict__ run_len,
+                                               int *__restrict__ frontier, int *__restrict__ keep,
+                                               double *__restrict__ keep_e)
 {
     __shared__ int s_w[kQB / 64];
     __shared__ int s_base[2];
@@ -130,7 +175,7 @@ __global__ void __launch_bounds__(kQB) k_q_pop(const double *__restrict__ e, int
         for (int base = blockIdx.x * kQB; base < n; base += gridDim.x * kQB) {
             const int i = base + (int)threadIdx.x;
             const bool due = i < n && St >= e[i];
-            append_chunk(i, due, false, n, qh, parity, frontier, keep, sc, s_w, s_base);
+            append_chunk(i, 0.0, due, false, n, qh, parity, frontier, keep, keep_e, sc, s_w, s_base);
         }
         return;
     }
@@ -151,15 +196,17 @@ __global__ void __launch_bounds__(kQB) k_q_pop(const double *__restrict__ e, int
                 read += (unsigned long long)min(kQB, len - off);
                 const int q = off + (int)threadIdx.x;
                 int i = -1;
+                double key = 0.0;
                 bool due = false, kp = false;
                 if (q < len) {
                     i = pool[st + q];
-                    if (i >= 0 && i < n && qa[i] == a) {
-                        due = St >= e[i];
+                    key = pool_e[st + q];
+                    if (i >= 0 && i < n) {
+                        due = St >= key;
                         kp = !due;
                     }
                 }
-                append_chunk(i, due, kp, n, qh, parity, frontier, keep, sc, s_w, s_base);
+                append_chunk(i, key, due, kp, n, qh, parity, frontier, keep, keep_e, sc, s_w, s_base);
             }
         }
     }
@@ -220,13 +267,14 @@ __global__ void __launch_bounds__(kQB) k_q_file_begin(const DevScalars *sc, QHea
 }
 
 __global__ void __launch_bounds__(kQB) k_q_file_count(const double *__restrict__ e, int n,
-                                                      const DevScalars *__restrict__ sc, QHead *qh,
+                                                      const DevScalars *__restrict__ sc, QHead *qh, int tiled_from,
                                                       const int *__restrict__ frontier, const int *__restrict__ keep,
-                                                      int *__restrict__ qa, int *__restrict__ bcnt)
+                                                      const double *__restrict__ qkey,
+                                                      const double *__restrict__ keep_e, int *__restrict__ bcnt)
 {
     __shared__ int s_h[kQAhead];
-    const int mode = qh->mode, nf = sc->nfront, nk = qh->nkeep;
-    const int items = mode ? n : nf + nk;
+    const FileArgs fa = file_args(qh, sc, n, tiled_from, frontier, keep, e, qkey, keep_e);
+    const int items = fa.mode ? n : fa.nf + fa.nk;
     const double W = qh->W;
     const long long a_ep = qh->a_epoch;
     const int a_hi = qh->a_hi;
@@ -235,11 +283,10 @@ __global__ void __launch_bounds__(kQB) k_q_file_count(const double *__restrict__
     double fmin_local = __builtin_inf();
     int nfar = 0;
     for (int q = blockIdx.x * kQB + (int)threadIdx.x; q < items; q += gridDim.x * kQB) {
-        const int i = file_item(q, mode, n, nf, frontier, nk, keep);
+        double ei = 0.0;
+        const int i = file_item(q, fa, ei);
         if (i < 0 || i >= n) continue;
-        const double ei = e[i];
         const int b = file_bucket(ei, W, a_ep, a_hi);
-        qa[i] = b >= 0 ? b : -1;
         if (b >= 0) {
             atomicAdd(&s_h[b - a_hi], 1);
         } else if (b == -1) {
@@ -290,24 +337,29 @@ __global__ void __launch_bounds__(kQB) k_q_file_runs(QHead *qh, int cap, int *__
     if (threadIdx.x == 0) qh->pool_top = top + run;
 }
 
-__global__ void __launch_bounds__(kQB) k_q_file_put(int n, const DevScalars *__restrict__ sc,
-                                                    const QHead *__restrict__ qh, const int *__restrict__ frontier,
-                                                    const int *__restrict__ keep, const int *__restrict__ qa,
-                                                    int *__restrict__ cursor, int *__restrict__ pool, int cap)
+__global__ void __launch_bounds__(kQB) k_q_file_put(const double *__restrict__ e, int n,
+                                                    const DevScalars *__restrict__ sc, const QHead *__restrict__ qh,
+                                                    int tiled_from, const int *__restrict__ frontier,
+                                                    const int *__restrict__ keep, const double *__restrict__ qkey,
+                                                    const double *__restrict__ keep_e, int *__restrict__ cursor,
+                                                    int *__restrict__ pool, double *__restrict__ pool_e, int cap)
 {
     __shared__ int s_c[kQAhead];
     __shared__ int s_base[kQAhead];
-    const int mode = qh->mode, nf = sc->nfront, nk = qh->nkeep;
-    const int items = mode ? n : nf + nk;
+    const FileArgs fa = file_args(qh, sc, n, tiled_from, frontier, keep, e, qkey, keep_e);
+    const int items = fa.mode ? n : fa.nf + fa.nk;
+    const double W = qh->W;
+    const long long a_ep = qh->a_epoch;
     const int a_hi = qh->a_hi;
     for (int base = blockIdx.x * kQB; base < items; base += gridDim.x * kQB) {
         for (int k = threadIdx.x; k < kQAhead; k += kQB) s_c[k] = 0;
         __syncthreads();
         const int q = base + (int)threadIdx.x;
-        int i = q < items ? file_item(q, mode, n, nf, frontier, nk, keep) : -1;
+        double key = 0.0;
+        const int i = q < items ? file_item(q, fa, key) : -1;
         int b = -1, rank = 0;
         if (i >= 0 && i < n) {
-            b = qa[i];
+            b = file_bucket(key, W, a_ep, a_hi);
             if (b >= 0) rank = atomicAdd(&s_c[b - a_hi], 1);
         }
         __syncthreads();
@@ -323,7 +375,10 @@ __global__ void __launch_bounds__(kQB) k_q_file_put(int n, const DevScalars *__r
         __syncthreads();
         if (b >= 0) {
             const int at = s_base[b - a_hi];
-            if (at >= 0 && at + rank < cap) pool[at + rank] = i;
+            if (at >= 0 && at + rank < cap) {
+                pool[at + rank] = i;
+                pool_e[at + rank] = key;
+            }
         }
         __syncthreads();
     }
@@ -342,7 +397,8 @@ int launch_queue_pop(nnc_ctx *c, float eps_declared)
     hipLaunchKernelGGL(k_q_clear, dim3(clear_blocks), dim3(kQB), 0, c->stream, c->frontier, &c->sc->nfront, n, c->fail,
                        c->qh, parity);
     hipLaunchKernelGGL(k_q_pop, dim3(kQPop), dim3(kQB), 0, c->stream, c->e, n, c->sc, parity, eps_declared, c->qh,
-                       c->q_pool, c->q_nruns, c->q_run_start, c->q_run_len, c->q_qa, c->frontier, c->q_keep);
+                       c->q_pool, c->q_pool_e, c->q_nruns, c->q_run_start, c->q_run_len, c->frontier, c->q_keep,
+                       c->q_keep_e);
     hipLaunchKernelGGL(k_q_after_pop, dim3(1), dim3(kQB), 0, c->stream, c->sc, c->qh, parity, c->q_nruns);
     return check();
 }
@@ -353,12 +409,13 @@ int launch_queue_file(nnc_ctx *c, int build)
     const int n = (int)c->n;
     hipLaunchKernelGGL(k_q_file_begin, dim3(1), dim3(kQB), 0, c->stream, c->sc, c->qh, parity, build, n, c->q_cap,
                        c->q_nruns, c->q_bcnt);
-    hipLaunchKernelGGL(k_q_file_count, dim3(kQPop), dim3(kQB), 0, c->stream, c->e, n, c->sc, c->qh, c->frontier,
-                       c->q_keep, c->q_qa, c->q_bcnt);
+    const int from = tiled_repair_from(c);
+    hipLaunchKernelGGL(k_q_file_count, dim3(kQPop), dim3(kQB), 0, c->stream, c->e, n, c->sc, c->qh, from, c->frontier,
+                       c->q_keep, c->q_key, c->q_keep_e, c->q_bcnt);
     hipLaunchKernelGGL(k_q_file_runs, dim3(1), dim3(kQB), 0, c->stream, c->qh, c->q_cap, c->q_nruns, c->q_run_start,
                        c->q_run_len, c->q_bcnt, c->q_cursor, c->sc);
-    hipLaunchKernelGGL(k_q_file_put, dim3(kQPop), dim3(kQB), 0, c->stream, n, c->sc, c->qh, c->frontier, c->q_keep,
-                       c->q_qa, c->q_cursor, c->q_pool, c->q_cap);
+    hipLaunchKernelGGL(k_q_file_put, dim3(kQPop), dim3(kQB), 0, c->stream, c->e, n, c->sc, c->qh, from, c->frontier,
+                       c->q_keep, c->q_key, c->q_keep_e, c->q_cursor, c->q_pool, c->q_pool_e, c->q_cap);
     return check();
 }
 

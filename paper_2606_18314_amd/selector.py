@@ -96,6 +96,105 @@ def collect(specs, steps: int, reps: int = 2, lanes: int = 16, log=None):
     return {"X": np.array(X, np.float32), "t_repair": np.array(trep), "t_rebuild": np.array(treb)}
 
 
+WAVES_PER_WORKGROUP = 16   # the batched filter and grid build run 1024-thread workgroups
+
+
+def scene_cost(st: dict) -> float:
+    """A scene-step's strategy-dependent cost inside the batched step, in wave-microseconds:
+    its grid build's workgroup time (16 waves) plus the summed time of the query waves
+    that worked on it (the filter's work is the same for both strategies)."""
+    return WAVES_PER_WORKGROUP * st["t_grid_us"] + st["t_query_us"]
+
+
+def collect_batched(specs, steps: int, batch_size: int = 128, lanes: int = 16, log=None):
+    """Features and the in-batch costs of both strategies of every scene-step.
+
+    Scenes are advanced in batches with the deployment's grids (the batch tuner's
+    rule); at each step the batch state is saved, the step is run with every scene
+    repaired and again with every scene rebuilt (per-scene wall-clock accounting,
+    NNC_BATCH_TIMING), and the batch continues from the repaired step.  Returns X
+    [M,6], t_repair [M], t_rebuild [M] (wave-microseconds, see scene_cost)."""
+    import synth
+    from . import autotune
+    X, trep, treb = [], [], []
+    s = torch.cuda.Stream()
+    t0 = time.time()
+    for b0 in range(0, len(specs), batch_size):
+        chunk = specs[b0:b0 + batch_size]
+        trajs = [synth.make_trajectory(sp["family"], sp["n"], sp["d"], steps, sp["eps"], tuple(sp["seed"]))
+                 for sp in chunk]
+        ns = [t.n for t in trajs]
+        ds = [t.d for t in trajs]
+        frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 1)]
+        grids = autotune.batch_grids(frames[0], ns, ds, lanes=lanes, factor=1.5, cells_per_point=8)
+        with torch.cuda.stream(s):
+            b = binding.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream, features=True,
+                                 timing=True, eager=True)
+            b.init(frames[0])
+        snap = None
+        for t in range(1, steps + 1):
+            with torch.cuda.stream(s):
+                snap = b.snapshot(into=snap)
+                b.step(frames[t], binding.POLICY_REPAIR)
+            st_rep = b.stats()
+            with torch.cuda.stream(s):
+                b.restore(snap)
+                b.step(frames[t], binding.POLICY_REBUILD)
+            st_reb = b.stats()
+            with torch.cuda.stream(s):
+                b.restore(snap)
+                b.step(frames[t], binding.POLICY_REPAIR)
+            for a, r in zip(st_rep, st_reb):
+                X.append(a["features"])
+                trep.append(scene_cost(a))
+                treb.append(scene_cost(r))
+        del snap
+        b.close()
+        if log:
+            log(f"collected {min(b0 + batch_size, len(specs))}/{len(specs)} scenes, {len(X)} transitions, "
+                f"{time.time() - t0:.0f} s")
+    return {"X": np.array(X, np.float32), "t_repair": np.array(trep), "t_rebuild": np.array(treb)}
+
+
+def inference_cost(specs, steps: int, params: np.ndarray, tau: float, lanes: int = 16, reps: int = 3):
+    """Per scene-step cost of the learned policy's features and network inside the batched
+    filter, in wave-microseconds: the filter workgroup's time under the learned policy
+    minus its time under the size threshold (which computes no features), median over
+    steps of the mean over scenes."""
+    import synth
+    from . import autotune
+    trajs = [synth.make_trajectory(sp["family"], sp["n"], sp["d"], steps, sp["eps"], tuple(sp["seed"]))
+             for sp in specs]
+    ns = [t.n for t in trajs]
+    ds = [t.d for t in trajs]
+    frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 1)]
+    grids = autotune.batch_grids(frames[0], ns, ds, lanes=lanes, factor=1.5, cells_per_point=8)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = binding.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream, timing=True, eager=True)
+        b.selector_load(torch.from_numpy(params.astype(np.float32)).cuda())
+        b.init(frames[0])
+    snap = None
+    diffs = []
+    for t in range(1, steps + 1):
+        f = {}
+        for _ in range(reps):
+            for pol in (binding.POLICY_THRESHOLD, binding.POLICY_LEARNED):
+                with torch.cuda.stream(s):
+                    snap = b.snapshot(into=snap) if (pol == binding.POLICY_THRESHOLD and _ == 0) else snap
+                    b.restore(snap)
+                    b.step(frames[t], pol, tau)
+                st = b.stats()
+                v = float(np.mean([x["t_filter_us"] for x in st]))
+                f[pol] = min(f.get(pol, math.inf), v)
+        diffs.append(f[binding.POLICY_LEARNED] - f[binding.POLICY_THRESHOLD])
+        with torch.cuda.stream(s):
+            b.restore(snap)
+            b.step(frames[t], binding.POLICY_REPAIR)
+    b.close()
+    return WAVES_PER_WORKGROUP * max(0.0, float(np.median(diffs)))
+
+
 def labels(t_rep, t_reb, clip: float = 10.0, floor: float = 0.05):
     y = (t_reb < t_rep).astype(np.int32)
     w = np.abs(t_rep - t_reb) / np.minimum(t_rep, t_reb)
@@ -165,8 +264,10 @@ def decide(params: np.ndarray, X: np.ndarray) -> np.ndarray:
     return (logits[:, 1] > logits[:, 0]).astype(np.int32)
 
 
-def regret(choice, t_rep, t_reb, extra_ms: float = 0.0) -> float:
-    cost = np.where(choice == 1, t_reb, t_rep) + extra_ms
+def regret(choice, t_rep, t_reb, extra: float = 0.0) -> float:
+    """Time regret against the per-step best strategy, sum T(choice) / sum min - 1; extra
+    is a per-transition cost of making the choice (features and inference)."""
+    cost = np.where(choice == 1, t_reb, t_rep) + extra
     return float(cost.sum() / np.minimum(t_rep, t_reb).sum() - 1.0)
 
 
@@ -195,6 +296,46 @@ def load_params(path: str = PARAMS_PATH):
     return p, meta
 
 
+def main_batched(args, log):
+    """Labels timed inside the batched step (collect_batched), training on the GPU
+    kernels, the threshold fitted on the same set, and on held-out scenes (other seeds)
+    the regrets with the learned policy's feature and inference cost included."""
+    train_specs = scene_specs(args.scenes, args.seed)
+    test_specs = scene_specs(max(args.scenes // 4, 32), args.seed + 4000)
+    t0 = time.time()
+    tr = collect_batched(train_specs, args.steps, log=log)
+    te = collect_batched(test_specs, args.steps, log=log)
+    log(f"{len(tr['X'])} training and {len(te['X'])} held-out transitions in {time.time() - t0:.0f} s; rebuild "
+        f"cheaper in {np.mean(tr['t_rebuild'] < tr['t_repair']):.3f} of the training ones")
+    Xtr, rtr, btr = tr["X"], tr["t_repair"], tr["t_rebuild"]
+    Xte, rte, bte = te["X"], te["t_repair"], te["t_rebuild"]
+    y, w = labels(rtr, btr)
+    t1 = time.time()
+    params = train(Xtr, y, w, epochs=args.epochs, seed=args.seed, log=log)
+    train_s = time.time() - t1
+    tau, _ = fit_threshold(Xtr, rtr, btr)
+    c_inf = inference_cost(test_specs[:64], 12, params, tau)
+    ch_net = decide(params, Xte)
+    res = {
+        "labels": "timed inside the batched step (per-scene wall-clock accounting, wave-microseconds)",
+        "transitions": int(len(Xtr) + len(Xte)), "train": int(len(Xtr)), "held_out": int(len(Xte)),
+        "train_seconds": train_s,
+        "rebuild_wins_fraction": float(np.mean(btr < rtr)),
+        "inference_wave_us_per_scene_step": c_inf,
+        "mean_best_wave_us_per_scene_step": float(np.minimum(rte, bte).mean()),
+        "regret_learned": regret(ch_net, rte, bte, c_inf),
+        "regret_learned_without_inference": regret(ch_net, rte, bte),
+        "regret_threshold": regret((Xte[:, 0] >= tau).astype(np.int32), rte, bte),
+        "regret_always_repair": regret(np.zeros(len(Xte), np.int32), rte, bte),
+        "regret_always_rebuild": regret(np.ones(len(Xte), np.int32), rte, bte),
+        "tau": tau, "accuracy_learned": float(np.mean(ch_net == (bte < rte))),
+        "specs_seed": args.seed, "held_out_seed": args.seed + 4000, "steps_per_scene": args.steps,
+        "scenes": args.scenes,
+    }
+    log(json.dumps(res))
+    save(params, res, args.out)
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser(description="collect labelled transitions and train the selector")
@@ -205,10 +346,16 @@ def main():
     ap.add_argument("--seed", type=int, default=5000)
     ap.add_argument("--holdout", type=float, default=0.2)
     ap.add_argument("--out", default=PARAMS_PATH)
+    ap.add_argument("--single-scene", action="store_true",
+                    help="label with isolated single-scene timing instead of inside the batched step")
     args = ap.parse_args()
 
     def log(msg):
         print(msg, flush=True)
+
+    if not args.single_scene:
+        main_batched(args, log)
+        return
 
     specs = scene_specs(args.scenes, args.seed)
     n_train = int(round(len(specs) * (1 - args.holdout)))

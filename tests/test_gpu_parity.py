@@ -216,6 +216,16 @@ def test_automatic_all_point_query_around_its_thresholds(nnc):
     run_parity(nnc, tr, G=187, strategy="rebuild")
 
 
+@pytest.mark.parametrize("d,eps", [(2, 1.5e-5), (2, 1e-6), (3, 6e-5)])
+def test_tiled_repair_of_long_candidate_lists(nnc, d, eps):
+    """N = 270000: candidate lists of at least N/64 entries (about 10 % here; 0.7 %
+    with the small step) are repaired by the cell-tiled query of the marked
+    candidates (the device picks it from the count), shorter ones pointwise; every
+    array against the oracle on every step."""
+    tr = synth.make_trajectory("uniform_brownian", 270000, d, 2, eps, 4600 + d)
+    run_parity(nnc, tr, G=259 if d == 2 else 40)
+
+
 @pytest.mark.parametrize("n", [(1 << 19) + 1, 3 * (1 << 20) + 4097])
 def test_large_scene_filter_compaction(nnc, n):
     """Above 2^19 points the filter counts, scans and writes in three passes: its
@@ -244,6 +254,22 @@ def test_large_scene_filter_compaction(nnc, n):
     assert fresh.any()
     assert np.array_equal(bits(host(state["d1"])[q][fresh]), bits(host(d1)[fresh]))
     assert np.array_equal(bits(host(state["d2"])[q][fresh]), bits(host(d2)[fresh]))
+    # fail flags: the filter clears those of the previous candidates (or all of them
+    # after a rebuild); afterwards only this step's candidates may carry one
+    p_prev = p1
+    for k, strategy in enumerate(("repair", "rebuild", "repair", "repair")):
+        p_next = synth.device_brownian_step(p_prev, 2e-4, seed=n + 2 + k)
+        ctx.step(p_next, -1.0)
+        cand = host(ctx.frontier_indices())
+        nn_before = host(ctx.state()["nn"])
+        ctx.repair() if strategy == "repair" else ctx.rebuild()
+        st = ctx.state()
+        failed = np.flatnonzero(host(st["fail"]))
+        if strategy == "repair":
+            assert np.all(np.isin(failed, cand)), k
+            changed = cand[host(st["nn"])[cand] != nn_before[cand]]
+            assert np.array_equal(failed, changed), k
+        p_prev = p_next
     ctx.close()
 
 
@@ -352,7 +378,7 @@ def test_queue_plane(nnc, lanes):
 
 
 def test_queue_step_sizes_that_outrun_the_ring(nnc):
-    """Steps that grow a hundredfold and shrink again: the clock runs past the ring's
+    """Steps that grow several thousandfold and shrink again: the clock runs past the ring's
     window and reaches the far set (the pop scans every key and the calendar is filed
     anew), then falls back to small steps; static frames (eps = 0) in between."""
     g = np.random.default_rng(77)
@@ -360,7 +386,7 @@ def test_queue_step_sizes_that_outrun_the_ring(nnc):
     p = g.random((d, n))
     frames = [p.copy()]
     for t in range(24):
-        scale = 1e-4 if t < 6 else (2e-2 if t < 10 else (0.0 if t in (12, 13) else 3e-4))
+        scale = 1e-5 if t < 6 else (5e-2 if t < 10 else (0.0 if t in (12, 13) else 3e-4))
         p = p + scale * g.standard_normal((d, n))
         frames.append(p.copy())
     tr = synth.Trajectory("custom", d, n, -1.0, np.array(frames, dtype=np.float32))

@@ -119,3 +119,52 @@ def test_single_scene_features(nnc):
         ctx.repair()
         sc.repair()
     ctx.close()
+
+
+def test_batch_cost_accounting_and_snapshots(nnc):
+    """Per-scene wall-clock accounting of the batched step (NNC_BATCH_TIMING): every
+    scene with queries reports query time, a grid build time exactly where a grid was
+    built; a batch snapshot restores the state bit for bit (the same step run twice
+    from it gives the same arrays)."""
+    import synth
+    from paper_2606_18314_amd import selector
+    specs = selector.scene_specs(12, seed=7400, n_hi=6000)
+    trajs = [synth.make_trajectory(sp["family"], sp["n"], sp["d"], 3, sp["eps"], tuple(sp["seed"])) for sp in specs]
+    frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(4)]
+    b = nnc.NNCBatch([t.n for t in trajs], [t.d for t in trajs], timing=True, features=True)
+    b.init(frames[0])
+    b.step(frames[1], nnc.POLICY_REPAIR)
+    snap = b.snapshot()
+    b.step(frames[2], nnc.POLICY_REBUILD)
+    st = b.stats()
+    assert all(x["t_grid_us"] > 0 and x["t_query_us"] > 0 and x["t_filter_us"] > 0 for x in st)
+    first = {k: v.clone() for k, v in b.state().items()}
+    b.restore(snap)
+    b.step(frames[2], nnc.POLICY_REBUILD)
+    again = b.state()
+    for k in first:
+        assert torch.equal(first[k], again[k]), k
+    b.restore(snap)
+    b.step(frames[2], nnc.POLICY_REPAIR)
+    st = b.stats()
+    for x in st:
+        assert x["t_query_us"] > 0 if x["n_cand"] > 0 else x["t_query_us"] >= 0
+    b.close()
+
+
+def test_trained_selector_beats_always_repair_on_held_out_transitions(nnc):
+    """The committed network (trained on transitions labelled inside the batched step)
+    against always repairing, on held-out scenes of other seeds with step sizes over a
+    decade: its time regret, with the learned policy's feature and inference cost
+    added to every transition, is lower."""
+    from paper_2606_18314_amd import selector
+    params, meta = selector.load_params()
+    assert params is not None
+    specs = selector.scene_specs(64, seed=9900)
+    data = selector.collect_batched(specs, 12)
+    X, tr, tb = data["X"], data["t_repair"], data["t_rebuild"]
+    c_inf = float(meta.get("inference_wave_us_per_scene_step", 0.0))
+    r_net = selector.regret(selector.decide(params, X), tr, tb, c_inf)
+    r_rep = selector.regret(np.zeros(len(X), np.int32), tr, tb)
+    print(f"held-out regret: learned {r_net:.4f} (inference {c_inf:.2f} wave-us), always repair {r_rep:.4f}")
+    assert r_net < r_rep
