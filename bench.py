@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--batch-tune", type=int, default=1,
                     help="1: time the batch tuner's choices; 0: use its usual choice without timing")
     ap.add_argument("--regret-scenes", type=int, default=100)
-    ap.add_argument("--regret-steps", type=int, default=110)
+    ap.add_argument("--regret-steps", type=int, default=40)
     ap.add_argument("--grid", default="table",
                     help="'table' (the committed tuning table, paper_2606_18314_amd/tuned_cube16k.json), "
                          "'auto' (tuned per family now) or an integer G for all")
@@ -169,6 +169,8 @@ def batched_leg(args, nnc, synth, autotune, torch):
             b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream)
             if pdev is not None:
                 b.selector_load(pdev)
+                band = meta.get("band", [0.0, 2.0])
+                b.selector_band(band[0], band[1])
             b.init(frames[0])
             b.step(frames[1], pol, tau)
         torch.cuda.synchronize()
@@ -269,21 +271,74 @@ def batched_leg(args, nnc, synth, autotune, torch):
     res["speedup_batched_repair_over_loop"] = res["repair"]["value"] / res["per_scene_loop"]["value"]
     if "learned" in res:
         res["speedup_learned_over_loop"] = res["learned"]["value"] / res["per_scene_loop"]["value"]
-    # selector error on freshly generated held-out transitions (seeds unseen in training)
+    # selector error on freshly generated held-out transitions (seeds unseen in training),
+    # both strategies timed inside the batched step; the learned policy's feature and
+    # network cost is charged to every transition inside its band
     if params is not None and args.regret_scenes > 0:
-        specs = selector.scene_specs(args.regret_scenes, seed=9000)
-        data = selector.collect(specs, args.regret_steps, reps=2)
+        specs = selector.scene_specs(args.regret_scenes, seed=9500)
+        data = selector.collect_batched(specs, args.regret_steps)
         X, tr_, tb_ = data["X"], data["t_repair"], data["t_rebuild"]
-        ch = selector.decide(params, X)
+        lo, hi = meta.get("band", [0.0, 2.0])
+        c_inf = float(meta.get("inference_wave_us_per_scene_step", 0.0))
+        ch, inb = selector.band_choice(X, selector.decide(params, X), lo, hi)
         res["selector"] = {
-            "transitions": int(len(X)),
-            "regret_learned": selector.regret(ch, tr_, tb_),
+            "transitions": int(len(X)), "labels": "timed inside the batched step (wave-microseconds)",
+            "regret_learned": selector.regret(ch, tr_, tb_, np.where(inb, c_inf, 0.0)),
+            "regret_learned_without_inference": selector.regret(ch, tr_, tb_),
+            "fraction_in_band": float(inb.mean()),
             "regret_threshold": selector.regret((X[:, 0] >= tau).astype(np.int32), tr_, tb_),
             "regret_always_repair": selector.regret(np.zeros(len(X), np.int32), tr_, tb_),
             "regret_always_rebuild": selector.regret(np.ones(len(X), np.int32), tr_, tb_),
             "training": meta,
         }
+        # the batched step on these mixed-step scenes under each policy (the selector's
+        # deployment workload: step sizes over a decade)
+        res["mixed_eps_batch"] = mixed_eps_batch(nnc, synth, autotune, selector, torch, params, meta, tau)
     return res
+
+
+def mixed_eps_batch(nnc, synth, autotune, selector, torch, params, meta, tau, scenes=256, steps=40):
+    """The selector's workload as one batch (N log-uniform in [500, 20000], both d, the
+    five families, eps log-uniform in [1e-4, 5e-3]): ms per step under each policy,
+    graph-captured like the 512-scene leg."""
+    specs = selector.scene_specs(scenes, seed=9700)
+    trajs = [synth.make_trajectory(sp["family"], sp["n"], sp["d"], steps + 1, sp["eps"], tuple(sp["seed"]))
+             for sp in specs]
+    ns = [t.n for t in trajs]
+    ds = [t.d for t in trajs]
+    frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 2)]
+    grids = autotune.batch_grids(frames[0], ns, ds, lanes=16, factor=1.5, cells_per_point=8)
+    s = torch.cuda.Stream()
+    pdev = torch.from_numpy(params).cuda()
+    out = {"scenes": scenes, "points": sum(ns), "steps": steps}
+    for name, pol in (("repair", 0), ("rebuild", 1), ("threshold", 2), ("learned", 3)):
+        with torch.cuda.stream(s):
+            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=16, stream=s.cuda_stream)
+            b.selector_load(pdev)
+            band = meta.get("band", [0.0, 2.0])
+            b.selector_band(band[0], band[1])
+            b.init(frames[0])
+            b.step(frames[1], pol, tau)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for t in range(2, steps + 2):
+                b.step(frames[t], pol, tau)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        with torch.cuda.stream(s):
+            g.replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = b.stats()
+        out[name] = {"ms_per_step": ms / steps, "value": sum(ns) * steps / (ms / 1e3),
+                     "last_step_rebuild_fraction": sum(x["strategy"] for x in st) / len(st)}
+        progress(f"mixed-eps batch {name}: {ms / steps:.4f} ms/step")
+        del g
+        b.close()
+    return out
 
 
 def batched_step_bytes(ns, ds, grids, stats):

@@ -253,7 +253,8 @@ int nnc_frontier_gyration(nnc_ctx *ctx, int which, double *gyration, double *cen
  * nnc_repair/nnc_rebuild); the selector predicts Section 3's best-strategy label
  * (the fastest strategy of the transition) from them, written to out (device float32 [NNC_FEATURES]):
  * |F|/N, H of the candidates, ln N, d, cells met by the candidates / G^d, and
- * eps_t / the median remaining motion budget e_i - S_{t-1} (median from a
+ * eps_t / the median remaining motion budget e_i - S_{t-1} of the certificates of
+ * points 0 .. min(N, 1024) - 1 (median from a
  * power-of-two histogram).  Asynchronous. */
 int nnc_features(nnc_ctx *ctx, float *out);
 
@@ -409,6 +410,12 @@ int nnc_batch_step(nnc_batch *b, const float *pos_new, int policy, float tau);
 /* Load the selector's parameters (device float32 [NNC_SELECTOR_PARAMS]); copied.
  * The network predicts Section 3's best-strategy label for NNC_POLICY_LEARNED. */
 int nnc_batch_selector_load(nnc_batch *b, const float *params);
+
+/* Band of candidate fractions [lo, hi) in which the learned policy computes the
+ * features and asks the network; below lo it repairs, from hi on it rebuilds (the
+ * size rule), so scene-steps outside the band cost no features.  Default [0, 2):
+ * the network everywhere.  NNC_E_INVAL unless lo <= hi. */
+int nnc_batch_selector_band(nnc_batch *b, float lo, float hi);
 
 /* Per-scene results of the last step (host array [scenes]): eps_t and S_t
  * (appendix clock), sizes and entropies of the failed and candidate sets

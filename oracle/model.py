@@ -456,7 +456,8 @@ class OracleScene:
         selector predicts that label from these descriptors of the candidate set):
         |F|/N; H of the candidates (Definition 2); ln N; d; m_cand / G^d, the fraction
         of all cells the candidates meet; and eps_t over the median remaining motion
-        budget r_i = e_i - S_{t-1} of the certificates with 0 < r_i < inf, the median
+        budget r_i = e_i - S_{t-1} of the certificates of points 0 .. min(N, 1024) - 1
+        (a fixed sample) with 0 < r_i < inf, the median
         read from a 64-bin histogram of r by binary exponent (bin = ilogb(r) + 48,
         clamped to [0, 63]; the first bin whose running count reaches half of all,
         represented by 1.5 * 2^(bin - 48)); 0 when no certificate has a finite budget.
@@ -466,7 +467,7 @@ class OracleScene:
         n = self.n
         cand = self.pending.candidates
         H, m, C, F = self.frontier_entropy(CANDIDATES, cand)
-        r = self.e - self.S_prev
+        r = self.e[:1024] - self.S_prev
         r = r[(r > 0) & np.isfinite(r)]
         h = np.zeros(64, np.int64)
         if r.size:

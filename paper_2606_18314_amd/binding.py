@@ -46,6 +46,7 @@ EXPORTS = (
     "nnc_mlp_workspace_bytes", "nnc_mlp_grad", "nnc_mlp_adam", "nnc_mlp_forward", "nnc_snapshot_update",
     "nnc_sqrt_f32", "nnc_mlp_grad_static", "nnc_frontier_gyration", "nnc_queue_stats",
     "nnc_batch_snapshot", "nnc_batch_restore", "nnc_batch_snap_free", "nnc_batch_snapshot_update",
+    "nnc_batch_selector_band",
 )
 
 POLICY_REPAIR, POLICY_REBUILD, POLICY_THRESHOLD, POLICY_LEARNED = range(4)
@@ -165,6 +166,7 @@ def load():
     lib.nnc_batch_snapshot.argtypes = [P, ctypes.POINTER(P)]
     lib.nnc_batch_restore.argtypes = [P, P]
     lib.nnc_batch_snapshot_update.argtypes = [P, P]
+    lib.nnc_batch_selector_band.argtypes = [P, ctypes.c_float, ctypes.c_float]
     lib.nnc_batch_snap_free.argtypes = [P]
     lib.nnc_batch_snap_free.restype = None
     lib.nnc_frontier_gyration.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -489,6 +491,10 @@ class NNCBatch:
         if params.numel() != SELECTOR_PARAMS or params.dtype != torch.float32:
             raise ValueError("selector parameters: float32 tensor of 4738 values")
         check(_lib.nnc_batch_selector_load(self.h, _ptr(params)), "nnc_batch_selector_load")
+
+    def selector_band(self, lo: float, hi: float) -> None:
+        """Candidate fractions [lo, hi) in which the learned policy asks the network."""
+        check(_lib.nnc_batch_selector_band(self.h, float(lo), float(hi)), "nnc_batch_selector_band")
 
     def stats(self) -> list:
         arr = (SceneStats * self.S)()

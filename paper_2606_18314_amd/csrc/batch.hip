@@ -35,6 +35,7 @@ constexpr int kB = 256;       // point-parallel workgroup
 constexpr int kFB = 1024;     // per-scene workgroup
 constexpr int kFRows = NNC_BATCH_MAX_N / kFB;
 constexpr int kH = 64;        // selector hidden width
+constexpr int kLnTable = 256; // candidate counts per cell with tabulated ln n and 1/n
 
 }  // namespace
 
@@ -135,33 +136,48 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
     publish_ingest<kB>(&a.sc[s], parity, sq, dC);
 }
 
-// The selector network on one wave: lane j is hidden unit j of both layers.
-// Returns (to every lane) 1 for rebuild, 0 for repair.
-__device__ int mlp_decide(const float *__restrict__ p, const float *x, float *s_h)
+// The selector network evaluated by the whole 1024-thread workgroup (every thread
+// calls it): layer 1 by the first wave (lane j: hidden unit j), layer 2 by all
+// threads, thread j * 16 + p summing inputs 4p .. 4p + 3 of unit j (the weights
+// read in one coalesced sweep) and the 16 parts combined by shuffles, layer 3 by
+// the first wave.  Returns (in thread 0) 1 for rebuild, 0 for repair.
+__device__ int mlp_decide(const float *__restrict__ p, const float *x, float *s_h1, float *s_h2)
 {
-    const int j = (int)lane_id();
+    static_assert(kFB == kH * 16, "one thread per (unit, quarter-row) of layer 2");
+    const int t = (int)threadIdx.x;
     const float *W1 = p, *b1 = p + kH * NNC_FEATURES, *W2 = b1 + kH, *b2 = W2 + kH * kH, *W3 = b2 + kH,
                 *b3 = W3 + 2 * kH;
-    float h = b1[j];
+    if (t < kH) {
+        float h = b1[t];
 #pragma unroll
-    for (int k = 0; k < NNC_FEATURES; ++k) h += W1[j * NNC_FEATURES + k] * x[k];
-    h = fmaxf(h, 0.0f);
-    s_h[j] = h;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float h2 = b2[j];
-    for (int k = 0; k < kH; ++k) h2 += W2[j * kH + k] * s_h[k];
-    h2 = fmaxf(h2, 0.0f);
-    float o0 = W3[j] * h2, o1 = W3[kH + j] * h2;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        o0 += __shfl_xor(o0, off, 64);
-        o1 += __shfl_xor(o1, off, 64);
+        for (int k = 0; k < NNC_FEATURES; ++k) h += W1[t * NNC_FEATURES + k] * x[k];
+        s_h1[t] = fmaxf(h, 0.0f);
     }
-    o0 += b3[0];
-    o1 += b3[1];
-    return o1 > o0 ? 1 : 0;
+    __syncthreads();
+    {
+        const int j = t >> 4, part = t & 15;
+        const float4 wv = *reinterpret_cast<const float4 *>(W2 + j * kH + part * 4);
+        float z = wv.x * s_h1[part * 4] + wv.y * s_h1[part * 4 + 1] + wv.z * s_h1[part * 4 + 2] +
+                  wv.w * s_h1[part * 4 + 3];
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) z += __shfl_xor(z, off, 16);
+        if (part == 0) s_h2[j] = fmaxf(b2[j] + z, 0.0f);
+    }
+    __syncthreads();
+    int dec = 0;
+    if (t < 64) {
+        const float h2 = s_h2[t];
+        float o0 = W3[t] * h2, o1 = W3[kH + t] * h2;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            o0 += __shfl_xor(o0, off, 64);
+            o1 += __shfl_xor(o1, off, 64);
+        }
+        o0 += b3[0];
+        o1 += b3[1];
+        dec = o1 > o0 ? 1 : 0;
+    }
+    return dec;
 }
 
 __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
@@ -172,10 +188,12 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
     __shared__ int s_cnt[NC];
     __shared__ int s_w[NW];
     __shared__ int s_vh[kVBins];
-    __shared__ int s_m;
     __shared__ double s_acc[NW];
+    __shared__ double s_inv[NW];
+    __shared__ double s_ln[kLnTable], s_rcp[kLnTable];
     __shared__ float s_x[NNC_FEATURES];
     __shared__ float s_h[kH];
+    __shared__ float s_h2[kH];
     __shared__ int s_dec;
     const int s = blockIdx.x;
     const long long t_start = a.cost ? wall_clock64() : 0;
@@ -183,11 +201,7 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
     DevScalars *sc = &a.sc[s];
     const int n = sd.n;
     const int parity = step_number(a) & 1;
-    // candidate histogram, entropy and the budget median only when a feature is wanted
-    // (the learned policy, or statistics requested)
-    const bool want = a.features_on || a.policy == NNC_POLICY_LEARNED;
     if (threadIdx.x < kVBins) s_vh[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_m = 0;
     const double Sprev = sc->S[parity ^ 1];
     const float eps = cert_sqrt(__uint_as_float(sc->dmax[parity]));
     const double St = advance_clock(sc, parity, -1.0f, threadIdx.x < 64);
@@ -204,23 +218,7 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
         const int i = k * kFB + (int)threadIdx.x;
-        int bin = -1;
-        if (i < n) {
-            a.fail[sd.poff + i] = 0;
-            const double r = ev[k] - Sprev;  // remaining motion budget of the certificate
-            if (r > 0.0 && r < __builtin_inf()) bin = validity_bin(r);
-        }
-        if (want) {
-            // the budget histogram, one LDS add per distinct bin of the wave (most
-            // budgets of a row fall in a few neighbouring bins)
-            unsigned long long left = __ballot(bin >= 0);
-            while (left) {
-                const int b = __shfl(bin, __ffsll((long long)left) - 1, 64);
-                const unsigned long long same = __ballot(bin == b) & left;
-                if (lane == 0) atomicAdd(&s_vh[b], (int)__popcll(same));
-                left &= ~same;
-            }
-        }
+        if (i < n) a.fail[sd.poff + i] = 0;
         masks[k] = __ballot(St >= ev[k]);
         if (lane == 0) s_cnt[k * NW + w] = __popcll(masks[k]);
     }
@@ -251,43 +249,88 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
             if (at < n) front[at] = i;
         }
     }
-    // candidate cells: histogram, touched list, entropy (all within this workgroup)
-    const int *cell = a.cell + sd.poff;
-    int *hist = a.hist_cand + sd.goff;
-    int *touched = a.touched_cand + sd.poff;
+    // The features (candidate histogram and entropy, the budget median) are computed
+    // when statistics are requested, or under the learned policy for a scene whose
+    // candidate fraction lies in the network's band [lo, hi) (outside it the size rule
+    // decides: repair below lo, rebuild from hi on).
+    const float f0 = n > 0 ? (float)tot / (float)n : 0.0f;
+    const bool learned = a.policy == NNC_POLICY_LEARNED && a.tdev[1];
+    const float band_lo = __int_as_float(a.tdev[2]), band_hi = __int_as_float(a.tdev[3]);
+    const bool in_band = learned && f0 >= band_lo && f0 < band_hi;
+    const bool want = a.features_on || in_band;
     if (want) {
-        // one LDS atomic per wave for the first touches of cells
-        for (int base = 0; base < tot; base += kFB) {
-            const int q = base + (int)threadIdx.x;
-            int c = 0;
-            bool first = false;
-            if (q < tot) {
-                c = cell[front[q]];
-                first = atomicAdd(&hist[c], 1) == 0;
+        // the budget histogram of the first kVSample certificates (the first row), one
+        // LDS add per distinct bin of the wave
+        static_assert(kVSample == kFB, "the sample is the first row");
+        {
+            const int i = (int)threadIdx.x;
+            int bin = -1;
+            if (i < n) {
+                const double r = ev[0] - Sprev;  // remaining motion budget of the certificate
+                if (r > 0.0 && r < __builtin_inf()) bin = validity_bin(r);
             }
-            const unsigned long long fm = __ballot(first);
-            if (fm) {
-                const int leader = __ffsll((long long)fm) - 1;
-                int at = 0;
-                if ((int)lane == leader) at = atomicAdd(&s_m, (int)__popcll(fm));
-                at = __shfl(at, leader, 64);
-                if (first) touched[at + rank_below(fm)] = c;
+            unsigned long long left = __ballot(bin >= 0);
+            while (left) {
+                const int b = __shfl(bin, __ffsll((long long)left) - 1, 64);
+                const unsigned long long same = __ballot(bin == b) & left;
+                if (lane == 0) atomicAdd(&s_vh[b], (int)__popcll(same));
+                left &= ~same;
             }
         }
     }
-    __syncthreads();
-    const int m = s_m;
-    double acc = 0.0;
-    for (int k = (int)threadIdx.x; k < m; k += kFB) {
-        const int nk = atomicExch(&hist[touched[k]], 0);
-        acc += (double)nk * log((double)nk);
+    // candidate cells: Definition 2's sum over cells of n ln n is the sum over candidates
+    // of ln n_(cell of the candidate), and the cells met number the sum of 1 / n_(cell);
+    // so the histogram is built with atomics whose results are not waited for, read
+    // back once per candidate and cleared (each thread keeps its candidates' cells)
+    double acc = 0.0, inv = 0.0;
+    if (want) {
+        // ln n and 1/n of the small counts from a table (one evaluation per thread,
+        // instead of one per candidate on this one CU)
+        if (threadIdx.x < kLnTable) {
+            s_ln[threadIdx.x] = threadIdx.x > 0 ? log((double)threadIdx.x) : 0.0;
+            s_rcp[threadIdx.x] = threadIdx.x > 0 ? 1.0 / (double)threadIdx.x : 0.0;
+        }
+        const int *cell = a.cell + sd.poff;
+        int *hist = a.hist_cand + sd.goff;
+        int cs[kFRows];
+#pragma unroll
+        for (int k = 0; k < kFRows; ++k) {
+            cs[k] = -1;
+            if ((masks[k] >> lane) & 1ull) {
+                cs[k] = cell[k * kFB + (int)threadIdx.x];
+                atomicAdd(&hist[cs[k]], 1);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kFRows; ++k) {
+            if (cs[k] >= 0) {
+                // the adds above completed at the L2 before the barrier, and no line of
+                // hist was read earlier in this kernel, so plain loads see them
+                const int nk = hist[cs[k]];
+                acc += nk < kLnTable ? s_ln[nk] : log((double)nk);
+                inv += nk < kLnTable ? s_rcp[nk] : 1.0 / (double)nk;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kFRows; ++k)
+            if (cs[k] >= 0) hist[cs[k]] = 0;
     }
     acc = wave_sum(acc);
-    if (lane == 0) s_acc[w] = acc;
+    inv = wave_sum(inv);
+    if (lane == 0) {
+        s_acc[w] = acc;
+        s_inv[w] = inv;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double sum = 0.0;
-        for (int k = 0; k < NW; ++k) sum += s_acc[k];
+        double sum = 0.0, msum = 0.0;
+        for (int k = 0; k < NW; ++k) {
+            sum += s_acc[k];
+            msum += s_inv[k];
+        }
+        const int m = (int)llround(msum);  // an integer: the error of the sum is far below 1/2
         const int C = sc->C;
         double Hc = 0.0;
         if (tot > 0 && C > 1) Hc = (log((double)tot) - sum / (double)tot) / log((double)C);
@@ -304,15 +347,17 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
         sc->Cres[1] = C;
         int dec = 0;
         if (a.policy == NNC_POLICY_REBUILD) dec = 1;
-        else if (a.policy != NNC_POLICY_REPAIR) dec = f[0] >= a.tau ? 1 : 0;
+        else if (a.policy == NNC_POLICY_THRESHOLD || (a.policy == NNC_POLICY_LEARNED && !learned))
+            dec = f[0] >= a.tau ? 1 : 0;
+        else if (a.policy == NNC_POLICY_LEARNED) dec = f0 >= band_hi ? 1 : 0;  // replaced in the band
         s_dec = dec;
     }
     __syncthreads();
-    if (a.policy == NNC_POLICY_LEARNED && a.tdev[1] && threadIdx.x < 64) {
+    if (in_band) {
         bool finite = true;
         for (int k = 0; k < NNC_FEATURES; ++k) finite = finite && __builtin_isfinite(s_x[k]);
-        if (finite) {
-            const int dec = mlp_decide(a.params, s_x, s_h);
+        if (finite) {  // uniform over the workgroup (shared features)
+            const int dec = mlp_decide(a.params, s_x, s_h, s_h2);
             if (threadIdx.x == 0) s_dec = dec;
         }
     }
@@ -707,6 +752,8 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
           hipMemcpyAsync((void *)a.tile_start, b->tile_start.data(), b->ntiles * 4, hipMemcpyHostToDevice,
                          b->stream) != hipSuccess)))
         rc = NNC_E_HIP;
+    // the learned policy's band: the network decides at every candidate fraction
+    if (rc == NNC_OK) rc = nnc::launch_fill(a.tdev + 3, __builtin_bit_cast(int, 2.0f), 1, b->stream);
     if (rc == NNC_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = NNC_E_HIP;
     if (rc != NNC_OK) {
         (void)hipFree(b->arena);
@@ -845,6 +892,14 @@ int nnc_batch_selector_load(nnc_batch *b, const float *params)
         hipSuccess)
         return NNC_E_HIP;
     return nnc::launch_fill(b->a.tdev + 1, 1, 1, b->stream);
+}
+
+int nnc_batch_selector_band(nnc_batch *b, float lo, float hi)
+{
+    if (!b || !(lo <= hi)) return NNC_E_INVAL;
+    int rc = nnc::launch_fill(b->a.tdev + 2, __builtin_bit_cast(int, lo), 1, b->stream);
+    if (rc == NNC_OK) rc = nnc::launch_fill(b->a.tdev + 3, __builtin_bit_cast(int, hi), 1, b->stream);
+    return rc;
 }
 
 int nnc_batch_scene_stats(nnc_batch *b, nnc_scene_stats *out)

@@ -844,7 +844,7 @@ __global__ void __launch_bounds__(1024) k_features(const double *__restrict__ e,
     if (threadIdx.x < kVBins) s_vh[threadIdx.x] = 0;
     __syncthreads();
     const double Sprev = sc->S[parity ^ 1];
-    for (int i = threadIdx.x; i < n; i += 1024) {
+    for (int i = threadIdx.x; i < min(n, kVSample); i += 1024) {
         const double r = e[i] - Sprev;
         if (r > 0.0 && r < __builtin_inf()) atomicAdd(&s_vh[validity_bin(r)], 1);
     }

@@ -873,9 +873,11 @@ __device__ __forceinline__ void query_one(const QueryArgs &a, int q, double St, 
 // and for a scene of a batch):
 //   f0 = |F|/N, f1 = H of the candidates, f2 = ln N, f3 = d,
 //   f4 = cells met by the candidates / G^d,
-//   f5 = eps_t / median remaining motion budget e_i - S_{t-1} of the certificates,
+//   f5 = eps_t / median remaining motion budget e_i - S_{t-1} of the certificates of
+//        the first kVSample points (a fixed sample: one pass of one workgroup),
 // the median taken from a 64-bin power-of-two histogram (bin b: [2^(b-48), 2^(b-47))).
 constexpr int kVBins = 64;
+constexpr int kVSample = 1024;  // certificates whose budgets give the median of f5
 constexpr int kVBias = 48;
 
 __device__ __forceinline__ int validity_bin(double r) { return min(max(ilogb(r) + kVBias, 0), kVBins - 1); }

@@ -156,11 +156,15 @@ def collect_batched(specs, steps: int, batch_size: int = 128, lanes: int = 16, l
     return {"X": np.array(X, np.float32), "t_repair": np.array(trep), "t_rebuild": np.array(treb)}
 
 
-def inference_cost(specs, steps: int, params: np.ndarray, tau: float, lanes: int = 16, reps: int = 3):
+def inference_cost(specs, steps: int, params: np.ndarray, tau: float, lanes: int = 16, reps: int = 5):
     """Per scene-step cost of the learned policy's features and network inside the batched
-    filter, in wave-microseconds: the filter workgroup's time under the learned policy
-    minus its time under the size threshold (which computes no features), median over
-    steps of the mean over scenes."""
+    step, in the labels' unit (wave-microseconds).  The same step is run from the same
+    state under the size rule set to always repair and under the learned policy with a
+    network whose output always says repair (the trained weights with the output bias
+    shifted), so both make the same decisions and differ only by the features and the
+    network; the wall-clock difference (median of reps) is converted to wave-microseconds
+    with the step's own ratio of summed scene costs to wall time, and shared over the
+    scenes."""
     import synth
     from . import autotune
     trajs = [synth.make_trajectory(sp["family"], sp["n"], sp["d"], steps, sp["eps"], tuple(sp["seed"]))
@@ -169,30 +173,66 @@ def inference_cost(specs, steps: int, params: np.ndarray, tau: float, lanes: int
     ds = [t.d for t in trajs]
     frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 1)]
     grids = autotune.batch_grids(frames[0], ns, ds, lanes=lanes, factor=1.5, cells_per_point=8)
+    repair_only = params.astype(np.float32).copy()
+    repair_only[-2], repair_only[-1] = 1e6, -1e6          # b3: the repair logit always wins
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         b = binding.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream, timing=True, eager=True)
-        b.selector_load(torch.from_numpy(params.astype(np.float32)).cuda())
+        b.selector_load(torch.from_numpy(repair_only).cuda())
         b.init(frames[0])
     snap = None
-    diffs = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    per_scene = []
     for t in range(1, steps + 1):
-        f = {}
-        for _ in range(reps):
-            for pol in (binding.POLICY_THRESHOLD, binding.POLICY_LEARNED):
+        with torch.cuda.stream(s):
+            snap = b.snapshot(into=snap)
+        wall = {}
+        for pol, tv in ((binding.POLICY_THRESHOLD, 2.0), (binding.POLICY_LEARNED, tau)):
+            times = []
+            for _ in range(reps):
                 with torch.cuda.stream(s):
-                    snap = b.snapshot(into=snap) if (pol == binding.POLICY_THRESHOLD and _ == 0) else snap
                     b.restore(snap)
-                    b.step(frames[t], pol, tau)
-                st = b.stats()
-                v = float(np.mean([x["t_filter_us"] for x in st]))
-                f[pol] = min(f.get(pol, math.inf), v)
-        diffs.append(f[binding.POLICY_LEARNED] - f[binding.POLICY_THRESHOLD])
+                    ev[0].record(s)
+                    b.step(frames[t], pol, tv)
+                    ev[1].record(s)
+                ev[1].synchronize()
+                times.append(ev[0].elapsed_time(ev[1]) * 1e3)
+            wall[pol] = float(np.median(times))
+        st = b.stats()
+        busy = sum(scene_cost(x) for x in st)
+        ratio = busy / wall[binding.POLICY_THRESHOLD]           # wave-microseconds per wall microsecond
+        dwall = wall[binding.POLICY_LEARNED] - wall[binding.POLICY_THRESHOLD]
+        per_scene.append(dwall * ratio / len(specs))
         with torch.cuda.stream(s):
             b.restore(snap)
             b.step(frames[t], binding.POLICY_REPAIR)
     b.close()
-    return WAVES_PER_WORKGROUP * max(0.0, float(np.median(diffs)))
+    return max(0.0, float(np.median(per_scene)))
+
+
+def fit_band(X, t_rep, t_reb, choice, c_inf: float):
+    """Band [lo, hi) of candidate fractions in which the network decides (outside it:
+    repair below lo, rebuild from hi on), minimising the regret with the features' and
+    network's cost c_inf charged to the transitions inside the band."""
+    f0 = X[:, 0]
+    qs = np.unique(np.concatenate([[0.0, 2.0], np.quantile(f0, np.linspace(0.0, 1.0, 41))]))
+    best = (math.inf, 0.0, 2.0)
+    for lo in qs:
+        for hi in qs:
+            if hi < lo:
+                continue
+            band = (f0 >= lo) & (f0 < hi)
+            ch = np.where(band, choice, (f0 >= hi).astype(np.int32))
+            r = regret(ch, t_rep, t_reb, np.where(band, c_inf, 0.0))
+            if r < best[0]:
+                best = (r, float(lo), float(hi))
+    return best[1], best[2]
+
+
+def band_choice(X, choice, lo: float, hi: float):
+    f0 = X[:, 0]
+    band = (f0 >= lo) & (f0 < hi)
+    return np.where(band, choice, (f0 >= hi).astype(np.int32)), band
 
 
 def labels(t_rep, t_reb, clip: float = 10.0, floor: float = 0.05):
@@ -315,16 +355,19 @@ def main_batched(args, log):
     train_s = time.time() - t1
     tau, _ = fit_threshold(Xtr, rtr, btr)
     c_inf = inference_cost(test_specs[:64], 12, params, tau)
-    ch_net = decide(params, Xte)
+    lo, hi = fit_band(Xtr, rtr, btr, decide(params, Xtr), c_inf)
+    ch_net, band = band_choice(Xte, decide(params, Xte), lo, hi)
     res = {
         "labels": "timed inside the batched step (per-scene wall-clock accounting, wave-microseconds)",
         "transitions": int(len(Xtr) + len(Xte)), "train": int(len(Xtr)), "held_out": int(len(Xte)),
         "train_seconds": train_s,
         "rebuild_wins_fraction": float(np.mean(btr < rtr)),
         "inference_wave_us_per_scene_step": c_inf,
+        "band": [lo, hi], "held_out_fraction_in_band": float(band.mean()),
         "mean_best_wave_us_per_scene_step": float(np.minimum(rte, bte).mean()),
-        "regret_learned": regret(ch_net, rte, bte, c_inf),
+        "regret_learned": regret(ch_net, rte, bte, np.where(band, c_inf, 0.0)),
         "regret_learned_without_inference": regret(ch_net, rte, bte),
+        "regret_network_everywhere": regret(decide(params, Xte), rte, bte, c_inf),
         "regret_threshold": regret((Xte[:, 0] >= tau).astype(np.int32), rte, bte),
         "regret_always_repair": regret(np.zeros(len(Xte), np.int32), rte, bte),
         "regret_always_rebuild": regret(np.ones(len(Xte), np.int32), rte, bte),
