@@ -160,13 +160,15 @@ def batched_leg(args, nnc, synth, autotune, torch):
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    policies = [("repair", 0), ("rebuild", 1), ("threshold", 2)]
+    # the paper's rule under each policy, then repair with the per-point motion budget
+    policies = [("repair", 0, False), ("rebuild", 1, False), ("threshold", 2, False)]
     if params is not None:
-        policies.append(("learned", 3))
+        policies.append(("learned", 3, False))
+    policies.append(("repair_budget", 0, True))
     pdev = torch.from_numpy(params).cuda() if params is not None else None
-    for name, pol in policies:
+    for name, pol, budget in policies:
         with torch.cuda.stream(s):
-            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream)
+            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, stream=s.cuda_stream, budget=budget)
             if pdev is not None:
                 b.selector_load(pdev)
                 band = meta.get("band", [0.0, 2.0])
@@ -188,7 +190,7 @@ def batched_leg(args, nnc, synth, autotune, torch):
         ms = e0.elapsed_time(e1)
         st = b.stats()
         rebuilt = sum(x["strategy"] for x in st) / len(st)
-        nbytes = batched_step_bytes(ns, ds, grids, st)
+        nbytes = batched_step_bytes(ns, ds, grids, st, budget)
         gbs = nbytes / (ms / steps * 1e-3) / 1e9
         progress(f"batched {name}: {ms / steps:.4f} ms/step, {gbs:.0f} GB/s algorithmic")
         res[name] = {"value": total * steps / (ms / 1e3), "ms_per_step": ms / steps,
@@ -341,14 +343,18 @@ def mixed_eps_batch(nnc, synth, autotune, selector, torch, params, meta, tau, sc
     return out
 
 
-def batched_step_bytes(ns, ds, grids, stats):
+def batched_step_bytes(ns, ds, grids, stats, budget=False):
     """Algorithmic bytes of one batched step from the last step's per-scene counts:
     ingest (new coordinates, rank, the slot record read and rewritten, cell), filter
     (key, fail flag; candidate list), queries (each query's coordinates and list entry,
     its certificate written; every slot record of the scene read once; the cell-start
-    table), and for a rebuilt scene its grid build (counts, scan, scatter)."""
+    table), and for a rebuilt scene its grid build (counts, scan, scatter); with the
+    per-point budget, its pass reads every key once (the expired points' further
+    reads are not counted: a lower bound)."""
     tot = 0
     for n, d, G, st in zip(ns, ds, grids, stats):
+        if budget:
+            tot += 8 * n
         cells = G ** d
         q = n if st["strategy"] == 1 else st["n_cand"]
         tot += n * (4 * d + 4 + 16 + 16 + 4) + n * 9 + 4 * st["n_cand"]

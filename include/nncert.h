@@ -341,7 +341,7 @@ typedef struct {
     double guard;            /* as in nnc_config */
     double refresh;          /* as in nnc_config */
     void *stream;            /* hipStream_t */
-    uint32_t flags;          /* NNC_BATCH_FEATURES | NNC_BATCH_EAGER | NNC_BATCH_TIMING */
+    uint32_t flags;          /* NNC_BATCH_FEATURES | NNC_BATCH_EAGER | NNC_BATCH_TIMING | NNC_BATCH_BUDGET */
 } nnc_batch_config;
 
 /* Compute the candidate histogram, H of the candidates and the selector features
@@ -354,6 +354,12 @@ typedef struct {
  * (nnc_scene_stats.t_*_us), to label each scene-step with its cheaper strategy
  * inside the batch (Section 3's best-strategy label). */
 #define NNC_BATCH_TIMING   4u
+/* The per-point motion budget of NNC_BUDGET (Section 5, Limitations) in every
+ * scene: before the filter, each expired certificate takes the block-local and
+ * the distance test, and only the points that fail both are candidates.  Costs a
+ * per-cell step stamp in the ingest, a binary64 certificate clock per point and
+ * one pass over the expired points. */
+#define NNC_BATCH_BUDGET   8u
 
 typedef struct {
     double  eps;             /* eps_t of the last step */
@@ -395,7 +401,7 @@ int nnc_batch_init(nnc_batch *b, const float *pos);
  * refresh grids where needed, run every scene's queries in one launch, and
  * reduce the failure entropy (Definition 2).  pos_new (device, concatenated) is
  * read during the step only: the previous coordinates are kept by the library.
- * Asynchronous.  The step's five kernels are captured into a HIP graph on the
+ * Asynchronous.  The step's kernels are captured into a HIP graph on the
  * first call and the graph is replayed while pos_new, policy and tau repeat
  * (write each new frame into the same buffer); another pointer, policy or tau
  * re-captures the graph (a host cost of tens of microseconds).  Under a caller's

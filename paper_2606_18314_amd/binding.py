@@ -436,9 +436,11 @@ class NNCBatch:
     [d_s, n_s] block starting at ``coord_off[s]``."""
 
     def __init__(self, ns, ds, grids=None, lanes: int = 0, guard: float = -1.0, refresh: float = 0.0,
-                 stream: int | None = None, features: bool = False, eager: bool = False, timing: bool = False):
+                 stream: int | None = None, features: bool = False, eager: bool = False, timing: bool = False,
+                 budget: bool = False):
         """eager: launch each step's kernels directly instead of through the library's graph;
-        timing: per-scene wall-clock cost accounting (stats' t_filter_us, t_grid_us, t_query_us)."""
+        timing: per-scene wall-clock cost accounting (stats' t_filter_us, t_grid_us, t_query_us);
+        budget: the per-point motion budget in every scene (NNC_BATCH_BUDGET)."""
         import numpy as np
         lib = load()
         self.S = len(ns)
@@ -449,7 +451,8 @@ class NNCBatch:
         cfg = BatchConfig(scenes=self.S, n=self._n.ctypes.data, d=self._d.ctypes.data,
                           grid_g=0 if self._g is None else self._g.ctypes.data, lanes=int(lanes),
                           guard=float(guard), refresh=float(refresh), stream=self.stream,
-                          flags=(1 if features else 0) | (2 if eager else 0) | (4 if timing else 0))
+                          flags=(1 if features else 0) | (2 if eager else 0) | (4 if timing else 0)
+                          | (8 if budget else 0))
         h = ctypes.c_void_p()
         check(lib.nnc_batch_create(ctypes.byref(h), ctypes.byref(cfg)), "nnc_batch_create")
         self.h = h.value

@@ -2,20 +2,25 @@
 // dimension advanced together, for gfx950.
 //
 // Every kernel spans all scenes:
-//   k_b_ingest   one workgroup per 256-point tile of a scene: displacement,
+//   k_b_ingest   one workgroup per 1024-point tile of a scene: displacement,
 //                per-scene maximum (one atomic per wave), cells, occupancy,
-//                current coordinates into the grid slots;
+//                current coordinates into the grid slots (and, with the
+//                per-point budget, the step stamps of the cells moving points
+//                leave and enter);
+//   k_b_budget   (per-point budget only) the same tiles: the budget tests of
+//                the expired certificates, moving the keys of those kept;
 //   k_b_filter   one 1024-thread workgroup per scene: clock, safety filter,
 //                ordered compaction, candidate-cell histogram and entropy, the
 //                six selector features, and the strategy decision (threshold
-//                rule or the selector network, evaluated by one wave);
+//                rule or the selector network, evaluated by the workgroup);
 //   k_b_grid     one workgroup per scene that needs a fresh grid (rebuild, or
 //                repair after the motion budget of the loose grid is spent):
 //                cell-start scan and counting-sort scatter; one extra workgroup
-//                turns the per-scene query counts into offsets;
-//   k_b_query    one persistent grid-stride launch over the queries of all
-//                scenes (candidates of repaired scenes, every point of rebuilt
-//                ones), L lanes per query, the same exact search as one scene;
+//                turns the per-scene query counts into offsets per dimension;
+//   k_b_query    one persistent grid-stride launch per dimension over the
+//                queries of all scenes of that dimension (candidates of
+//                repaired scenes, every point of rebuilt ones), L lanes per
+//                query, the same exact search as one scene;
 //   k_b_entropy  one workgroup per scene: failure entropy (Definition 2).
 // No workgroup waits for another: all cross-scene coordination is by kernel
 // order, so the step is safe to capture in a graph.
@@ -32,6 +37,8 @@ namespace {
 using namespace kc;
 
 constexpr int kB = 256;       // point-parallel workgroup
+constexpr int kIU = 4;        // points per thread of the ingest
+constexpr int kTile = kB * kIU;  // points of a scene per ingest workgroup
 constexpr int kFB = 1024;     // per-scene workgroup
 constexpr int kFRows = NNC_BATCH_MAX_N / kFB;
 constexpr int kH = 64;        // selector hidden width
@@ -65,6 +72,8 @@ struct BatchArgs {
     int *nn, *stamp, *frontier, *hist_fail, *touched_fail, *hist_cand, *touched_cand;
     float *d1, *d2;
     double *e;
+    double *Si;      // certificate clocks (per-point budget), or null
+    int *last_move;  // per cell: last step a moving point left or entered it (per-point budget), or null
     uint8_t *fail;
     const int *tile_scene, *tile_start;
     int *strategy, *need_grid, *qcount, *qpre;
@@ -82,9 +91,10 @@ __global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
 {
     const int s = a.tile_scene[blockIdx.x];
     const SceneDesc sd = a.desc[s];
-    const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x;
     int dC = 0;
-    if (i < sd.n) {
+    for (int u = 0; u < kIU; ++u) {
+        const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x + u * kB;
+        if (i >= sd.n) break;
         const float *p = a.pos_cur + sd.coff;
         const size_t n1 = (size_t)sd.n;
         const float x = p[i], y = p[n1 + i], z = sd.d == 3 ? p[2 * n1 + i] : 0.f;
@@ -95,45 +105,148 @@ __global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
         else
             atomicOr(&a.sc[s].err, kErrNonFinite);
         a.cell[sd.poff + i] = c;
-        dC = atomicAdd(&a.counts[sd.goff + c], 1) == 0;
+        dC += atomicAdd(&a.counts[sd.goff + c], 1) == 0;
     }
     add_C(&a.sc[s], dC);
 }
 
+// kIU points per thread (thread t of the tile: points t, t + kB, ...), their
+// loads issued together so that each wave waits for few memory round trips.
 __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
 {
     const int s = a.tile_scene[blockIdx.x];
     const SceneDesc sd = a.desc[s];
-    const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x;
+    const int i0 = a.tile_start[blockIdx.x] + (int)threadIdx.x;
     const int parity = step_number(a) & 1;
+    const float *pn = a.pos_cur + sd.coff;
+    const size_t n1 = (size_t)sd.n, n2 = 2 * (size_t)sd.n;
+    const bool d3 = sd.d == 3;
+    float4 *slots = a.slots + sd.poff;
+    int rk[kIU], oc[kIU];
+#pragma unroll
+    for (int u = 0; u < kIU; ++u) {
+        const int i = i0 + u * kB;
+        rk[u] = i < sd.n ? a.rank[sd.poff + i] : 0;
+        oc[u] = i < sd.n ? a.cell[sd.poff + i] : 0;
+    }
+    float4 old4[kIU];
+    float x1[kIU], y1[kIU], z1[kIU];
+#pragma unroll
+    for (int u = 0; u < kIU; ++u) {
+        const int i = i0 + u * kB;
+        const bool in = i < sd.n;
+        // the slot record holds the point's coordinates of the previous step
+        old4[u] = in ? slots[rk[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+        x1[u] = in ? pn[i] : 0.f;
+        y1[u] = in ? pn[n1 + i] : 0.f;
+        z1[u] = in && d3 ? pn[n2 + i] : 0.f;
+    }
     float sq = 0.0f;
     int dC = 0;
-    if (i < sd.n) {
-        // the slot record holds the point's coordinates of the previous step
-        const float *pn = a.pos_cur + sd.coff;
-        const size_t n1 = (size_t)sd.n, n2 = 2 * (size_t)sd.n;
-        const bool d3 = sd.d == 3;
-        float4 *rec = a.slots + sd.poff + a.rank[sd.poff + i];
-        const float4 old4 = *rec;
-        const float x0 = old4.x, y0 = old4.y, z0 = old4.z;
-        const float x1 = pn[i], y1 = pn[n1 + i], z1 = d3 ? pn[n2 + i] : 0.f;
-        *rec = make_float4(x1, y1, z1, __int_as_float(i));
-        const bool ok = d3 ? all_finite<3>(x1, y1, z1) && all_finite<3>(x0, y0, z0)
-                           : all_finite<2>(x1, y1, z1) && all_finite<2>(x0, y0, z0);
+#pragma unroll
+    for (int u = 0; u < kIU; ++u) {
+        const int i = i0 + u * kB;
+        if (i >= sd.n) continue;
+        slots[rk[u]] = make_float4(x1[u], y1[u], z1[u], __int_as_float(i));
+        const float x0 = old4[u].x, y0 = old4[u].y, z0 = old4[u].z;
+        const bool ok = d3 ? all_finite<3>(x1[u], y1[u], z1[u]) && all_finite<3>(x0, y0, z0)
+                           : all_finite<2>(x1[u], y1[u], z1[u]) && all_finite<2>(x0, y0, z0);
         if (ok) {
-            sq = d3 ? sqdist<3>(x0, y0, z0, x1, y1, z1) : sqdist<2>(x0, y0, z0, x1, y1, z1);
-            const int c = d3 ? cell_id<3>(x1, y1, z1, sd.G) : cell_id<2>(x1, y1, z1, sd.G);
-            const int old = a.cell[sd.poff + i];
-            if (c != old) {
+            sq = fmaxf(sq, d3 ? sqdist<3>(x0, y0, z0, x1[u], y1[u], z1[u]) : sqdist<2>(x0, y0, z0, x1[u], y1[u], z1[u]));
+            const int c = d3 ? cell_id<3>(x1[u], y1[u], z1[u], sd.G) : cell_id<2>(x1[u], y1[u], z1[u], sd.G);
+            if (c != oc[u]) {
                 a.cell[sd.poff + i] = c;
-                dC -= atomicSub(&a.counts[sd.goff + old], 1) == 1;
+                dC -= atomicSub(&a.counts[sd.goff + oc[u]], 1) == 1;
                 dC += atomicAdd(&a.counts[sd.goff + c], 1) == 0;
+            }
+            if (a.last_move && (x1[u] != x0 || y1[u] != y0 || z1[u] != z0)) {
+                // the cells a moving point leaves and enters; every writer stores the same value
+                a.last_move[sd.goff + oc[u]] = step_number(a);
+                a.last_move[sd.goff + c] = step_number(a);
             }
         } else {
             atomicOr(&a.sc[s].err, kErrNonFinite);
         }
     }
     publish_ingest<kB>(&a.sc[s], parity, sq, dC);
+}
+
+// Per-point motion budget of every expired certificate, before the filter (the
+// same two tests as a single scene's): (1) block-local: no cell of the point's
+// 3^d block was stamped after its certificate and (d2 + D)(1 + 2^-20) + fuzz is
+// below the distance to the outside of the block (D = S_t - S_i) -- the key moves
+// to the next binary64 value above S_t; (2) distance: the kept neighbour's
+// current distance r is below d2 (1 - g) - 2 D (1 + g) -- the key moves to
+// S_t + gap K.  Otherwise the point stays expired and the filter lists it.  S_t is
+// computed as the filter will compute it, read-only.  Tiles as in the ingest.
+__global__ void __launch_bounds__(kB) k_b_budget(BatchArgs a)
+{
+    const int s = a.tile_scene[blockIdx.x];
+    const SceneDesc sd = a.desc[s];
+    const int parity = step_number(a) & 1;
+    const DevScalars *sc = &a.sc[s];
+    const int lane = (int)lane_id();
+    const float m = fmaxf(wave_max(__uint_as_float(sc->dmax_part[parity][lane])), __uint_as_float(sc->dmax[parity]));
+    const double St = sc->S[parity ^ 1] + (double)cert_sqrt(m);
+    const int G = sd.G, n = sd.n;
+    const bool d3 = sd.d == 3;
+    const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
+    const float *p = a.pos_cur + sd.coff;
+    const double w = 1.0 / (double)G;
+    for (int u = 0; u < kIU; ++u) {
+        const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x + u * kB;
+        if (i >= n) break;
+        double *ei = a.e + sd.poff + i;
+        if (!(St >= *ei)) continue;
+        const int j = a.nn[sd.poff + i];
+        if (j < 0 || j >= n) continue;
+        const double dS = St - a.Si[sd.poff + i];
+        const float d2 = a.d2[sd.poff + i];
+        const float xi = p[i], yi = p[n1 + i], zi = d3 ? p[n2 + i] : 0.0f;
+        {
+            const int id = a.cell[sd.poff + i], si = a.stamp[sd.poff + i];
+            const int gc[3] = {id % G, (id / G) % G, d3 ? id / (G * G) : 0};
+            const int *lm = a.last_move + sd.goff;
+            bool quiet = true;
+            for (int oz = (d3 ? -1 : 0); oz <= (d3 ? 1 : 0) && quiet; ++oz) {
+                const int z = gc[2] + oz;
+                if (z < 0 || z >= (d3 ? G : 1)) continue;
+                for (int oy = -1; oy <= 1 && quiet; ++oy) {
+                    const int y = gc[1] + oy;
+                    if (y < 0 || y >= G) continue;
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int x = gc[0] + ox;
+                        if (x < 0 || x >= G) continue;
+                        if (lm[x + G * (y + G * z)] > si) {
+                            quiet = false;
+                            break;
+                        }
+                    }
+                }
+            }
+            if (quiet) {
+                double B = __builtin_inf();
+                const float pc[3] = {xi, yi, zi};
+                for (int k = 0; k < (d3 ? 3 : 2); ++k) {
+                    const double x = (double)pc[k];
+                    if (gc[k] - 1 > 0) B = fmin(B, x - (double)(gc[k] - 1) * w);
+                    if (gc[k] + 1 < G - 1) B = fmin(B, (double)(gc[k] + 2) * w - x);
+                }
+                const double need = ((double)d2 + dS) * (1.0 + 0x1p-20) + kFuzz;
+                if (need < B) {
+                    // the next binary64 value above the clock (S_t >= 0): tested again once anything moves
+                    *ei = __longlong_as_double(__double_as_longlong(St) + 1);
+                    continue;
+                }
+            }
+        }
+        const float sq = d3 ? sqdist<3>(xi, yi, zi, p[j], p[n1 + j], p[n2 + j])
+                            : sqdist<2>(xi, yi, 0.0f, p[j], p[n1 + j], 0.0f);
+        const float r = cert_sqrt(sq);
+        const double thr = (double)d2 * (1.0 - a.guard) - 2.0 * (dS * (1.0 + a.guard));
+        const double gap = thr - (double)r;
+        if (gap > 0.0) *ei = St + gap * a.K;
+    }
 }
 
 // The selector network evaluated by the whole 1024-thread workgroup (every thread
@@ -379,16 +492,21 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
 {
     __shared__ int s_w[kFB / 64];
     if ((int)blockIdx.x == a.scenes) {
-        int run = 0;
-        for (int base = 0; base < a.scenes; base += kFB) {
-            const int s = base + (int)threadIdx.x;
-            const int v = s < a.scenes ? a.qcount[s] : 0;
-            int tot;
-            const int ex = block_excl_scan<kFB>(v, s_w, tot);
-            if (s < a.scenes) a.qpre[s] = run + ex;
-            run += tot;
+        // query offsets per dimension: qpre[(d - 2) * (scenes + 1) + s] counts the
+        // queries of the scenes of dimension d before scene s
+        for (int d = 2; d <= 3; ++d) {
+            int *pre = a.qpre + (d - 2) * (a.scenes + 1);
+            int run = 0;
+            for (int base = 0; base < a.scenes; base += kFB) {
+                const int s = base + (int)threadIdx.x;
+                const int v = s < a.scenes && a.desc[s].d == d ? a.qcount[s] : 0;
+                int tot;
+                const int ex = block_excl_scan<kFB>(v, s_w, tot);
+                if (s < a.scenes) pre[s] = run + ex;
+                run += tot;
+            }
+            if (threadIdx.x == 0) pre[a.scenes] = run;
         }
-        if (threadIdx.x == 0) a.qpre[a.scenes] = run;
         return;
     }
     const int s = blockIdx.x;
@@ -398,34 +516,97 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
     }
     const long long t_start = a.cost ? wall_clock64() : 0;
     const SceneDesc sd = a.desc[s];
-    int run = 0;
-    for (int base = 0; base < sd.ncell; base += kFB) {
-        const int c = base + (int)threadIdx.x;
-        const int v = c < sd.ncell ? a.counts[sd.goff + c] : 0;
-        int tot;
-        const int ex = block_excl_scan<kFB>(v, s_w, tot);
-        if (c < sd.ncell) {
-            a.cell_start[sd.soff + c] = run + ex;
-            a.cursor[sd.goff + c] = run + ex;
+    // cell-start scan over groups of four cells (the scene's cell regions start on
+    // 16-byte boundaries and are padded with empty cells): wave w owns one
+    // contiguous segment of the groups; it sums its segment, the workgroup scans
+    // the 16 sums, then the wave scans its segment 64 groups at a time with a
+    // running carry, four rounds of loads in flight (no workgroup barrier per
+    // chunk).  Every padding entry receives the total, the sentinel included.
+    {
+        constexpr int NW = kFB / 64, U = 4;
+        const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+        const int nq = (sd.ncell + 3) >> 2;
+        const int seg = (((nq + NW - 1) / NW) + 63) & ~63;
+        const int q0 = min(w * seg, nq), q1 = min(q0 + seg, nq);
+        const int4 *cnt = reinterpret_cast<const int4 *>(a.counts + sd.goff);
+        int4 *cs4 = reinterpret_cast<int4 *>(a.cell_start + sd.soff);
+        int4 *cu4 = reinterpret_cast<int4 *>(a.cursor + sd.goff);
+        int part = 0;
+        for (int b = q0; b < q1; b += U * 64) {
+            int4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = b + u * 64 + lane;
+                v[u] = k < q1 ? cnt[k] : make_int4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) part += v[u].x + v[u].y + v[u].z + v[u].w;
         }
-        run += tot;
-    }
-    if (threadIdx.x == 0) {
-        a.cell_start[sd.soff + sd.ncell] = run;
-        a.sc[s].S_grid = a.sc[s].S[step_number(a) & 1];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+        if (lane == 0) s_w[w] = part;
+        __syncthreads();
+        int carry = 0, total = 0;
+        for (int k = 0; k < NW; ++k) {
+            const int v = s_w[k];
+            carry += k < w ? v : 0;
+            total += v;
+        }
+        for (int b = q0; b < q1; b += U * 64) {
+            int4 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = b + u * 64 + lane;
+                v[u] = k < q1 ? cnt[k] : make_int4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = b + u * 64 + lane;
+                const int sum = v[u].x + v[u].y + v[u].z + v[u].w;
+                int incl = sum;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int o = __shfl_up(incl, off, 64);
+                    if (lane >= off) incl += o;
+                }
+                const int ex = carry + incl - sum;
+                const int4 st = make_int4(ex, ex + v[u].x, ex + v[u].x + v[u].y, ex + v[u].x + v[u].y + v[u].z);
+                if (k < q1) {
+                    cs4[k] = st;
+                    cu4[k] = st;
+                }
+                carry += __shfl(incl, 63, 64);
+            }
+        }
+        if (threadIdx.x == 0) {
+            a.cell_start[sd.soff + sd.ncell] = total;
+            a.sc[s].S_grid = a.sc[s].S[step_number(a) & 1];
+        }
     }
     __syncthreads();
+    // counting-sort scatter, four points per thread in flight
     const size_t n1 = (size_t)sd.n;
     const float *p = a.pos_cur + sd.coff;
     float4 *so = a.slots + sd.poff;
-    for (int i = (int)threadIdx.x; i < sd.n; i += kFB) {
-        const int k = atomicAdd(&a.cursor[sd.goff + a.cell[sd.poff + i]], 1);
-        if (k >= sd.n) {
-            atomicOr(&a.sc[s].err, kErrOverflow);
-            continue;
+    constexpr int U = 4;
+    for (int i0 = (int)threadIdx.x; i0 < sd.n; i0 += U * kFB) {
+        int k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kFB;
+            k[u] = i < sd.n ? atomicAdd(&a.cursor[sd.goff + a.cell[sd.poff + i]], 1) : -1;
         }
-        a.rank[sd.poff + i] = k;
-        so[k] = make_float4(p[i], p[n1 + i], sd.d == 3 ? p[2 * n1 + i] : 0.0f, __int_as_float(i));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kFB;
+            if (i >= sd.n) continue;
+            if (k[u] >= sd.n) {
+                atomicOr(&a.sc[s].err, kErrOverflow);
+                continue;
+            }
+            a.rank[sd.poff + i] = k[u];
+            so[k[u]] = make_float4(p[i], p[n1 + i], sd.d == 3 ? p[2 * n1 + i] : 0.0f, __int_as_float(i));
+        }
     }
     if (a.cost) {
         __syncthreads();
@@ -457,7 +638,7 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
     q.d1 = a.d1 + sd.poff;
     q.d2 = a.d2 + sd.poff;
     q.e = a.e + sd.poff;
-    q.Si = nullptr;
+    q.Si = a.Si ? a.Si + sd.poff : nullptr;
     q.cmask = nullptr;
     q.qkey = nullptr;
     q.tiled_from = 0;
@@ -481,11 +662,12 @@ __device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneD
 // scene's end), then the wave moves on.  The scene index is uniform over the wave,
 // so the scene's descriptor and pointers sit in scalar registers and a wave never
 // runs the plane and the cube search side by side.
-template <int L>
+template <int D, int L>
 __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
 {
     constexpr int GPW = 64 / L;  // lane groups per wave
-    const int total = a.qpre[a.scenes];
+    const int *qpre = a.qpre + (D - 2) * (a.scenes + 1);
+    const int total = qpre[a.scenes];
     const int lane = threadIdx.x & (L - 1);
     const int grp = (int)(threadIdx.x & 63) / L;
     const int nw = (int)gridDim.x * (kB / 64);
@@ -497,13 +679,13 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
     int lo = 0, hi = a.scenes;  // the last s with qpre[s] <= g
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (a.qpre[mid] <= g) lo = mid;
+        if (qpre[mid] <= g) lo = mid;
         else hi = mid;
     }
     int s = __builtin_amdgcn_readfirstlane(lo);
     const int t = step_number(a), parity = t & 1;
     while (g < q1) {
-        const int first = a.qpre[s], next = a.qpre[s + 1];
+        const int first = qpre[s], next = qpre[s + 1];
         if (g < next) {
             const SceneDesc sd = a.desc[s];
             const QueryArgs q = scene_view(a, sd, s, init, t);
@@ -512,12 +694,7 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
             const int end = min(next, q1);
             const long long t_start = a.cost ? wall_clock64() : 0;
             for (; g < end; g += GPW) {
-                if (g + grp < end) {
-                    if (sd.d == 3)
-                        query_one<3, L, true>(q, g + grp - first, St, margin, lane);
-                    else
-                        query_one<2, L, true>(q, g + grp - first, St, margin, lane);
-                }
+                if (g + grp < end) query_one<D, L, true>(q, g + grp - first, St, margin, lane);
             }
             g = end;
             if (a.cost && (threadIdx.x & 63) == 0)
@@ -572,7 +749,8 @@ struct nnc_batch {
     void *arena;
     nnc::BatchArgs a;       // device pointers, refreshed per call
     size_t arena_bytes;
-    int inited, features_on, eager;
+    int inited, features_on, eager, budget;
+    int has_d[2];           // scenes of dimension 2, 3 present
     double tick_us;         // microseconds per wall-clock tick (NNC_BATCH_TIMING)
     // the step as a graph: instantiated on the first call and replayed while
     // (positions, policy, tau) repeat; another key re-captures and updates it
@@ -594,15 +772,24 @@ int default_grid_b(int64_t n, int d)
     return g < 1.0 ? 1 : (int)g;
 }
 
-int launch_query_b(const nnc_batch *b, const nnc::BatchArgs &a, int init)
+template <int D>
+void launch_query_d(const nnc_batch *b, const nnc::BatchArgs &a, int init)
 {
     const int blocks = 2048;
     switch (b->lanes) {
-    case 1: hipLaunchKernelGGL(nnc::k_b_query<1>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
-    case 64: hipLaunchKernelGGL(nnc::k_b_query<64>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
-    case 32: hipLaunchKernelGGL(nnc::k_b_query<32>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
-    default: hipLaunchKernelGGL(nnc::k_b_query<16>, dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 1: hipLaunchKernelGGL((nnc::k_b_query<D, 1>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 64: hipLaunchKernelGGL((nnc::k_b_query<D, 64>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 32: hipLaunchKernelGGL((nnc::k_b_query<D, 32>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    default: hipLaunchKernelGGL((nnc::k_b_query<D, 16>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     }
+}
+
+// One launch per dimension present (each kernel holds one search, so the plane's
+// launch is not limited by the cube's register use).
+int launch_query_b(const nnc_batch *b, const nnc::BatchArgs &a, int init)
+{
+    if (b->has_d[0]) launch_query_d<2>(b, a, init);
+    if (b->has_d[1]) launch_query_d<3>(b, a, init);
     return nnc::check();
 }
 
@@ -620,6 +807,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     b->lanes = cfg->lanes == 1 || cfg->lanes == 32 || cfg->lanes == 64 ? cfg->lanes : 16;
     b->features_on = (cfg->flags & NNC_BATCH_FEATURES) != 0;
     b->eager = (cfg->flags & NNC_BATCH_EAGER) != 0;
+    b->budget = (cfg->flags & NNC_BATCH_BUDGET) != 0;
     b->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
     b->K = 1.0 / (4.0 + 4.0 * b->guard);
     b->stream = (hipStream_t)cfg->stream;
@@ -641,6 +829,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
             delete b;
             return NNC_E_INVAL;
         }
+        b->has_d[d - 2] = 1;
         nnc::SceneDesc &sd = b->desc[s];
         sd.n = (int)n;
         sd.d = d;
@@ -655,9 +844,9 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
         b->coord_off[s] = Q;
         P += n;
         Q += n * d;
-        NC += sd.ncell;
-        NS += sd.ncell + 1;
-        for (int64_t i0 = 0; i0 < n; i0 += nnc::kB) {
+        NC += (sd.ncell + 3) & ~3;      // cell regions start on 16-byte boundaries
+        NS += (sd.ncell + 1 + 3) & ~3;
+        for (int64_t i0 = 0; i0 < n; i0 += nnc::kTile) {
             b->tile_scene.push_back(s);
             b->tile_start.push_back((int)i0);
         }
@@ -682,8 +871,9 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     bytes += 2 * al(Pp * 4) + al(Pp * 8) + al(Pp);             // d1, d2, e, fail
     bytes += 4 * al(Pp * 4);                                   // stamp, frontier, touched x2
     bytes += 4 * al((size_t)NC * 4) + al((size_t)NS * 4);      // counts, cursor, hist x2, cell_start
-    bytes += 2 * al(T * 4) + 3 * al(S * 4) + al((S + 1) * 4);  // tiles, strategy/need/qcount, qpre
+    bytes += 2 * al(T * 4) + 3 * al(S * 4) + al(2 * (S + 1) * 4);  // tiles, strategy/need/qcount, qpre
     bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4) + al(4 * 4) + al(S * 3 * 8);
+    if (b->budget) bytes += al(Pp * 8) + al((size_t)NC * 4);   // certificate clocks, cell stamps
     if (hipMalloc(&b->arena, bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete b;
@@ -726,11 +916,15 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     a.strategy = (int *)take(S * 4);
     a.need_grid = (int *)take(S * 4);
     a.qcount = (int *)take(S * 4);
-    a.qpre = (int *)take((S + 1) * 4);
+    a.qpre = (int *)take(2 * (S + 1) * 4);
     a.features = (float *)take(S * NNC_FEATURES * 4);
     a.params = (const float *)take(NNC_SELECTOR_PARAMS * 4);
     a.tdev = (int *)take(4 * 4);
     unsigned long long *cost = (unsigned long long *)take(S * 3 * 8);
+    if (b->budget) {
+        a.Si = (double *)take(Pp * 8);
+        a.last_move = (int *)take((size_t)NC * 4);
+    }
     a.cost = (cfg->flags & NNC_BATCH_TIMING) ? cost : nullptr;
     a.scenes = b->S;
     b->arena_bytes = bytes;
@@ -793,7 +987,8 @@ int nnc_batch_init(nnc_batch *b, const float *pos)
         hipMemsetAsync(a.counts, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
         hipMemsetAsync(a.hist_fail, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
         hipMemsetAsync(a.hist_cand, 0, (size_t)b->NC * 4, b->stream) != hipSuccess ||
-        hipMemsetAsync(a.nn, 0xff, (size_t)(b->P > 0 ? b->P : 1) * 4, b->stream) != hipSuccess)
+        hipMemsetAsync(a.nn, 0xff, (size_t)(b->P > 0 ? b->P : 1) * 4, b->stream) != hipSuccess ||
+        (a.last_move && hipMemsetAsync(a.last_move, 0, (size_t)b->NC * 4, b->stream) != hipSuccess))
         return NNC_E_HIP;
     a.pos_cur = pos;
     a.init = 1;
@@ -818,6 +1013,8 @@ int launch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
     a.tau = tau;
     a.features_on = b->features_on;
     if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_ingest, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
+    if (b->budget && b->ntiles > 0)
+        hipLaunchKernelGGL(nnc::k_b_budget, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
     int rc = nnc::check();

@@ -47,11 +47,25 @@ def make_scenes(seed, count, nmax=6000, steps=10):
     return trajs, grids
 
 
-def run_batch(nnc, trajs, grids, policy, tau=0.5, params=None, lanes=16):
+def localized_scene(seed, d, n, steps, radius=0.15):
+    """Points of the unit box of which only those within `radius` of one centre move."""
+    g = np.random.default_rng(seed)
+    p = g.random((d, n))
+    c = np.full((d, 1), 0.4)
+    frames = [p.copy()]
+    for _ in range(steps):
+        movers = np.linalg.norm(p - c, axis=0) < radius
+        p = p + np.where(movers, g.standard_normal((d, n)) * 3e-4, 0.0)
+        frames.append(p.copy())
+    return synth.Trajectory("custom", d, n, -1.0, np.array(frames, dtype=np.float32))
+
+
+def run_batch(nnc, trajs, grids, policy, tau=0.5, params=None, lanes=16, budget=False):
     ns = [t.n for t in trajs]
     ds = [t.d for t in trajs]
-    b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, features=True)
-    oracles = [model.OracleScene(d=t.d, n=t.n, G=G) for t, G in zip(trajs, grids)]
+    b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, features=True, budget=budget)
+    rule = "budget" if budget else "clock"
+    oracles = [model.OracleScene(d=t.d, n=t.n, G=G, rule=rule) for t, G in zip(trajs, grids)]
     steps = trajs[0].steps
     frames = [dev(synth.concat_frame(trajs, t)) for t in range(steps + 1)]
     if params is not None:
@@ -106,6 +120,20 @@ def test_batch_policies_match_per_scene_oracles(nnc, policy):
         assert set(chosen) == {0}
     if policy == 1:
         assert set(chosen) == {1}
+
+
+@pytest.mark.parametrize("policy", [0, 2])
+def test_batch_budget_matches_per_scene_oracles(nnc, policy):
+    """The per-point motion budget in every scene (NNC_BATCH_BUDGET): candidates,
+    moved keys and certificates of each scene against its oracle under the budget
+    rule, with two scenes whose motion is confined to one ball (the block-local test
+    keeps the still blocks' certificates there)."""
+    trajs, grids = make_scenes(61 + policy, 8)
+    steps = trajs[0].steps
+    for k, d in enumerate((2, 3)):
+        trajs.append(localized_scene(70 + k, d, 6000 if d == 2 else 5000, steps))
+        grids.append(60 if d == 2 else 15)
+    run_batch(nnc, trajs, grids, policy, tau=0.45, budget=True)
 
 
 @pytest.mark.parametrize("lanes", [1, 32, 64])
