@@ -79,6 +79,7 @@ struct BatchArgs {
     int *strategy, *need_grid, *qcount, *qpre;
     float *features;
     const float *params;
+    const kc::QueryArgs *qs;  // per scene: the fixed part of its query view
 };
 
 namespace {
@@ -614,45 +615,25 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
     }
 }
 
-// Per-scene view of the concatenated arrays for the shared query routine.
-__device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, const SceneDesc &sd, int s, int init, int t)
+// Per-scene view of the concatenated arrays for the shared query routine: the
+// fixed part was built on the host at creation (one record per scene, read with
+// scalar loads), so the query kernel keeps only the scene's view live, not the
+// batch's base pointers as well; the step fills in what changes.
+__device__ __forceinline__ QueryArgs scene_view(const BatchArgs &a, int s, int init, int t)
 {
-    QueryArgs q;
-    q.pos = a.pos_cur + sd.coff;
-    q.slots = a.slots + sd.poff;
-    q.cell_start = a.cell_start + sd.soff;
-    q.cell = a.cell + sd.poff;
-    q.list = a.frontier + sd.poff;
-    q.count_dev = nullptr;
-    q.list_cap = 0;
-    q.n = sd.n;
-    q.G = sd.G;
+    // read through the constant address space: the records never change during a
+    // launch, so the compiler may use scalar loads (the view stays in SGPRs)
+#if __HIP_DEVICE_COMPILE__
+    using CView = const __attribute__((address_space(4))) QueryArgs;
+    QueryArgs q = ((CView *)a.qs)[s];
+#else
+    QueryArgs q = a.qs[s];  // (the host pass only parses this function)
+#endif
+    q.pos = a.pos_cur + a.desc[s].coff;
     q.all = a.strategy[s];
     q.init = init;
     q.t = t;
     q.parity = t & 1;
-    q.nn = a.nn + sd.poff;
-    q.stamp = a.stamp + sd.poff;
-    q.hist = a.hist_fail + sd.goff;
-    q.touched = a.touched_fail + sd.poff;
-    q.d1 = a.d1 + sd.poff;
-    q.d2 = a.d2 + sd.poff;
-    q.e = a.e + sd.poff;
-    q.Si = a.Si ? a.Si + sd.poff : nullptr;
-    q.cmask = nullptr;
-    q.qkey = nullptr;
-    q.tiled_from = 0;
-    q.fail = a.fail + sd.poff;
-    q.sc = &a.sc[s];
-    q.guard = a.guard;
-    q.K = a.K;
-    // scenes of a batch live in the unit box
-    for (int k = 0; k < 3; ++k) {
-        q.box.lo[k] = 0.0f;
-        q.box.s[k] = (float)sd.G;
-        q.box.w[k] = 1.0 / (double)sd.G;
-    }
-    q.fuzz = kFuzz;
     return q;
 }
 
@@ -687,8 +668,7 @@ __global__ void __launch_bounds__(kB) k_b_query(BatchArgs a, int init)
     while (g < q1) {
         const int first = qpre[s], next = qpre[s + 1];
         if (g < next) {
-            const SceneDesc sd = a.desc[s];
-            const QueryArgs q = scene_view(a, sd, s, init, t);
+            const QueryArgs q = scene_view(a, s, init, t);
             const double St = a.sc[s].S[parity];
             const double margin = query_margin(St, a.sc[s].S_grid, kFuzz);
             const int end = min(next, q1);
@@ -874,6 +854,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     bytes += 2 * al(T * 4) + 3 * al(S * 4) + al(2 * (S + 1) * 4);  // tiles, strategy/need/qcount, qpre
     bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4) + al(4 * 4) + al(S * 3 * 8);
     if (b->budget) bytes += al(Pp * 8) + al((size_t)NC * 4);   // certificate clocks, cell stamps
+    bytes += al(S * sizeof(nnc::kc::QueryArgs));               // per-scene query views
     if (hipMalloc(&b->arena, bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete b;
@@ -925,6 +906,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
         a.Si = (double *)take(Pp * 8);
         a.last_move = (int *)take((size_t)NC * 4);
     }
+    a.qs = (const nnc::kc::QueryArgs *)take(S * sizeof(nnc::kc::QueryArgs));
     a.cost = (cfg->flags & NNC_BATCH_TIMING) ? cost : nullptr;
     a.scenes = b->S;
     b->arena_bytes = bytes;
@@ -937,8 +919,41 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     }
     a.guard = b->guard;
     a.K = b->K;
+    // the fixed part of every scene's query view (scenes of a batch live in the unit box)
+    std::vector<nnc::kc::QueryArgs> qv(S);
+    for (size_t s = 0; s < S; ++s) {
+        const nnc::SceneDesc &sd = b->desc[s];
+        nnc::kc::QueryArgs &q = qv[s];
+        memset(&q, 0, sizeof(q));
+        q.slots = a.slots + sd.poff;
+        q.cell_start = a.cell_start + sd.soff;
+        q.cell = a.cell + sd.poff;
+        q.list = a.frontier + sd.poff;
+        q.n = sd.n;
+        q.G = sd.G;
+        q.nn = a.nn + sd.poff;
+        q.stamp = a.stamp + sd.poff;
+        q.hist = a.hist_fail + sd.goff;
+        q.touched = a.touched_fail + sd.poff;
+        q.d1 = a.d1 + sd.poff;
+        q.d2 = a.d2 + sd.poff;
+        q.e = a.e + sd.poff;
+        q.Si = a.Si ? a.Si + sd.poff : nullptr;
+        q.fail = a.fail + sd.poff;
+        q.sc = a.sc + s;
+        q.guard = a.guard;
+        q.K = a.K;
+        for (int k = 0; k < 3; ++k) {
+            q.box.lo[k] = 0.0f;
+            q.box.s[k] = (float)sd.G;
+            q.box.w[k] = 1.0 / (double)sd.G;
+        }
+        q.fuzz = nnc::kc::kFuzz;
+    }
     int rc = NNC_OK;
-    if (hipMemcpyAsync((void *)a.desc, b->desc.data(), S * sizeof(nnc::SceneDesc), hipMemcpyHostToDevice,
+    if (hipMemcpyAsync((void *)a.qs, qv.data(), S * sizeof(nnc::kc::QueryArgs), hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipMemcpyAsync((void *)a.desc, b->desc.data(), S * sizeof(nnc::SceneDesc), hipMemcpyHostToDevice,
                        b->stream) != hipSuccess ||
         (b->ntiles > 0 &&
          (hipMemcpyAsync((void *)a.tile_scene, b->tile_scene.data(), b->ntiles * 4, hipMemcpyHostToDevice,

@@ -293,7 +293,7 @@ struct QueryArgs {
                                // null for a single scene, whose entropy scans hist
     float *d1, *d2;
     double *e;
-    double *Si;                // clock of each certificate (a single scene; null in a batch)
+    double *Si;                // clock of each certificate (per-point budget), or null
     uint8_t *cmask;            // tiled repair: candidates marked in slot order (cleared as read); else null
     double *qkey;              // expiry calendar: new key of list entry q written at qkey[q]; else null
     int tiled_from;            // > 0: candidate lists of at least this many entries go to the tiled
