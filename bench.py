@@ -74,6 +74,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--batch-tune", type=int, default=1,
                     help="1: time the batch tuner's choices; 0: use its usual choice without timing")
+    ap.add_argument("--batch-policies", default="repair,rebuild,threshold,learned,repair_budget",
+                    help="policies of the batched leg")
+    ap.add_argument("--batch-loops", type=int, default=1,
+                    help="1: also time the one-context-per-scene baselines")
     ap.add_argument("--regret-scenes", type=int, default=100)
     ap.add_argument("--regret-steps", type=int, default=40)
     ap.add_argument("--grid", default="table",
@@ -165,6 +169,8 @@ def batched_leg(args, nnc, synth, autotune, torch):
     if params is not None:
         policies.append(("learned", 3, False))
     policies.append(("repair_budget", 0, True))
+    wanted = set(args.batch_policies.split(","))
+    policies = [p for p in policies if p[0] in wanted]
     pdev = torch.from_numpy(params).cuda() if params is not None else None
     for name, pol, budget in policies:
         with torch.cuda.stream(s):
@@ -200,6 +206,8 @@ def batched_leg(args, nnc, synth, autotune, torch):
                                   "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": nbytes}}
         del g
         b.close()
+    if not args.batch_loops:
+        return res
     # the same scenes, one context per scene, advanced one after another (graph-captured)
     per = min(steps, 10)
     tr_frames = [[torch.from_numpy(tr.frames[t]).cuda() for t in range(per + 2)] for tr in trajs]
