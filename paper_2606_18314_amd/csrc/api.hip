@@ -69,7 +69,7 @@ size_t carve(nnc_ctx *c, char *base)
     c->wide = k.take<int32_t>(n);
     c->rec = k.take<int4>(n);
     c->cmask = k.take<uint8_t>(n);
-    c->ntcount = (int)((n + 4095) / 4096 + 1);
+    c->ntcount = (int)(((n + 4095) / 4096 + 1 + 3) & ~3ll);  // whole groups of four (k_filter_offsets)
     c->tcount = k.take<int32_t>((size_t)c->ntcount);
     c->nfmask = (long long)((n + 4095) / 4096 + 1) * 64;
     c->fmask = k.take<unsigned long long>((size_t)c->nfmask);

@@ -338,11 +338,12 @@ __global__ void __launch_bounds__(kSmallB) k_filter_small(const double *__restri
 
 // Reduce-then-scan filter for large N (no chain between tiles): k_filter_count
 // advances the clock, stores each tile's candidate ballots (one bit per point)
-// and counts them, k_filter_offsets scans the counts in one workgroup,
+// (each wave's as one contiguous run) and counts them, k_filter_offsets scans
+// the counts in one workgroup,
 // k_filter_write reads the ballots back (not the keys) and writes each tile's
 // candidates at its offset, in index order.  The fail flags are cleared over the
-// previous step's candidates (the only ones its repair could set) unless the host
-// asks for all of them (after a rebuild, a caller's list or a restore).
+// previous step's candidates (the only ones its repair could set) when that list
+// is short, else all of them, as after a rebuild, a caller's list or a restore.
 constexpr int kFRows = 16;                // items per thread in the counting tiles
 constexpr int kFTile = kB * kFRows;       // 4096 items per tile
 constexpr int kFMasks = kFRows * (kB / 64);  // ballot words per tile
@@ -353,31 +354,52 @@ __global__ void __launch_bounds__(kB) k_filter_count(const double *__restrict__ 
                                                      int clear_all, const int *__restrict__ prev_list)
 {
     __shared__ int s_w[kB / 64];
-    const double St = advance_clock(sc, parity, eps_decl, blockIdx.x == 0 && threadIdx.x < 64);
     const long long base = (long long)blockIdx.x * kFTile;
+    // the tile's keys are requested before the clock's dependent loads and stores
+    double ev[kFRows];
+#pragma unroll
+    for (int k = 0; k < kFRows; ++k) {
+        const long long i = base + (long long)k * kB + threadIdx.x;
+        ev[k] = i < n ? e[i] : __builtin_inf();
+    }
+    const double St = advance_clock(sc, parity, eps_decl, blockIdx.x == 0 && threadIdx.x < 64);
     const int w = (int)(threadIdx.x >> 6);
-    int c = 0;
+    const int lane = (int)lane_id();
+    int c = 0;  // wave-uniform
+    // a list longer than n / 64 costs more in scattered byte stores (a cache line
+    // each) than streaming zeros over all n flags
+    const int prev = min(sc->nfront, n);  // the count is rewritten only by the next kernel
+    clear_all = clear_all || (long long)prev * 64 > (long long)n;
     if (!clear_all) {
-        const int prev = min(sc->nfront, n);  // the count is rewritten only by the next kernel
         for (int q = blockIdx.x * kB + (int)threadIdx.x; q < prev; q += gridDim.x * kB) {
             const int i = prev_list[q];
             if (i >= 0 && i < n) fail[i] = 0;
         }
     }
+    // the wave's kFRows ballots, lane k holding row k's, stored as one contiguous run
+    unsigned long long mine = 0;
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
         const long long i = base + (long long)k * kB + threadIdx.x;
-        bool cand = false;
-        if (i < n) {
-            cand = St >= e[i];
-            if (clear_all) fail[i] = 0;
-        }
-        const unsigned long long m = __ballot(cand);
-        if (lane_id() == 0) fmask[(long long)blockIdx.x * kFMasks + k * (kB / 64) + w] = m;
-        c += cand ? 1 : 0;
+        const unsigned long long m = __ballot(i < n && St >= ev[k]);
+        c += __popcll(m);
+        if (lane == k) mine = m;
     }
-    c = wave_sum(c);
-    if (lane_id() == 0) s_w[threadIdx.x >> 6] = c;
+    if (lane < kFRows) fmask[(long long)blockIdx.x * kFMasks + w * kFRows + lane] = mine;
+    if (clear_all) {
+        // the tile's flags as 16-byte stores (fail is 256-byte aligned; a partial last tile
+        // clears byte by byte)
+        static_assert(kFTile % (16 * kB) == 0, "whole 16-byte stores per tile");
+#pragma unroll
+        for (int u = 0; u < kFTile / (16 * kB); ++u) {
+            const long long f0 = base + 16ll * (u * kB + (int)threadIdx.x);
+            if (f0 + 16 <= n)
+                *reinterpret_cast<uint4 *>(fail + f0) = make_uint4(0u, 0u, 0u, 0u);
+            else
+                for (long long i = f0; i < n && i < f0 + 16; ++i) fail[i] = 0;
+        }
+    }
+    if (lane == 0) s_w[w] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
@@ -386,19 +408,49 @@ __global__ void __launch_bounds__(kB) k_filter_count(const double *__restrict__ 
     }
 }
 
+// Each thread scans a contiguous run of the tile counts, four at a time (one
+// workgroup scan in all; tcount is 256-byte aligned and holds at least
+// tiles rounded up to four, with a zero beyond the last tile, see the sizing).
 __global__ void __launch_bounds__(1024) k_filter_offsets(int *__restrict__ tcount, int tiles, DevScalars *sc)
 {
     __shared__ int s_w[1024 / 64];
-    int run = 0;
-    for (int base = 0; base < tiles; base += 1024) {
-        const int t = base + (int)threadIdx.x;
-        const int v = t < tiles ? tcount[t] : 0;
-        int tot;
-        const int ex = block_excl_scan<1024>(v, s_w, tot);
-        if (t < tiles) tcount[t] = run + ex;
-        run += tot;
+    const int t4 = (tiles + 3) >> 2;                       // groups of four
+    const int per = (t4 + 1023) / 1024;
+    const int g0 = min((int)threadIdx.x * per, t4), g1 = min(g0 + per, t4);
+    int4 *tc4 = reinterpret_cast<int4 *>(tcount);
+    auto get = [&](int g) {
+        int4 v = tc4[g];
+        const int t = 4 * g;  // entries past the last tile count as zero
+        if (t + 1 >= tiles) v.y = 0;
+        if (t + 2 >= tiles) v.z = 0;
+        if (t + 3 >= tiles) v.w = 0;
+        return v;
+    };
+    int sum = 0;
+    for (int g = g0; g < g1; ++g) {
+        const int4 v = get(g);
+        sum += v.x + v.y + v.z + v.w;
     }
-    if (threadIdx.x == 0) sc->nfront = run;
+    int tot;
+    int run = block_excl_scan<1024>(sum, s_w, tot);
+    for (int g = g0; g < g1; ++g) {
+        const int4 v = get(g);
+        int4 o;
+        o.x = run;
+        o.y = run + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        run = o.w + v.w;
+        const int t = 4 * g;
+        if (t + 3 < tiles) {
+            tc4[g] = o;
+        } else {
+            tcount[t] = o.x;
+            if (t + 1 < tiles) tcount[t + 1] = o.y;
+            if (t + 2 < tiles) tcount[t + 2] = o.z;
+        }
+    }
+    if (threadIdx.x == 0) sc->nfront = tot;
 }
 
 __global__ void __launch_bounds__(kB) k_filter_write(int n, const unsigned long long *__restrict__ fmask,
@@ -409,21 +461,41 @@ __global__ void __launch_bounds__(kB) k_filter_write(int n, const unsigned long 
     const int w = threadIdx.x >> 6;
     const unsigned lane = lane_id();
     const long long base = (long long)blockIdx.x * kFTile;
+    const int t0 = threadIdx.x < 64 ? toff[blockIdx.x] : 0;  // requested with the ballots
+    // the wave's ballots: one load (lane k: row k), then broadcast
+    const unsigned long long mine =
+        lane < (unsigned)kFRows ? fmask[(long long)blockIdx.x * kFMasks + w * kFRows + lane] : 0ull;
     unsigned long long masks[kFRows];
 #pragma unroll
     for (int k = 0; k < kFRows; ++k) {
-        masks[k] = fmask[(long long)blockIdx.x * kFMasks + k * (kB / 64) + w];
+        masks[k] = __shfl(mine, k, 64);
         if (lane == 0) s_cnt[k][w] = __popcll(masks[k]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = toff[blockIdx.x];
-        for (int k = 0; k < kFRows; ++k)
-            for (int v = 0; v < kB / 64; ++v) {
-                const int c = s_cnt[k][v];
-                s_cnt[k][v] = run;
-                run += c;
-            }
+    // the tile's (row, wave) counts in index order: one exclusive scan by the first
+    // wave, each lane taking CPL consecutive counts
+    constexpr int CPL = kFRows * (kB / 64) / 64;
+    static_assert(CPL * 64 == kFRows * (kB / 64), "whole counts per lane");
+    if (threadIdx.x < 64) {
+        int *flat = &s_cnt[0][0] + CPL * threadIdx.x;
+        int v[CPL], sum = 0;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            v[u] = flat[u];
+            sum += v[u];
+        }
+        int incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if ((int)lane >= off) incl += o;
+        }
+        int run = t0 + incl - sum;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            flat[u] = run;
+            run += v[u];
+        }
     }
     __syncthreads();
 #pragma unroll
