@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--queue-exps", default="20,22,24", help="log2 N of the queue leg's scenes")
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--repeats", type=int, default=5, help="timed replays per leg (the median is reported)")
+    ap.add_argument("--scaling-lanes", type=int, default=4, help="lanes per query of the scaling leg's queries")
     ap.add_argument("--scaling-exps", default="16,18,20,22,24,26",
                     help="log2 N of the scaling leg's scenes")
     ap.add_argument("--scenes", type=int, default=512)
@@ -153,8 +154,8 @@ def batched_leg(args, nnc, synth, autotune, torch):
     if args.batch_tune:
         grids, lanes, table = autotune.tune_batch(frames, ns, ds, eps_steps=8, stream=s)
     else:   # the tuner's usual choice, without its timing sweep
-        lanes, table = 16, {}
-        grids = autotune.batch_grids(frames[0], ns, ds, lanes=16, factor=1.5, cells_per_point=8)
+        lanes, table = 4, {}
+        grids = autotune.batch_grids(frames[0], ns, ds, lanes=4, factor=1.5, cells_per_point=8)
     params, meta = selector.load_params()
     tau = float(meta.get("tau", 0.5)) if meta else 0.5
     total = sum(ns)
@@ -317,13 +318,13 @@ def mixed_eps_batch(nnc, synth, autotune, selector, torch, params, meta, tau, sc
     ns = [t.n for t in trajs]
     ds = [t.d for t in trajs]
     frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 2)]
-    grids = autotune.batch_grids(frames[0], ns, ds, lanes=16, factor=1.5, cells_per_point=8)
+    grids = autotune.batch_grids(frames[0], ns, ds, lanes=4, factor=1.5, cells_per_point=8)
     s = torch.cuda.Stream()
     pdev = torch.from_numpy(params).cuda()
     out = {"scenes": scenes, "points": sum(ns), "steps": steps}
     for name, pol in (("repair", 0), ("rebuild", 1), ("threshold", 2), ("learned", 3)):
         with torch.cuda.stream(s):
-            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=16, stream=s.cuda_stream)
+            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=4, stream=s.cuda_stream)
             b.selector_load(pdev)
             band = meta.get("band", [0.0, 2.0])
             b.selector_band(band[0], band[1])
@@ -387,10 +388,10 @@ def sweep_leg(args, nnc, synth, torch):
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    # lanes per query: the faster of 1 and 16 on repair + rebuild of a 5% diffuse transition
+    # lanes per query: the fastest of 1, 4, 8 and 16 on repair + rebuild of a 5% diffuse transition
     lanes_table = {}
     c = None
-    for L in (1, 16):
+    for L in (1, 4, 8, 16):
         with torch.cuda.stream(s):
             ctx = nnc.NNCert(n, d, grid_g=G, stream=s.cuda_stream, lanes=L)
             ctx.init_certificates(P0)
@@ -657,7 +658,7 @@ def scaling_leg(args, nnc, synth, torch):
     for e in [int(v) for v in args.scaling_exps.split(",") if v]:
         n = 1 << e
         p0 = synth.device_uniform(n, d, seed=7000 + e)
-        ctx = nnc.NNCert(n, d, lanes=16)
+        ctx = nnc.NNCert(n, d, lanes=args.scaling_lanes)
         G = ctx.grid_g
         ctx.init_certificates(p0)
         st = ctx.state()

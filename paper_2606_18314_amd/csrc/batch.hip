@@ -727,6 +727,7 @@ inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP
 
 struct nnc_batch {
     int S, lanes;
+    int lanes2, lanes3;     // lanes per query in the plane and in the cube
     double guard, K;
     hipStream_t stream;
     std::vector<nnc::SceneDesc> desc;
@@ -764,10 +765,18 @@ template <int D>
 void launch_query_d(const nnc_batch *b, const nnc::BatchArgs &a, int init)
 {
     const int blocks = 2048;
-    switch (b->lanes) {
+    switch (D == 2 ? b->lanes2 : b->lanes3) {
     case 1: hipLaunchKernelGGL((nnc::k_b_query<D, 1>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     case 64: hipLaunchKernelGGL((nnc::k_b_query<D, 64>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     case 32: hipLaunchKernelGGL((nnc::k_b_query<D, 32>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 4:
+        if constexpr (D == 2)
+            hipLaunchKernelGGL((nnc::k_b_query<2, 4>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init);
+        break;
+    case 8:
+        if constexpr (D == 2)
+            hipLaunchKernelGGL((nnc::k_b_query<2, 8>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init);
+        break;
     default: hipLaunchKernelGGL((nnc::k_b_query<D, 16>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     }
 }
@@ -792,7 +801,14 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     nnc_batch *b = new (std::nothrow) nnc_batch();
     if (!b) return NNC_E_NOMEM;
     b->S = cfg->scenes;
-    b->lanes = cfg->lanes == 1 || cfg->lanes == 32 || cfg->lanes == 64 ? cfg->lanes : 16;
+    b->lanes = cfg->lanes == 1 || cfg->lanes == 4 || cfg->lanes == 8 || cfg->lanes == 16 || cfg->lanes == 32 ||
+                       cfg->lanes == 64
+                   ? cfg->lanes
+                   : 0;
+    // a plane block has three rows, a cube block nine: groups narrower than 16 serve the
+    // plane only (more queries in flight per wave; measured faster there)
+    b->lanes2 = b->lanes == 0 ? 4 : b->lanes;
+    b->lanes3 = b->lanes == 0 || b->lanes == 4 || b->lanes == 8 ? 16 : b->lanes;
     b->features_on = (cfg->flags & NNC_BATCH_FEATURES) != 0;
     b->eager = (cfg->flags & NNC_BATCH_EAGER) != 0;
     b->budget = (cfg->flags & NNC_BATCH_BUDGET) != 0;

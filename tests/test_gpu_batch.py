@@ -60,7 +60,7 @@ def localized_scene(seed, d, n, steps, radius=0.15):
     return synth.Trajectory("custom", d, n, -1.0, np.array(frames, dtype=np.float32))
 
 
-def run_batch(nnc, trajs, grids, policy, tau=0.5, params=None, lanes=16, budget=False):
+def run_batch(nnc, trajs, grids, policy, tau=0.5, params=None, lanes=0, budget=False):
     ns = [t.n for t in trajs]
     ds = [t.d for t in trajs]
     b = nnc.NNCBatch(ns, ds, grids=grids, lanes=lanes, features=True, budget=budget)
@@ -136,7 +136,7 @@ def test_batch_budget_matches_per_scene_oracles(nnc, policy):
     run_batch(nnc, trajs, grids, policy, tau=0.45, budget=True)
 
 
-@pytest.mark.parametrize("lanes", [1, 32, 64])
+@pytest.mark.parametrize("lanes", [1, 8, 16, 32, 64])
 def test_batch_lane_widths(nnc, lanes):
     trajs, grids = make_scenes(21, 6, nmax=4000, steps=6)
     run_batch(nnc, trajs, grids, 2, tau=0.5, lanes=lanes)

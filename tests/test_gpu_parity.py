@@ -182,6 +182,16 @@ def test_lanes_per_query_and_fine_grids(nnc, lanes, d):
     run_parity(nnc, tr, G=64 if d == 3 else 200, lanes=lanes, strategy="alternate")
 
 
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_plane_narrow_lane_groups(nnc, lanes):
+    """Lane groups narrower than 16 (the plane only: its block has three rows), on a
+    grid fine enough that most queries widen, with repairs and rebuilds."""
+    tr = synth.make_trajectory("clustered_drift", 3000, 2, 12, 5e-4, 79)
+    run_parity(nnc, tr, G=200, lanes=lanes, strategy="alternate")
+    tr = synth.make_trajectory("uniform_brownian", 5000, 2, 10, 2e-3, 80)
+    run_parity(nnc, tr, G=35, lanes=lanes, strategy="alternate")
+
+
 @pytest.mark.parametrize("lanes", [1, 16])
 @pytest.mark.parametrize("G", [1, 2, 5, 33])
 @pytest.mark.parametrize("d", [2, 3])
@@ -450,14 +460,14 @@ def test_isolated_point_forces_widening(nnc):
         frames.append(q)
     tr = synth.Trajectory("custom", 2, n, -1.0, np.array(frames, dtype=np.float32))
     run_parity(nnc, tr, G=40)
-    for lanes in (1, 16, 64):
+    for lanes in (1, 4, 8, 16, 64):
         run_parity(nnc, tr, G=40, lanes=lanes)
     p3 = np.concatenate([np.array(frames), 0.1 + 0.02 * g.random((6, 1, n))], axis=1)
     p3[:, 2, -1] = 0.97
     run_parity(nnc, synth.Trajectory("custom", 3, n, -1.0, p3.astype(np.float32)), G=25, lanes=32)
 
 
-@pytest.mark.parametrize("lanes", [1, 16, 64])
+@pytest.mark.parametrize("lanes", [1, 4, 16, 64])
 @pytest.mark.parametrize("d", [2, 3])
 def test_cutoff_with_mixed_density_and_large_steps(nnc, d, lanes):
     """Dense clusters beside sparse outliers on a fine grid, with steps that vary
