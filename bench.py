@@ -154,8 +154,8 @@ def batched_leg(args, nnc, synth, autotune, torch):
     if args.batch_tune:
         grids, lanes, table = autotune.tune_batch(frames, ns, ds, eps_steps=8, stream=s)
     else:   # the tuner's usual choice, without its timing sweep
-        lanes, table = 4, {}
-        grids = autotune.batch_grids(frames[0], ns, ds, lanes=4, factor=1.5, cells_per_point=8)
+        lanes, table = 0, {}   # the library's default: 4 lanes per plane query, 8 per cube query
+        grids = autotune.batch_grids(frames[0], ns, ds, lanes=0, factor=1.5, cells_per_point=8)
     params, meta = selector.load_params()
     tau = float(meta.get("tau", 0.5)) if meta else 0.5
     total = sum(ns)
@@ -209,13 +209,17 @@ def batched_leg(args, nnc, synth, autotune, torch):
         b.close()
     if not args.batch_loops:
         return res
+
+    def scene_lanes(d):
+        """The batch's lanes per query for a scene of dimension d (its default: 4 / 8)."""
+        return (4 if d == 2 else 8) if lanes == 0 else lanes
     # the same scenes, one context per scene, advanced one after another (graph-captured)
     per = min(steps, 10)
     tr_frames = [[torch.from_numpy(tr.frames[t]).cuda() for t in range(per + 2)] for tr in trajs]
     ctxs = []
     with torch.cuda.stream(s):
         for k, tr in enumerate(trajs):
-            c = nnc.NNCert(ns[k], ds[k], grid_g=grids[k], stream=s.cuda_stream, lanes=lanes)
+            c = nnc.NNCert(ns[k], ds[k], grid_g=grids[k], stream=s.cuda_stream, lanes=scene_lanes(ds[k]))
             c.init_certificates(tr_frames[k][0])
             c.step(tr_frames[k][1], 5e-4)
             c.repair()
@@ -248,7 +252,7 @@ def batched_leg(args, nnc, synth, autotune, torch):
     for k, tr in enumerate(trajs):
         st_k = bstreams[k % nstreams]
         with torch.cuda.stream(st_k):
-            c = nnc.NNCert(ns[k], ds[k], grid_g=grids[k], stream=st_k.cuda_stream, lanes=lanes)
+            c = nnc.NNCert(ns[k], ds[k], grid_g=grids[k], stream=st_k.cuda_stream, lanes=scene_lanes(ds[k]))
             c.init_certificates(tr_frames[k][0])
             c.step(tr_frames[k][1], 5e-4)
             c.repair()
@@ -318,13 +322,13 @@ def mixed_eps_batch(nnc, synth, autotune, selector, torch, params, meta, tau, sc
     ns = [t.n for t in trajs]
     ds = [t.d for t in trajs]
     frames = [torch.from_numpy(synth.concat_frame(trajs, t)).cuda() for t in range(steps + 2)]
-    grids = autotune.batch_grids(frames[0], ns, ds, lanes=4, factor=1.5, cells_per_point=8)
+    grids = autotune.batch_grids(frames[0], ns, ds, lanes=0, factor=1.5, cells_per_point=8)
     s = torch.cuda.Stream()
     pdev = torch.from_numpy(params).cuda()
     out = {"scenes": scenes, "points": sum(ns), "steps": steps}
     for name, pol in (("repair", 0), ("rebuild", 1), ("threshold", 2), ("learned", 3)):
         with torch.cuda.stream(s):
-            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=4, stream=s.cuda_stream)
+            b = nnc.NNCBatch(ns, ds, grids=grids, lanes=0, stream=s.cuda_stream)
             b.selector_load(pdev)
             band = meta.get("band", [0.0, 2.0])
             b.selector_band(band[0], band[1])

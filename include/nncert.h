@@ -111,9 +111,8 @@ typedef struct {
     uint32_t flags;       /* NNC_COPY_POSITIONS | NNC_SYNC | NNC_QUERY_TILED | NNC_QUERY_POINTWISE |
                              NNC_BUDGET | NNC_QUEUE */
     int32_t  block;       /* lanes that share one 2-NN query: 1 (one thread per query,
-                             for large N), 4 or 8 (d = 2 only: a 3^2 block has three
-                             rows; in d = 3 these mean the default), 16, 32 or 64;
-                             0 = 32 for d = 3 and 16 for d = 2 */
+                             for large N), 4 (d = 2 only; in d = 3 it means the
+                             default), 8, 16, 32 or 64; 0 = 32 for d = 3 and 16 for d = 2 */
     /* Domain box of the grid: axis k is cut into grid_g equal cells over
      * [lo[k], hi[k]); a point's cell on axis k is floor(fl32(fl32(x - lo[k]) * s_k))
      * clamped to [0, grid_g - 1], s_k = fl32(grid_g / (hi[k] - lo[k])) with the
@@ -339,8 +338,8 @@ typedef struct {
     const int64_t *n;        /* host [scenes]: points per scene, 0 <= n <= NNC_BATCH_MAX_N */
     const int32_t *d;        /* host [scenes]: 2 or 3 */
     const int32_t *grid_g;   /* host [scenes]: cells per axis; NULL or entries <= 0 = occupancy rule */
-    int32_t lanes;           /* lanes per query: 1, 4, 8, 16, 32 or 64 (4 and 8 in the plane;
-                                cube scenes then use 16); 0 = 4 in the plane, 16 in the cube */
+    int32_t lanes;           /* lanes per query: 1, 4, 8, 16, 32 or 64 (4 in the plane only;
+                                cube scenes then use 16); 0 = 4 in the plane, 8 in the cube */
     double guard;            /* as in nnc_config */
     double refresh;          /* as in nnc_config */
     void *stream;            /* hipStream_t */

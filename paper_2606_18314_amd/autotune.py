@@ -115,7 +115,7 @@ def batch_grids(frame0: torch.Tensor, ns, ds, target: float = 4.0, lanes: int = 
     return grids
 
 
-def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(1.25, 1.5, 2.0), caps=(8, 16), lanes=(4, 8, 16),
+def tune_batch(frames, ns, ds, eps_steps: int = 4, factors=(1.25, 1.5, 2.0), caps=(8, 16), lanes=(0, 8, 16),
                policy: int = 0, stream=None):
     """Fastest (grid factor, cells-per-point cap, lanes) for a batch over a few steps;
     returns (grids, lanes, table)."""

@@ -225,7 +225,7 @@ int nnc_create(nnc_ctx **out, const nnc_config *cfg)
     c->ncell = (int)cells;
     c->block = 256;
     c->lanes = cfg->block == 1 || cfg->block == 16 || cfg->block == 32 || cfg->block == 64 ? cfg->block
-               : (cfg->block == 4 || cfg->block == 8) && cfg->d == 2                        ? cfg->block
+               : cfg->block == 8 || (cfg->block == 4 && cfg->d == 2)                        ? cfg->block
                                                                                              : (cfg->d == 3 ? 32 : 16);
     c->guard = cfg->guard < 0.0 ? 0x1p-18 : cfg->guard;
     c->K = 1.0 / (4.0 + 4.0 * c->guard);

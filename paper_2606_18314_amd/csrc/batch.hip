@@ -773,10 +773,7 @@ void launch_query_d(const nnc_batch *b, const nnc::BatchArgs &a, int init)
         if constexpr (D == 2)
             hipLaunchKernelGGL((nnc::k_b_query<2, 4>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init);
         break;
-    case 8:
-        if constexpr (D == 2)
-            hipLaunchKernelGGL((nnc::k_b_query<2, 8>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init);
-        break;
+    case 8: hipLaunchKernelGGL((nnc::k_b_query<D, 8>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     default: hipLaunchKernelGGL((nnc::k_b_query<D, 16>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
     }
 }
@@ -805,10 +802,11 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
                        cfg->lanes == 64
                    ? cfg->lanes
                    : 0;
-    // a plane block has three rows, a cube block nine: groups narrower than 16 serve the
-    // plane only (more queries in flight per wave; measured faster there)
+    // a plane block has three rows, a cube block nine: groups of 4 serve the plane only
+    // (narrow groups keep more queries in flight per wave; measured faster: the default
+    // 4 in the plane and 8 in the cube)
     b->lanes2 = b->lanes == 0 ? 4 : b->lanes;
-    b->lanes3 = b->lanes == 0 || b->lanes == 4 || b->lanes == 8 ? 16 : b->lanes;
+    b->lanes3 = b->lanes == 0 ? 8 : b->lanes == 4 ? 16 : b->lanes;
     b->features_on = (cfg->flags & NNC_BATCH_FEATURES) != 0;
     b->eager = (cfg->flags & NNC_BATCH_EAGER) != 0;
     b->budget = (cfg->flags & NNC_BATCH_BUDGET) != 0;

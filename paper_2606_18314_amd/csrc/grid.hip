@@ -1314,6 +1314,7 @@ void launch_pointwise(nnc_ctx *c, const QueryArgs &a)
         if (c->lanes == 64) launch_query_t<3, 64>(a, maxq, c->stream, c->unit_box);
         else if (c->lanes == 32) launch_query_t<3, 32>(a, maxq, c->stream, c->unit_box);
         else if (c->lanes == 1) launch_query_t<3, 1>(a, maxq, c->stream, c->unit_box);
+        else if (c->lanes == 8) launch_query_t<3, 8>(a, maxq, c->stream, c->unit_box);
         else launch_query_t<3, 16>(a, maxq, c->stream, c->unit_box);
     }
 }

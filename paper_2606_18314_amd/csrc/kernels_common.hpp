@@ -492,29 +492,56 @@ __device__ __forceinline__ bool scan_block(const QueryArgs &a, float x, float y,
         }
         return any;
     }
-    static_assert(L == 1 || L >= R, "a group needs one lane per row");
-    int rs = 0, rl = 0;
-    bool cut = false;
-    if (lane < R) {
-        const int dy = lane % 3 - 1, dz = D == 3 ? lane / 3 - 1 : 0;
+    // one lane per row; a group of 8 in the cube also gives its first lane the ninth row
+    static_assert(L == 1 || L >= R || (D == 3 && L == 8), "a group needs a lane per row");
+    constexpr int RL = R < L ? R : L;  // rows held one per lane
+    auto row_bounds = [&](int r, int &rs_, int &rl_, bool &cut_) {
+        const int dy = r % 3 - 1, dz = D == 3 ? r / 3 - 1 : 0;
         const int cy = gy + dy, cz = gz + dz;
         if (cy >= 0 && cy < G && cz >= 0 && cz < (D == 3 ? G : 1)) {
             int xlo, xhi;
-            block_row<D>(glo, ghi, T2, gx, G, dy, dz, xlo, xhi, cut);
+            block_row<D>(glo, ghi, T2, gx, G, dy, dz, xlo, xhi, cut_);
             if (xlo <= xhi) {
                 const int row = (cz * G + cy) * G;
-                rs = a.cell_start[row + xlo];
-                rl = a.cell_start[row + xhi + 1] - rs;
+                rs_ = a.cell_start[row + xlo];
+                rl_ = a.cell_start[row + xhi + 1] - rs_;
             }
         }
+    };
+    int rs = 0, rl = 0;
+    bool cut = false;
+    if (lane < RL) row_bounds(lane, rs, rl, cut);
+    int rs9 = 0, rl9 = 0;  // the ninth row of a group of 8 (its first lane)
+    if constexpr (RL < R) {
+        bool cut9 = false;
+        if (lane == 0) row_bounds(8, rs9, rl9, cut9);
+        cut |= cut9;
     }
     const unsigned long long gmask = L == 64 ? ~0ull : ((1ull << L) - 1) << (lane_id() & ~(unsigned)(L - 1));
     const bool any = (__ballot(cut) & gmask) != 0;
     int incl = rl;
 #pragma unroll
-    for (int off = 1; off < R; off <<= 1) {
+    for (int off = 1; off < RL; off <<= 1) {
         const int v = __shfl_up(incl, off, L);
         if (lane >= off) incl += v;
+    }
+    if constexpr (RL < R) {
+        // eight rows on the lanes, the ninth after them: its prefix is the others' sum
+        const int pre9 = __shfl(incl, RL - 1, L);
+        const int start9 = __shfl(rs9, 0, L);
+        const int total = pre9 + __shfl(rl9, 0, L);
+        const int pre = incl - rl;
+        walk_slots<D, L>(a, x, y, z, i, total, lane, t, [&](int kk) {
+            int lo = 0;
+#pragma unroll
+            for (int step = L / 2; step > 0; step >>= 1) {
+                const int p = __shfl(pre, lo + step, L);
+                if (p <= kk) lo += step;
+            }
+            const int in_row = __shfl(rs, lo, L) + (kk - __shfl(pre, lo, L));
+            return kk >= pre9 ? start9 + (kk - pre9) : in_row;
+        });
+        return any;
     }
     const int total = __shfl(incl, R - 1, L);
     if constexpr (D == 3) {

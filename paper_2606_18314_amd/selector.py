@@ -106,7 +106,7 @@ def scene_cost(st: dict) -> float:
     return WAVES_PER_WORKGROUP * st["t_grid_us"] + st["t_query_us"]
 
 
-def collect_batched(specs, steps: int, batch_size: int = 128, lanes: int = 4, log=None):
+def collect_batched(specs, steps: int, batch_size: int = 128, lanes: int = 0, log=None):
     """Features and the in-batch costs of both strategies of every scene-step.
 
     Scenes are advanced in batches with the deployment's grids (the batch tuner's
@@ -156,7 +156,7 @@ def collect_batched(specs, steps: int, batch_size: int = 128, lanes: int = 4, lo
     return {"X": np.array(X, np.float32), "t_repair": np.array(trep), "t_rebuild": np.array(treb)}
 
 
-def inference_cost(specs, steps: int, params: np.ndarray, tau: float, lanes: int = 4, reps: int = 5):
+def inference_cost(specs, steps: int, params: np.ndarray, tau: float, lanes: int = 0, reps: int = 5):
     """Per scene-step cost of the learned policy's features and network inside the batched
     step, in the labels' unit (wave-microseconds).  The same step is run from the same
     state under the size rule set to always repair and under the learned policy with a

@@ -174,7 +174,7 @@ def test_extra_families_reduced(nnc, family, d):
     run_parity(nnc, tr, G=9 if d == 3 else 32, strategy="alternate")
 
 
-@pytest.mark.parametrize("lanes", [1, 16, 32, 64])
+@pytest.mark.parametrize("lanes", [1, 8, 16, 32, 64])
 @pytest.mark.parametrize("d", [2, 3])
 def test_lanes_per_query_and_fine_grids(nnc, lanes, d):
     """Every lane-group width, on grids fine enough that most queries widen."""
@@ -464,10 +464,11 @@ def test_isolated_point_forces_widening(nnc):
         run_parity(nnc, tr, G=40, lanes=lanes)
     p3 = np.concatenate([np.array(frames), 0.1 + 0.02 * g.random((6, 1, n))], axis=1)
     p3[:, 2, -1] = 0.97
-    run_parity(nnc, synth.Trajectory("custom", 3, n, -1.0, p3.astype(np.float32)), G=25, lanes=32)
+    for lanes in (8, 32):
+        run_parity(nnc, synth.Trajectory("custom", 3, n, -1.0, p3.astype(np.float32)), G=25, lanes=lanes)
 
 
-@pytest.mark.parametrize("lanes", [1, 4, 16, 64])
+@pytest.mark.parametrize("lanes", [1, 4, 8, 16, 64])
 @pytest.mark.parametrize("d", [2, 3])
 def test_cutoff_with_mixed_density_and_large_steps(nnc, d, lanes):
     """Dense clusters beside sparse outliers on a fine grid, with steps that vary
