@@ -61,7 +61,7 @@ def pick_grid(pos: torch.Tensor, d: int, target: float = 3.0) -> int:
     return best
 
 
-def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(1, 16, 32, 64),
+def tune_grid(frames, d: int, eps: float, steps: int = 6, grids=None, lanes=(1, 8, 16, 32, 64),
               stream=None) -> tuple[tuple[int, int], dict]:
     """Fastest (G, lanes per query) over a short run of step + repair on frames[0..steps];
     returns ((G, L), {"G/L": ms per step})."""
