@@ -298,9 +298,11 @@ class NNCert:
         self.frontier = Frontier()
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module globals may already be gone: then the process
+        # is ending and its device memory with it
+        if getattr(self, "h", None) and _lib is not None:
             _lib.nnc_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -463,9 +465,9 @@ class NNCBatch:
         self._keep = []
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.nnc_batch_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.close()
