@@ -63,6 +63,7 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=190)
+    ap.add_argument("--branches", type=int, default=5, help="streams (graph branches) the five headline scenes use")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--legs", default="repair,rebuild,allpairs,batched,sweep,scaling,audit,queue")
     ap.add_argument("--queue-exps", default="20,22,24", help="log2 N of the queue leg's scenes")
@@ -789,8 +790,24 @@ def main():
         lanes = {f: 0 for f in fams}
 
     # one stream per scene: the five scenes are independent, so their step chains
-    # may run side by side (the graph holds one branch per scene)
-    fstreams = {f: torch.cuda.Stream() for f in fams}
+    # may run side by side (the graph holds one branch per scene); with --branches k < 5
+    # the scenes share k streams, the longest first onto the least loaded (the tuning
+    # table's step times as weights)
+    nbr = max(1, min(args.branches, len(fams)))
+    if nbr >= len(fams):
+        fstreams = {f: torch.cuda.Stream() for f in fams}
+    else:
+        weight = {f: 1.0 for f in fams}
+        if os.path.exists(table_path):
+            tabw = json.load(open(table_path))["scenes"]
+            weight = {f: float(tabw[f]["ms_per_step"]) for f in fams}
+        pool = [torch.cuda.Stream() for _ in range(nbr)]
+        load = [0.0] * nbr
+        fstreams = {}
+        for f in sorted(fams, key=lambda f: -weight[f]):
+            k = min(range(nbr), key=lambda j: load[j])
+            fstreams[f] = pool[k]
+            load[k] += weight[f]
 
     def make_ctxs(per_scene_streams):
         ctxs = {}
