@@ -26,8 +26,8 @@
 //                  enclosed (Corollary 1); then the new certificate, expiry
 //                  key, failure flag and failure histogram.
 //   k_query_tiled  all-point query of large scenes: cell patches with their
-//   k_finish_all   neighbourhood staged in LDS, slot-ordered records, then the
-//                  point-order certificates.
+//   k_finish_all   neighbourhood staged in LDS, point-order records, then the
+//                  certificates.
 //   k_entropy*     normalised entropy (Definition 2) from a scan of the cell
 //                  histogram (one workgroup, or partial sums for large grids);
 //   k_cand_hist    the candidates' histogram for the same.
@@ -652,9 +652,11 @@ __global__ void __launch_bounds__(kB) k_query(QueryArgs a)
 // one thread per point.  A point whose second neighbour is not enclosed by the
 // first block is appended to the widening list and finished by the pointwise
 // query; a tile whose neighbourhood exceeds the LDS capacity runs the pointwise
-// search for its points.  Results go to a slot-ordered record per point
-// (coalesced), and k_finish_all moves them to point order with one random 16-byte
-// read per point instead of six scattered stores.  Tiles are dealt to XCDs in
+// search for its points.  Results go to a 16-byte record per point in point
+// order (one scattered 16-byte store, which costs about 32 bytes of HBM traffic),
+// and k_finish_all turns the records into certificates reading them in sequence
+// (a scattered 16-byte read would fetch a whole 128-byte line, and six scattered
+// certificate stores a line each).  Tiles are dealt to XCDs in
 // contiguous ranges (workgroups go to the eight XCDs round-robin), so
 // neighbouring tiles share an L2.
 constexpr int kTB = 512;       // threads per tile
@@ -822,11 +824,11 @@ __global__ void __launch_bounds__(kTB) k_query_tiled(QueryArgs a, int TX, int TY
                 wide[at] = i;
             else
                 atomicOr(&a.sc->err, kErrOverflow);
-            if (!a.cmask) rec[slot] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
+            if (!a.cmask) rec[i] = make_int4(-1, 0, 0, 0);  // finished by the widening pass
         } else if (a.cmask) {
             write_certificate(a, i, t, St, a.nn[i], -1);      // a repaired candidate, in place
         } else {
-            rec[slot] = make_int4(t.nn, __float_as_int(t.s1), __float_as_int(t.s2), 1);
+            rec[i] = make_int4(t.nn, __float_as_int(t.s1), __float_as_int(t.s2), 1);
         }
     }
 }
@@ -846,14 +848,13 @@ __global__ void __launch_bounds__(kB) k_cand_mask(const int *__restrict__ list, 
     }
 }
 
-// Point-order completion of the tiled pass: certificate of point i from the
-// record of its slot (skipped if the widening pass owns the point).
-__global__ void __launch_bounds__(kB) k_finish_all(QueryArgs a, const int *__restrict__ rank,
-                                                   const int4 *__restrict__ rec)
+// Point-order completion of the tiled pass: certificate of point i from its
+// record (skipped if the widening pass owns the point).
+__global__ void __launch_bounds__(kB) k_finish_all(QueryArgs a, const int4 *__restrict__ rec)
 {
     const int i = blockIdx.x * kB + threadIdx.x;
     if (i >= a.n) return;
-    const int4 r = rec[rank[i]];
+    const int4 r = rec[i];
     if (r.w == 0) return;
     Top2 t;
     t.nn = r.x;
@@ -1420,8 +1421,7 @@ int launch_query_all(nnc_ctx *c, int init)
     if (tiles > 0x7fffffffLL) return NNC_E_INVAL;
     const QueryArgs a = query_args(c, nullptr, nullptr, 1, init);
     launch_tiled(c, a, TX, TY, nsx, nsy, tiles);
-    hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, a, c->grid.rank,
-                       (const int4 *)c->rec);
+    hipLaunchKernelGGL(k_finish_all, dim3(blocks_for(c->n, kB)), dim3(kB), 0, c->stream, a, (const int4 *)c->rec);
     launch_pointwise(c, query_args(c, c->wide, &c->sc->nwide, 0, init));
     return check();
 }
