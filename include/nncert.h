@@ -341,7 +341,7 @@ typedef struct {
     int32_t lanes;           /* lanes per query: 1, 4, 8, 16, 32 or 64 (4 in the plane only;
                                 cube scenes then use 16); 0 = 4 in the plane, 8 in the cube */
     double guard;            /* as in nnc_config */
-    double refresh;          /* as in nnc_config */
+    double refresh;          /* as in nnc_config, but <= 0 = 0.125 */
     void *stream;            /* hipStream_t */
     uint32_t flags;          /* NNC_BATCH_FEATURES | NNC_BATCH_EAGER | NNC_BATCH_TIMING | NNC_BATCH_BUDGET */
 } nnc_batch_config;
