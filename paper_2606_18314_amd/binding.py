@@ -264,7 +264,9 @@ class NNCert:
     def __init__(self, n: int, d: int, grid_g: int = 0, guard: float = -1.0, refresh: float = 0.0,
                  copy_positions: bool = False, sync: bool = False, stream: int | None = None, lanes: int = 0,
                  all_query: str = "auto", box=None, budget: bool = False, queue: bool = False):
-        """all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
+        """lanes: lanes per query (1, 4 (plane only), 8, 16, 32 or 64; 0 = 32 in the cube,
+        16 in the plane).
+        all_query: "auto", "tiled" or "pointwise" -- how initialisation and rebuild
         query every point (under "auto" tiled by cells from N = 65536 on at
         initialisation, from 2^17 (d = 2) or 2^19 (d = 3) on at a rebuild).
         box: (lo, hi), per-axis bounds of the grid's domain (default the unit box).
@@ -440,7 +442,9 @@ class NNCBatch:
     def __init__(self, ns, ds, grids=None, lanes: int = 0, guard: float = -1.0, refresh: float = 0.0,
                  stream: int | None = None, features: bool = False, eager: bool = False, timing: bool = False,
                  budget: bool = False):
-        """eager: launch each step's kernels directly instead of through the library's graph;
+        """lanes: lanes per query (1, 4, 8, 16, 32 or 64; 4 serves plane scenes only, cube
+        scenes then use 16; 0 = 4 in the plane and 8 in the cube);
+        eager: launch each step's kernels directly instead of through the library's graph;
         timing: per-scene wall-clock cost accounting (stats' t_filter_us, t_grid_us, t_query_us);
         budget: the per-point motion budget in every scene (NNC_BATCH_BUDGET)."""
         import numpy as np
