@@ -1141,13 +1141,15 @@ inline int check() { return hipGetLastError() == hipSuccess ? NNC_OK : NNC_E_HIP
 template <int D, int L>
 void launch_query_t(const QueryArgs &a, long long maxq, hipStream_t s, bool unit)
 {
-    // at most 2048 workgroups (eight per CU) striding over the queries: enough
-    // waves to fill the chip, and few idle ones when the count on the device is
-    // far below the bound maxq
+    // at most 8192 workgroups (32 per CU, more than can be resident) striding over
+    // the queries: the waves queue behind the resident ones, so a wave held up by
+    // slow queries delays little else (against 2048: the plane repair query at
+    // 2^24 509 -> 428 us), and few are idle when the count on the device is far
+    // below the bound maxq
     constexpr int GPB = kB / L;
     long long blocks = (maxq + GPB - 1) / GPB;
     if (blocks < 1) blocks = 1;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 8192) blocks = 8192;
     if (unit)
         hipLaunchKernelGGL((k_query<D, L, true>), dim3((unsigned)blocks), dim3(kB), 0, s, a);
     else
