@@ -184,25 +184,47 @@ __global__ void __launch_bounds__(kB) k_ingest(const float *__restrict__ pold, c
     float s = 0.0f;
     int dC = 0;
     const size_t n1 = (size_t)n, n2 = 2 * (size_t)n;
-    for (int i = blockIdx.x * kB + (int)threadIdx.x; i < n; i += gridDim.x * kB) {
-        const float x0 = pold[i], y0 = pold[n1 + i], z0 = D == 3 ? pold[n2 + i] : 0.f;
-        const float x1 = pnew[i], y1 = pnew[n1 + i], z1 = D == 3 ? pnew[n2 + i] : 0.f;
-        slots[rank[i]] = make_float4(x1, y1, z1, __int_as_float(i));
-        if (all_finite<D>(x1, y1, z1) && all_finite<D>(x0, y0, z0)) {
-            s = fmaxf(s, sqdist<D>(x0, y0, z0, x1, y1, z1));
-            const int c = cell_id<D>(x1, y1, z1, G, box);
-            const int old = cell[i];
-            if (c != old) {
-                cell[i] = c;
-                dC -= atomicSub(&counts[old], 1) == 1;
-                dC += atomicAdd(&counts[c], 1) == 0;
+    // U points per thread per pass, their loads issued together (large scenes run
+    // many passes; one point per pass waits for each point's loads in turn)
+    constexpr int U = 4;
+    const int stride = gridDim.x * kB;
+    for (int i0 = blockIdx.x * kB + (int)threadIdx.x; i0 < n; i0 += U * stride) {
+        float x0[U], y0[U], z0[U], x1[U], y1[U], z1[U];
+        int rk[U], oc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * stride;
+            const bool in = i < n;
+            x0[u] = in ? pold[i] : 0.f;
+            y0[u] = in ? pold[n1 + i] : 0.f;
+            z0[u] = in && D == 3 ? pold[n2 + i] : 0.f;
+            x1[u] = in ? pnew[i] : 0.f;
+            y1[u] = in ? pnew[n1 + i] : 0.f;
+            z1[u] = in && D == 3 ? pnew[n2 + i] : 0.f;
+            rk[u] = in ? rank[i] : 0;
+            oc[u] = in ? cell[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * stride;
+            if (i >= n) continue;
+            slots[rk[u]] = make_float4(x1[u], y1[u], z1[u], __int_as_float(i));
+            if (all_finite<D>(x1[u], y1[u], z1[u]) && all_finite<D>(x0[u], y0[u], z0[u])) {
+                s = fmaxf(s, sqdist<D>(x0[u], y0[u], z0[u], x1[u], y1[u], z1[u]));
+                const int c = cell_id<D>(x1[u], y1[u], z1[u], G, box);
+                const int old = oc[u];
+                if (c != old) {
+                    cell[i] = c;
+                    dC -= atomicSub(&counts[old], 1) == 1;
+                    dC += atomicAdd(&counts[c], 1) == 0;
+                }
+                if (last_move && (x1[u] != x0[u] || y1[u] != y0[u] || z1[u] != z0[u])) {
+                    last_move[old] = t;  // every writer stores the same value
+                    last_move[c] = t;
+                }
+            } else {
+                atomicOr(&sc->err, kErrNonFinite);
             }
-            if (last_move && (x1 != x0 || y1 != y0 || z1 != z0)) {
-                last_move[old] = t;  // every writer stores the same value
-                last_move[c] = t;
-            }
-        } else {
-            atomicOr(&sc->err, kErrNonFinite);
         }
     }
     publish_ingest_spread<kB>(sc, parity, s, dC);
