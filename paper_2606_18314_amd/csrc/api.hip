@@ -61,7 +61,8 @@ size_t carve(nnc_ctx *c, char *base)
     c->state_bytes = k.off;
     c->sync = k.take<nnc::DevSync>(1);
     c->grid.cursor = k.take<int>(nc);
-    // one descriptor per look-back tile (512 or 2048 items of the filter, 2048 of the cell scan)
+    // one descriptor per look-back tile (512 or 2048 items of the filter, 4096 of the cell
+    // scan; sized for 2048 here, which covers both)
     const size_t tf = (n + 511) / 512, tc = (nc + 2047) / 2048;
     const size_t tiles = (tf > tc ? tf : tc) + 1;
     c->nstatus = (int)tiles;

@@ -44,8 +44,8 @@ namespace {
 using namespace kc;
 
 constexpr int kB = 256;            // threads per point-parallel workgroup
-constexpr int kRows = 8;           // items per thread in the cell-scan tiles
-constexpr int kTile = kB * kRows;  // items per cell-scan look-back tile
+constexpr int kScanV = 16;              // consecutive cells per thread in the cell scan
+constexpr int kScanTile = kB * kScanV;  // cells per cell-scan look-back tile
 // filter look-back tiles: 512 items up to kFiltSmallTilesN points, 1024 above
 // (measured: shorter tiles win at small N, longer chains lose as N grows; from
 // kReduceScanMinN on the filter is reduce-then-scan)
@@ -533,6 +533,9 @@ __global__ void __launch_bounds__(kB) k_filter_write(int n, const unsigned long 
     }
 }
 
+// Each thread scans kScanV consecutive cells (16-byte loads and stores where the
+// run lies inside the table; the table is 256-byte aligned), one workgroup scan
+// per tile of kScanTile cells, then the look-back across tiles.
 __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ counts, int ncell,
                                                    int *__restrict__ cell_start, int *__restrict__ cursor,
                                                    DevScalars *sc, DevSync *sy, int parity,
@@ -544,18 +547,32 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
     __shared__ unsigned s_base;
     take_ticket(sy, &s_tile, &s_epoch);
     const int tile = s_tile;
-    const long long base = (long long)tile * kTile;
-    int pref[kRows];
-    int run = 0;
+    const long long c0 = (long long)tile * kScanTile + (long long)threadIdx.x * kScanV;
+    const bool whole = c0 + kScanV <= ncell;
+    int v[kScanV];
+    if (whole) {
+        const int4 *p4 = reinterpret_cast<const int4 *>(counts + c0);
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const long long c = base + (long long)k * kB + threadIdx.x;
-        const int v = c < ncell ? counts[c] : 0;
-        int tot;
-        const int ex = block_excl_scan<kB>(v, s_w, tot);
-        pref[k] = run + ex;
-        run += tot;
+        for (int q = 0; q < kScanV / 4; ++q) {
+            const int4 w = p4[q];
+            v[4 * q] = w.x;
+            v[4 * q + 1] = w.y;
+            v[4 * q + 2] = w.z;
+            v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanV; ++k) v[k] = c0 + k < ncell ? counts[c0 + k] : 0;
     }
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanV; ++k) {
+        const int x = v[k];
+        v[k] = sum;  // exclusive prefix within the thread's run
+        sum += x;
+    }
+    int run;
+    const int ex = block_excl_scan<kB>(sum, s_w, run);
     if (threadIdx.x < 64) {
         const unsigned excl = lookback(status, tile, (unsigned)run, s_epoch, &sc->err);
         if (threadIdx.x == 0) {
@@ -571,14 +588,23 @@ __global__ void __launch_bounds__(kB) k_scan_cells(const int *__restrict__ count
         }
     }
     __syncthreads();
-    const int b = (int)s_base;
+    const int b = (int)s_base + ex;
+    if (whole) {
+        int4 *cs4 = reinterpret_cast<int4 *>(cell_start + c0);
+        int4 *cu4 = reinterpret_cast<int4 *>(cursor + c0);
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-        const long long c = base + (long long)k * kB + threadIdx.x;
-        if (c < ncell) {
-            cell_start[c] = b + pref[k];
-            cursor[c] = b + pref[k];
+        for (int q = 0; q < kScanV / 4; ++q) {
+            const int4 w = make_int4(b + v[4 * q], b + v[4 * q + 1], b + v[4 * q + 2], b + v[4 * q + 3]);
+            cs4[q] = w;
+            cu4[q] = w;
         }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanV; ++k)
+            if (c0 + k < ncell) {
+                cell_start[c0 + k] = b + v[k];
+                cursor[c0 + k] = b + v[k];
+            }
     }
 }
 
@@ -1256,7 +1282,7 @@ int launch_filter(nnc_ctx *c, float eps_declared)
 int launch_grid_build(nnc_ctx *c, const float *pos, bool from_slots)
 {
     const int parity = (int)(c->t & 1);
-    const int tiles = blocks_for(c->ncell, kTile);
+    const int tiles = blocks_for(c->ncell, kScanTile);
     if (tiles > c->nstatus) return NNC_E_INVAL;
     hipLaunchKernelGGL(k_scan_cells, dim3(tiles), dim3(kB), 0, c->stream, c->grid.counts, c->ncell,
                        c->grid.cell_start, c->grid.cursor, c->sc, c->sync, parity, c->status);
