@@ -740,6 +740,10 @@ struct nnc_batch {
     size_t arena_bytes;
     int inited, features_on, eager, budget;
     int has_d[2];           // scenes of dimension 2, 3 present
+    // with scenes of both dimensions, the plane's query runs on a second stream beside
+    // the cube's (forked from and joined back into the batch's stream, also in a graph)
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
     double tick_us;         // microseconds per wall-clock tick (NNC_BATCH_TIMING)
     // the step as a graph: instantiated on the first call and replayed while
     // (positions, policy, tau) repeat; another key re-captures and updates it
@@ -762,31 +766,43 @@ int default_grid_b(int64_t n, int d)
 }
 
 template <int D>
-void launch_query_d(const nnc_batch *b, const nnc::BatchArgs &a, int init)
+void launch_query_d(const nnc_batch *b, const nnc::BatchArgs &a, int init, hipStream_t st)
 {
     // more waves than can be resident, each with a shorter chunk of the query list:
     // the chunks with slow queries hold up less (2048 -> 6144 workgroups: 0.833 ->
     // 0.764 ms per step on the 512-scene workload; waves without a chunk return)
     const int blocks = 6144;
     switch (D == 2 ? b->lanes2 : b->lanes3) {
-    case 1: hipLaunchKernelGGL((nnc::k_b_query<D, 1>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
-    case 64: hipLaunchKernelGGL((nnc::k_b_query<D, 64>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
-    case 32: hipLaunchKernelGGL((nnc::k_b_query<D, 32>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 1: hipLaunchKernelGGL((nnc::k_b_query<D, 1>), dim3(blocks), dim3(nnc::kB), 0, st, a, init); break;
+    case 64: hipLaunchKernelGGL((nnc::k_b_query<D, 64>), dim3(blocks), dim3(nnc::kB), 0, st, a, init); break;
+    case 32: hipLaunchKernelGGL((nnc::k_b_query<D, 32>), dim3(blocks), dim3(nnc::kB), 0, st, a, init); break;
     case 4:
         if constexpr (D == 2)
-            hipLaunchKernelGGL((nnc::k_b_query<2, 4>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init);
+            hipLaunchKernelGGL((nnc::k_b_query<2, 4>), dim3(blocks), dim3(nnc::kB), 0, st, a, init);
         break;
-    case 8: hipLaunchKernelGGL((nnc::k_b_query<D, 8>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
-    default: hipLaunchKernelGGL((nnc::k_b_query<D, 16>), dim3(blocks), dim3(nnc::kB), 0, b->stream, a, init); break;
+    case 8: hipLaunchKernelGGL((nnc::k_b_query<D, 8>), dim3(blocks), dim3(nnc::kB), 0, st, a, init); break;
+    default: hipLaunchKernelGGL((nnc::k_b_query<D, 16>), dim3(blocks), dim3(nnc::kB), 0, st, a, init); break;
     }
 }
 
 // One launch per dimension present (each kernel holds one search, so the plane's
-// launch is not limited by the cube's register use).
+// launch is not limited by the cube's register use); with both, the two run side by
+// side, each filling the other's tail.
 int launch_query_b(const nnc_batch *b, const nnc::BatchArgs &a, int init)
 {
-    if (b->has_d[0]) launch_query_d<2>(b, a, init);
-    if (b->has_d[1]) launch_query_d<3>(b, a, init);
+    if (b->has_d[0] && b->has_d[1] && b->side) {
+        if (hipEventRecord(b->ev_fork, b->stream) != hipSuccess ||
+            hipStreamWaitEvent(b->side, b->ev_fork, 0) != hipSuccess)
+            return NNC_E_HIP;
+        launch_query_d<2>(b, a, init, b->side);
+        launch_query_d<3>(b, a, init, b->stream);
+        if (hipEventRecord(b->ev_join, b->side) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess)
+            return NNC_E_HIP;
+        return nnc::check();
+    }
+    if (b->has_d[0]) launch_query_d<2>(b, a, init, b->stream);
+    if (b->has_d[1]) launch_query_d<3>(b, a, init, b->stream);
     return nnc::check();
 }
 
@@ -991,7 +1007,15 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     // the learned policy's band: the network decides at every candidate fraction
     if (rc == NNC_OK) rc = nnc::launch_fill(a.tdev + 3, __builtin_bit_cast(int, 2.0f), 1, b->stream);
     if (rc == NNC_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = NNC_E_HIP;
+    if (rc == NNC_OK && b->has_d[0] && b->has_d[1] &&
+        (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess))
+        rc = NNC_E_HIP;
     if (rc != NNC_OK) {
+        if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+        if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+        if (b->side) (void)hipStreamDestroy(b->side);
         (void)hipFree(b->arena);
         delete b;
         return rc;
@@ -1004,7 +1028,11 @@ void nnc_batch_destroy(nnc_batch *b)
 {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     (void)hipFree(b->arena);
     delete b;
 }
