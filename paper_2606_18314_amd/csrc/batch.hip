@@ -88,13 +88,24 @@ namespace {
 // clock of parity (t - 1) & 1 and writes that of parity t & 1.
 __device__ __forceinline__ int step_number(const BatchArgs &a) { return a.init ? 0 : a.tdev[0] + 1; }
 
+// Workgroup b of nb runs on XCD b mod 8 (workgroups are dealt to the eight XCDs in
+// turn); it takes item b / 8 of that XCD's contiguous share of the nb items (tiles,
+// query chunks), so neighbouring items, mostly of one scene, share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int x = b & 7, k = b >> 3;
+    const int full = nb >> 3, rem = nb & 7;
+    return x * full + min(x, rem) + k;
+}
+
 __global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
 {
-    const int s = a.tile_scene[blockIdx.x];
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int s = a.tile_scene[tb];
     const SceneDesc sd = a.desc[s];
     int dC = 0;
     for (int u = 0; u < kIU; ++u) {
-        const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x + u * kB;
+        const int i = a.tile_start[tb] + (int)threadIdx.x + u * kB;
         if (i >= sd.n) break;
         const float *p = a.pos_cur + sd.coff;
         const size_t n1 = (size_t)sd.n;
@@ -115,9 +126,10 @@ __global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
 // loads issued together so that each wave waits for few memory round trips.
 __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
 {
-    const int s = a.tile_scene[blockIdx.x];
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int s = a.tile_scene[tb];
     const SceneDesc sd = a.desc[s];
-    const int i0 = a.tile_start[blockIdx.x] + (int)threadIdx.x;
+    const int i0 = a.tile_start[tb] + (int)threadIdx.x;
     const int parity = step_number(a) & 1;
     const float *pn = a.pos_cur + sd.coff;
     const size_t n1 = (size_t)sd.n, n2 = 2 * (size_t)sd.n;
@@ -182,7 +194,8 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
 // computed as the filter will compute it, read-only.  Tiles as in the ingest.
 __global__ void __launch_bounds__(kB) k_b_budget(BatchArgs a)
 {
-    const int s = a.tile_scene[blockIdx.x];
+    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int s = a.tile_scene[tb];
     const SceneDesc sd = a.desc[s];
     const int parity = step_number(a) & 1;
     const DevScalars *sc = &a.sc[s];
@@ -195,7 +208,7 @@ __global__ void __launch_bounds__(kB) k_b_budget(BatchArgs a)
     const float *p = a.pos_cur + sd.coff;
     const double w = 1.0 / (double)G;
     for (int u = 0; u < kIU; ++u) {
-        const int i = a.tile_start[blockIdx.x] + (int)threadIdx.x + u * kB;
+        const int i = a.tile_start[tb] + (int)threadIdx.x + u * kB;
         if (i >= n) break;
         double *ei = a.e + sd.poff + i;
         if (!(St >= *ei)) continue;
@@ -654,7 +667,8 @@ __global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(D == 3 
     const int lane = threadIdx.x & (L - 1);
     const int grp = (int)(threadIdx.x & 63) / L;
     const int nw = (int)gridDim.x * (kB / 64);
-    const int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (kB / 64) + (int)(threadIdx.x >> 6));
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int w = __builtin_amdgcn_readfirstlane(blk * (kB / 64) + (int)(threadIdx.x >> 6));
     const int per = (total + nw - 1) / nw;
     int g = w * per;
     const int q1 = min(g + per, total);
