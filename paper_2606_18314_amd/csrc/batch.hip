@@ -16,7 +16,9 @@
 //   k_b_grid     one workgroup per scene that needs a fresh grid (rebuild, or
 //                repair after the motion budget of the loose grid is spent):
 //                cell-start scan and counting-sort scatter; one extra workgroup
-//                turns the per-scene query counts into offsets per dimension;
+//                turns the per-scene query counts into offsets per dimension
+//                (with scenes of both dimensions, one launch per dimension, each
+//                followed by that dimension's queries on a stream of its own);
 //   k_b_query    one persistent grid-stride launch per dimension over the
 //                queries of all scenes of that dimension (candidates of
 //                repaired scenes, every point of rebuilt ones), L lanes per
@@ -76,6 +78,7 @@ struct BatchArgs {
     int *last_move;  // per cell: last step a moving point left or entered it (per-point budget), or null
     uint8_t *fail;
     const int *tile_scene, *tile_start;
+    const int *dscene;     // scene indices ordered by dimension: the plane's, then the cube's
     int *strategy, *need_grid, *qcount, *qpre;
     float *features;
     const float *params;
@@ -502,13 +505,15 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
 }
 
 // Per-scene grid builds (workgroups 0..scenes-1) and the query offsets (last workgroup).
-__global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
+__global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a, int first, int count, int dmask)
 {
     __shared__ int s_w[kFB / 64];
-    if ((int)blockIdx.x == a.scenes) {
-        // query offsets per dimension: qpre[(d - 2) * (scenes + 1) + s] counts the
-        // queries of the scenes of dimension d before scene s
+    if ((int)blockIdx.x == count) {
+        // query offsets per dimension (dimension d when bit d - 2 of dmask is set):
+        // qpre[(d - 2) * (scenes + 1) + s] counts the queries of the scenes of
+        // dimension d before scene s
         for (int d = 2; d <= 3; ++d) {
+            if (!((dmask >> (d - 2)) & 1)) continue;
             int *pre = a.qpre + (d - 2) * (a.scenes + 1);
             int run = 0;
             for (int base = 0; base < a.scenes; base += kFB) {
@@ -523,7 +528,7 @@ __global__ void __launch_bounds__(kFB) k_b_grid(BatchArgs a)
         }
         return;
     }
-    const int s = blockIdx.x;
+    const int s = a.dscene[first + (int)blockIdx.x];
     if (!a.need_grid[s]) {
         if (a.cost && threadIdx.x == 0) a.cost[3 * s + 1] = 0;
         return;
@@ -745,7 +750,7 @@ struct nnc_batch {
     double guard, K;
     hipStream_t stream;
     std::vector<nnc::SceneDesc> desc;
-    std::vector<int> tile_scene, tile_start;
+    std::vector<int> tile_scene, tile_start, dscene;
     std::vector<long long> point_off, coord_off;
     long long P, Q, NC, NS;
     int ntiles;
@@ -754,6 +759,7 @@ struct nnc_batch {
     size_t arena_bytes;
     int inited, features_on, eager, budget;
     int has_d[2];           // scenes of dimension 2, 3 present
+    int S2;                 // scenes of dimension 2 (the first S2 entries of dscene)
     // with scenes of both dimensions, the plane's query runs on a second stream beside
     // the cube's (forked from and joined back into the batch's stream, also in a graph)
     hipStream_t side;
@@ -818,6 +824,30 @@ int launch_query_b(const nnc_batch *b, const nnc::BatchArgs &a, int init)
     if (b->has_d[0]) launch_query_d<2>(b, a, init, b->stream);
     if (b->has_d[1]) launch_query_d<3>(b, a, init, b->stream);
     return nnc::check();
+}
+
+// A step's grid builds and queries.  With scenes of both dimensions each dimension's
+// builds and query launch form a chain of their own (the plane's on the second
+// stream), so one dimension's queries run while the other's grids are still built.
+int launch_grid_query(const nnc_batch *b, const nnc::BatchArgs &a)
+{
+    const int S = b->S, S2 = b->S2;
+    if (b->has_d[0] && b->has_d[1] && b->side) {
+        if (hipEventRecord(b->ev_fork, b->stream) != hipSuccess ||
+            hipStreamWaitEvent(b->side, b->ev_fork, 0) != hipSuccess)
+            return NNC_E_HIP;
+        hipLaunchKernelGGL(nnc::k_b_grid, dim3(S2 + 1), dim3(nnc::kFB), 0, b->side, a, 0, S2, 1);
+        launch_query_d<2>(b, a, 0, b->side);
+        hipLaunchKernelGGL(nnc::k_b_grid, dim3(S - S2 + 1), dim3(nnc::kFB), 0, b->stream, a, S2, S - S2, 2);
+        launch_query_d<3>(b, a, 0, b->stream);
+        if (hipEventRecord(b->ev_join, b->side) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess)
+            return NNC_E_HIP;
+        return nnc::check();
+    }
+    hipLaunchKernelGGL(nnc::k_b_grid, dim3(S + 1), dim3(nnc::kFB), 0, b->stream, a, 0, S, 3);
+    const int rc = nnc::check();
+    return rc == NNC_OK ? launch_query_b(b, a, 0) : rc;
 }
 
 }  // namespace
@@ -899,6 +929,11 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     b->NC = NC;
     b->NS = NS;
     b->ntiles = (int)b->tile_scene.size();
+    for (int s = 0; s < b->S; ++s)
+        if (b->desc[s].d == 2) b->dscene.push_back(s);
+    b->S2 = (int)b->dscene.size();
+    for (int s = 0; s < b->S; ++s)
+        if (b->desc[s].d == 3) b->dscene.push_back(s);
     const size_t S = (size_t)b->S, Pp = (size_t)(P > 0 ? P : 1);
     const size_t T = (size_t)(b->ntiles > 0 ? b->ntiles : 1);
     size_t bytes = 0;
@@ -908,7 +943,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     bytes += 2 * al(Pp * 4) + al(Pp * 8) + al(Pp);             // d1, d2, e, fail
     bytes += 4 * al(Pp * 4);                                   // stamp, frontier, touched x2
     bytes += 4 * al((size_t)NC * 4) + al((size_t)NS * 4);      // counts, cursor, hist x2, cell_start
-    bytes += 2 * al(T * 4) + 3 * al(S * 4) + al(2 * (S + 1) * 4);  // tiles, strategy/need/qcount, qpre
+    bytes += 2 * al(T * 4) + 4 * al(S * 4) + al(2 * (S + 1) * 4);  // tiles, strategy/need/qcount/dscene, qpre
     bytes += al(S * NNC_FEATURES * 4) + al(NNC_SELECTOR_PARAMS * 4) + al(4 * 4) + al(S * 3 * 8);
     if (b->budget) bytes += al(Pp * 8) + al((size_t)NC * 4);   // certificate clocks, cell stamps
     bytes += al(S * sizeof(nnc::kc::QueryArgs));               // per-scene query views
@@ -955,6 +990,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     a.need_grid = (int *)take(S * 4);
     a.qcount = (int *)take(S * 4);
     a.qpre = (int *)take(2 * (S + 1) * 4);
+    a.dscene = (const int *)take(S * 4);
     a.features = (float *)take(S * NNC_FEATURES * 4);
     a.params = (const float *)take(NNC_SELECTOR_PARAMS * 4);
     a.tdev = (int *)take(4 * 4);
@@ -1012,6 +1048,7 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
                        b->stream) != hipSuccess ||
         hipMemcpyAsync((void *)a.desc, b->desc.data(), S * sizeof(nnc::SceneDesc), hipMemcpyHostToDevice,
                        b->stream) != hipSuccess ||
+        hipMemcpyAsync((void *)a.dscene, b->dscene.data(), S * 4, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         (b->ntiles > 0 &&
          (hipMemcpyAsync((void *)a.tile_scene, b->tile_scene.data(), b->ntiles * 4, hipMemcpyHostToDevice,
                          b->stream) != hipSuccess ||
@@ -1078,7 +1115,7 @@ int nnc_batch_init(nnc_batch *b, const float *pos)
     a.init = 1;
     if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_cells_init, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_init_flags, dim3((b->S + 255) / 256), dim3(256), 0, b->stream, a);
-    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
+    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a, 0, b->S, 3);
     int rc = nnc::check();
     if (rc == NNC_OK) rc = launch_query_b(b, a, 1);
     b->inited = rc == NNC_OK;
@@ -1100,9 +1137,7 @@ int launch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
     if (b->budget && b->ntiles > 0)
         hipLaunchKernelGGL(nnc::k_b_budget, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
-    hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a);
-    int rc = nnc::check();
-    if (rc == NNC_OK) rc = launch_query_b(b, a, 0);
+    int rc = launch_grid_query(b, a);
     if (rc == NNC_OK) {
         hipLaunchKernelGGL(nnc::k_b_entropy, dim3(b->S), dim3(nnc::kB), 0, b->stream, a);
         rc = nnc::check();
