@@ -101,9 +101,9 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x * full + min(x, rem) + k;
 }
 
-__global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
+__global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a, int first)
 {
-    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tb = first + xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int s = a.tile_scene[tb];
     const SceneDesc sd = a.desc[s];
     int dC = 0;
@@ -127,9 +127,9 @@ __global__ void __launch_bounds__(kB) k_b_cells_init(BatchArgs a)
 
 // kIU points per thread (thread t of the tile: points t, t + kB, ...), their
 // loads issued together so that each wave waits for few memory round trips.
-__global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
+__global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a, int first)
 {
-    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tb = first + xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int s = a.tile_scene[tb];
     const SceneDesc sd = a.desc[s];
     const int i0 = a.tile_start[tb] + (int)threadIdx.x;
@@ -195,9 +195,9 @@ __global__ void __launch_bounds__(kB) k_b_ingest(BatchArgs a)
 // current distance r is below d2 (1 - g) - 2 D (1 + g) -- the key moves to
 // S_t + gap K.  Otherwise the point stays expired and the filter lists it.  S_t is
 // computed as the filter will compute it, read-only.  Tiles as in the ingest.
-__global__ void __launch_bounds__(kB) k_b_budget(BatchArgs a)
+__global__ void __launch_bounds__(kB) k_b_budget(BatchArgs a, int first)
 {
-    const int tb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tb = first + xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int s = a.tile_scene[tb];
     const SceneDesc sd = a.desc[s];
     const int parity = step_number(a) & 1;
@@ -310,7 +310,7 @@ __device__ int mlp_decide(const float *__restrict__ p, const float *x, float *s_
     return dec;
 }
 
-__global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
+__global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a, int first)
 {
     constexpr int NW = kFB / 64;
     constexpr int NC = kFRows * NW;
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kFB) k_b_filter(BatchArgs a)
     __shared__ float s_h[kH];
     __shared__ float s_h2[kH];
     __shared__ int s_dec;
-    const int s = blockIdx.x;
+    const int s = a.dscene[first + (int)blockIdx.x];
     const long long t_start = a.cost ? wall_clock64() : 0;
     const SceneDesc sd = a.desc[s];
     DevScalars *sc = &a.sc[s];
@@ -760,6 +760,7 @@ struct nnc_batch {
     int inited, features_on, eager, budget;
     int has_d[2];           // scenes of dimension 2, 3 present
     int S2;                 // scenes of dimension 2 (the first S2 entries of dscene)
+    int T2;                 // ingest tiles of those scenes (the first T2 tiles)
     // with scenes of both dimensions, the plane's query runs on a second stream beside
     // the cube's (forked from and joined back into the batch's stream, also in a graph)
     hipStream_t side;
@@ -826,26 +827,41 @@ int launch_query_b(const nnc_batch *b, const nnc::BatchArgs &a, int init)
     return nnc::check();
 }
 
-// A step's grid builds and queries.  With scenes of both dimensions each dimension's
-// builds and query launch form a chain of their own (the plane's on the second
-// stream), so one dimension's queries run while the other's grids are still built.
-int launch_grid_query(const nnc_batch *b, const nnc::BatchArgs &a)
+// One dimension's part of a step on stream st: ingest (and the per-point budget) of
+// tiles [t0, t0 + nt), filter and grid builds of the scenes dscene[s0, s0 + ns), and
+// the query launch of dimension D (none when D is 0: the caller runs the queries).
+template <int D>
+void launch_chain(const nnc_batch *b, const nnc::BatchArgs &a, hipStream_t st, int t0, int nt, int s0, int ns,
+                  int dmask)
 {
-    const int S = b->S, S2 = b->S2;
+    if (nt > 0) {
+        hipLaunchKernelGGL(nnc::k_b_ingest, dim3(nt), dim3(nnc::kB), 0, st, a, t0);
+        if (b->budget) hipLaunchKernelGGL(nnc::k_b_budget, dim3(nt), dim3(nnc::kB), 0, st, a, t0);
+    }
+    hipLaunchKernelGGL(nnc::k_b_filter, dim3(ns), dim3(nnc::kFB), 0, st, a, s0);
+    hipLaunchKernelGGL(nnc::k_b_grid, dim3(ns + 1), dim3(nnc::kFB), 0, st, a, s0, ns, dmask);
+    if constexpr (D != 0) launch_query_d<D>(b, a, 0, st);
+}
+
+// A step up to its queries.  With scenes of both dimensions each dimension's kernels
+// form a chain of their own (the plane's on the second stream, forked from the
+// batch's stream and joined back), so the two overlap: one dimension's queries run
+// while the other's grids are still built.
+int launch_chains(const nnc_batch *b, const nnc::BatchArgs &a)
+{
+    const int S = b->S, S2 = b->S2, T = b->ntiles, T2 = b->T2;
     if (b->has_d[0] && b->has_d[1] && b->side) {
         if (hipEventRecord(b->ev_fork, b->stream) != hipSuccess ||
             hipStreamWaitEvent(b->side, b->ev_fork, 0) != hipSuccess)
             return NNC_E_HIP;
-        hipLaunchKernelGGL(nnc::k_b_grid, dim3(S2 + 1), dim3(nnc::kFB), 0, b->side, a, 0, S2, 1);
-        launch_query_d<2>(b, a, 0, b->side);
-        hipLaunchKernelGGL(nnc::k_b_grid, dim3(S - S2 + 1), dim3(nnc::kFB), 0, b->stream, a, S2, S - S2, 2);
-        launch_query_d<3>(b, a, 0, b->stream);
+        launch_chain<2>(b, a, b->side, 0, T2, 0, S2, 1);
+        launch_chain<3>(b, a, b->stream, T2, T - T2, S2, S - S2, 2);
         if (hipEventRecord(b->ev_join, b->side) != hipSuccess ||
             hipStreamWaitEvent(b->stream, b->ev_join, 0) != hipSuccess)
             return NNC_E_HIP;
         return nnc::check();
     }
-    hipLaunchKernelGGL(nnc::k_b_grid, dim3(S + 1), dim3(nnc::kFB), 0, b->stream, a, 0, S, 3);
+    launch_chain<0>(b, a, b->stream, 0, T, 0, S, 3);
     const int rc = nnc::check();
     return rc == NNC_OK ? launch_query_b(b, a, 0) : rc;
 }
@@ -928,12 +944,24 @@ int nnc_batch_create(nnc_batch **out, const nnc_batch_config *cfg)
     b->Q = Q;
     b->NC = NC;
     b->NS = NS;
-    b->ntiles = (int)b->tile_scene.size();
     for (int s = 0; s < b->S; ++s)
         if (b->desc[s].d == 2) b->dscene.push_back(s);
     b->S2 = (int)b->dscene.size();
     for (int s = 0; s < b->S; ++s)
         if (b->desc[s].d == 3) b->dscene.push_back(s);
+    // the ingest tiles in the same order: the plane's scenes' tiles first
+    b->tile_scene.clear();
+    b->tile_start.clear();
+    for (int k = 0; k < b->S; ++k) {
+        const int s = b->dscene[k];
+        if (k == b->S2) b->T2 = (int)b->tile_scene.size();
+        for (int64_t i0 = 0; i0 < cfg->n[s]; i0 += nnc::kTile) {
+            b->tile_scene.push_back(s);
+            b->tile_start.push_back((int)i0);
+        }
+    }
+    if (b->S2 == b->S) b->T2 = (int)b->tile_scene.size();
+    b->ntiles = (int)b->tile_scene.size();
     const size_t S = (size_t)b->S, Pp = (size_t)(P > 0 ? P : 1);
     const size_t T = (size_t)(b->ntiles > 0 ? b->ntiles : 1);
     size_t bytes = 0;
@@ -1113,7 +1141,7 @@ int nnc_batch_init(nnc_batch *b, const float *pos)
         return NNC_E_HIP;
     a.pos_cur = pos;
     a.init = 1;
-    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_cells_init, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
+    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_cells_init, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a, 0);
     hipLaunchKernelGGL(nnc::k_b_init_flags, dim3((b->S + 255) / 256), dim3(256), 0, b->stream, a);
     hipLaunchKernelGGL(nnc::k_b_grid, dim3(b->S + 1), dim3(nnc::kFB), 0, b->stream, a, 0, b->S, 3);
     int rc = nnc::check();
@@ -1133,11 +1161,7 @@ int launch_step(nnc_batch *b, const float *pos_new, int policy, float tau)
     a.policy = policy;
     a.tau = tau;
     a.features_on = b->features_on;
-    if (b->ntiles > 0) hipLaunchKernelGGL(nnc::k_b_ingest, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
-    if (b->budget && b->ntiles > 0)
-        hipLaunchKernelGGL(nnc::k_b_budget, dim3(b->ntiles), dim3(nnc::kB), 0, b->stream, a);
-    hipLaunchKernelGGL(nnc::k_b_filter, dim3(b->S), dim3(nnc::kFB), 0, b->stream, a);
-    int rc = launch_grid_query(b, a);
+    int rc = launch_chains(b, a);
     if (rc == NNC_OK) {
         hipLaunchKernelGGL(nnc::k_b_entropy, dim3(b->S), dim3(nnc::kB), 0, b->stream, a);
         rc = nnc::check();
