@@ -112,6 +112,23 @@ def run_batch(nnc, trajs, grids, policy, tau=0.5, params=None, lanes=0, budget=F
     return chosen
 
 
+@pytest.mark.parametrize("dims", ["plane", "cube", "empty_plane"])
+def test_batch_one_dimension_and_an_empty_chain(nnc, dims):
+    """Batches whose scenes all share one dimension (the step's kernels in one chain),
+    and a mixed batch whose plane scenes are all empty (the plane's chain of kernels
+    has no ingest tile), under the repair and the rebuild policy."""
+    spec = {"plane": [(2, 500), (2, 3000), (2, 1200)],
+            "cube": [(3, 800), (3, 2500), (3, 40)],
+            "empty_plane": [(2, 0), (3, 1500), (2, 0), (3, 700)]}[dims]
+    trajs, grids = [], []
+    for k, (d, n) in enumerate(spec):
+        fam = synth.FAMILIES[k % len(synth.FAMILIES)]
+        trajs.append(synth.make_trajectory(fam, n, d, 6, 5e-4, (71, k)))
+        grids.append(15 if n < 1000 else 25)
+    for policy in (0, 1):
+        run_batch(nnc, trajs, grids, policy)
+
+
 @pytest.mark.parametrize("policy", [0, 1, 2])
 def test_batch_policies_match_per_scene_oracles(nnc, policy):
     trajs, grids = make_scenes(11 + policy, 10)

@@ -156,12 +156,14 @@ def test_trained_selector_beats_always_repair_on_held_out_transitions(nnc):
     """The committed network (trained on transitions labelled inside the batched step)
     against always repairing, on held-out scenes of other seeds with step sizes over a
     decade: its time regret, with the learned policy's feature and inference cost added
-    to every transition inside its band (where it computes features), is lower."""
+    to every transition inside its band (where it computes features), is lower.  The
+    held-out batch has the training batches' size (128 scenes; a scene's labels depend
+    on the batch it runs in) and 40 steps per scene."""
     from paper_2606_18314_amd import selector
     params, meta = selector.load_params()
     assert params is not None
-    specs = selector.scene_specs(64, seed=9900)
-    data = selector.collect_batched(specs, 12)
+    specs = selector.scene_specs(128, seed=9900)
+    data = selector.collect_batched(specs, 40)
     X, tr, tb = data["X"], data["t_repair"], data["t_rebuild"]
     c_inf = float(meta.get("inference_wave_us_per_scene_step", 0.0))
     lo, hi = meta.get("band", [0.0, 2.0])
