@@ -400,8 +400,12 @@ int nnc_batch_init(nnc_batch *b, const float *pos);
 /* One maintenance step of every scene (Algorithm 1 per scene, with the clock of
  * the appendix): measure eps_t, advance the clock, update the cells, filter and
  * compact, compute the features, choose the strategy by policy, rebuild or
- * refresh grids where needed, run every scene's queries in one launch, and
- * reduce the failure entropy (Definition 2).  pos_new (device, concatenated) is
+ * refresh grids where needed, run every scene's queries in one launch per
+ * dimension, and reduce the failure entropy (Definition 2).  With scenes of both
+ * dimensions, the plane scenes' kernels up to their queries run on a stream the
+ * library owns, forked from the batch's stream by an event and joined back into it
+ * before the entropy, so the step stays ordered on the batch's stream (also under
+ * capture, where the fork and join become graph edges).  pos_new (device, concatenated) is
  * read during the step only: the previous coordinates are kept by the library.
  * Asynchronous.  The step's kernels are captured into a HIP graph on the
  * first call and the graph is replayed while pos_new, policy and tau repeat
