@@ -1,7 +1,11 @@
 // Batched maintenance step: many independent scenes of uneven size and
 // dimension advanced together, for gfx950.
 //
-// Every kernel spans all scenes:
+// Every kernel spans all scenes, or, with scenes of both dimensions, all scenes of
+// one dimension: the plane's kernels up to their queries form one chain, the cube's
+// another, run side by side on two streams (forked from the batch's stream and
+// joined back before the entropy).  Tiles and query chunks are dealt to the XCDs in
+// contiguous shares.
 //   k_b_ingest   one workgroup per 1024-point tile of a scene: displacement,
 //                per-scene maximum (one atomic per wave), cells, occupancy,
 //                current coordinates into the grid slots (and, with the
@@ -16,10 +20,9 @@
 //   k_b_grid     one workgroup per scene that needs a fresh grid (rebuild, or
 //                repair after the motion budget of the loose grid is spent):
 //                cell-start scan and counting-sort scatter; one extra workgroup
-//                turns the per-scene query counts into offsets per dimension
-//                (with scenes of both dimensions, one launch per dimension, each
-//                followed by that dimension's queries on a stream of its own);
-//   k_b_query    one persistent grid-stride launch per dimension over the
+//                turns the per-scene query counts into offsets per dimension;
+//   k_b_query    one launch per dimension (more waves than can be resident,
+//                each a contiguous chunk of the list) over the
 //                queries of all scenes of that dimension (candidates of
 //                repaired scenes, every point of rebuilt ones), L lanes per
 //                query, the same exact search as one scene;
